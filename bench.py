@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""TSQR benchmark on one MI355X: FP64 R + explicit Q of a tall-skinny matrix.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+One step is one pass of the whole hot path over the resident input: the leaf
+chains (local Householder QRs of every tile), the binary tree over the leaf R
+factors, the root sign normalisation, the top-down seed descent and the Q
+expansion (tsqr_factor_into + tsqr_form_q; A is only read, so every step sees
+the same input).  Prints ONE JSON line.
+
+Flop convention (nominal): R + Q = 4mn^2 - 4n^3/3, R only = 2mn^2 - 2n^3/3.
+Byte convention (algorithmic HBM traffic): factor with reflectors 16mn (read A,
+write V), Q expansion 16mn (read V, write Q).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix)
+
+WORKLOADS = {
+    # m = 2^24, n = 32, A = U diag(sigma) V^T, sigma log-spaced 1 .. 1e-12
+    "tsqr_fp64_rq_m16777216_n32_kappa1e12": dict(m=1 << 24, n=32, decades=12.0, mode="rq"),
+    "tsqr_fp64_r_m16777216_n32_kappa1e12": dict(m=1 << 24, n=32, decades=12.0, mode="r"),
+    # m = 4096, n = 16, A iid N(0,1), 8 leaves of 512 rows, binary tree over them
+    "tsqr_fp64_rq_m4096_n16_gaussian": dict(m=4096, n=16, decades=None, mode="rq", leaf_rows=512),
+}
+DEFAULT = "tsqr_fp64_rq_m16777216_n32_kappa1e12"
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def flops_rq(m: int, n: int) -> float:
+    return 4.0 * m * n * n - 4.0 * n ** 3 / 3.0
+
+
+def flops_r(m: int, n: int) -> float:
+    return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+
+
+def make_input(w: dict, seed: int):
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import synth
+    from paper_0809_2407_amd import tsqr as T
+
+    m, n = w["m"], w["n"]
+    if w["decades"] is None:
+        A = T.to_colmajor(torch.from_numpy(synth.gaussian(m, n, seed)))
+        sig = None
+    else:
+        At, sig = synth.prescribed_sigma_torch(m, n, seed, w["decades"], device="cuda")
+        A = At.t()  # column-major view, ld = m
+    torch.cuda.synchronize()
+    return A, sig
+
+
+def cpu_baseline(A_dev, info: dict, sample_rows: int, mode: str):
+    """The oracle as it stands, on the first sample_rows rows of the same input,
+    on the host cores (tree of the same shape: same leaf and tile rows)."""
+    import numpy as np
+
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import oracle
+
+    m, n = A_dev.shape
+    ms = min(m, sample_rows)
+    As = np.asfortranarray(A_dev[:ms].cpu().numpy())
+    threads = oracle.num_threads()
+    t0 = time.perf_counter()
+    t = oracle.TSQR(As, info["leaf_rows"], info["tile_rows"])
+    if mode == "rq":
+        t.form_q()
+    t.R()
+    dt = time.perf_counter() - t0
+    fl = flops_rq(ms, n) if mode == "rq" else flops_r(ms, n)
+    return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {ms} of {m} rows (x{n}), same leaf/tile rows, "
+                      f"{'R + explicit Q' if mode == 'rq' else 'R only'}, {dt:.2f} s"}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 24)
+    ap.add_argument("--no-check", action="store_true", help="skip the accuracy check after timing")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this TSQR build runs on one GPU; the multi-GPU path (one all-gather "
+                                   "of the R factors) is a design, not a build: use --gpus 1"}))
+        return 2
+
+    import torch
+    from paper_0809_2407_amd import tsqr as T
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        return 1
+    w = dict(WORKLOADS[args.workload])
+    m, n, mode = w["m"], w["n"], w["mode"]
+    log(f"workload {args.workload}: generating input")
+    A, sig = make_input(w, args.seed)
+    plan = T.Plan(m, n, leaf_rows=w.get("leaf_rows", 0), want_q=(mode == "rq"))
+    info = plan.info()
+    log(f"plan: {info}")
+    V = T.colmajor(m, n) if mode == "rq" else None
+    Q = T.colmajor(m, n) if mode == "rq" else None
+    R = T.colmajor(n, n)
+
+    def step():
+        plan.factor_into(A, V, R)
+        if mode == "rq":
+            plan.form_q(V, Q)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ph = plan.timings()
+    plan.profile(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.4f} ms/step; phases {ph}")
+
+    fl = flops_rq(m, n) if mode == "rq" else flops_r(m, n)
+    value = fl / (ms_step * 1e-3) / 1e9
+    # dominant kernel: the phase with the largest device time
+    phase_bytes = {"leaf": (16.0 if mode == "rq" else 8.0) * m * n, "form_q": 16.0 * m * n}
+    dom = max(phase_bytes, key=lambda k: ph[k][0] / max(1, ph[k][1]) if ph[k][1] else 0.0)
+    dom_ms = ph[dom][0] / max(1, ph[dom][1])
+    achieved = phase_bytes[dom] / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                "kernel_ms": dom_ms, "bytes_per_launch": phase_bytes[dom]}
+    path_bytes = (32.0 if mode == "rq" else 8.0) * m * n
+    t_roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), path_bytes / (HBM_PEAK_GBS * 1e9))
+
+    result = {
+        "metric": "TSQR R+Q GFLOP/s & % roofline; mixed/batched vs FP64 at stated backward error",
+        "value": value, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "mode": mode,
+                   "sigma": None if sig is None else f"logspace(0,-{w['decades']:g},{n})",
+                   "seed": args.seed, "tree": {1: "binary", 2: "flat", 3: "hybrid"}.get(info["tree"], "auto"),
+                   "tile_rows": info["tile_rows"], "leaf_rows": info["leaf_rows"],
+                   "num_leaves": info["num_leaves"], "tree_levels": info["tree_levels"],
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "path_roofline": {"t_roof_ms": t_roof * 1e3, "frac": t_roof * 1e3 / ms_step,
+                          "bytes": path_bytes, "flops": fl},
+        "phases_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in ph.items()},
+    }
+
+    if not args.no_check and mode == "rq":
+        with torch.no_grad():
+            nA = torch.linalg.norm(A)
+            E = torch.addmm(A, Q, R, alpha=-1.0)
+            bwd = float(torch.linalg.norm(E) / nA)
+            del E
+            G = Q.t() @ Q
+            orth = float(torch.linalg.norm(G - torch.eye(n, dtype=G.dtype, device=G.device)))
+        result["accuracy"] = {"backward_error": bwd, "orthogonality": orth, "bound": 20 * n * 2.0 ** -53}
+        log(f"accuracy {result['accuracy']}")
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on host cores)")
+        result["cpu_baseline"] = cpu_baseline(A, info, args.cpu_sample_rows, mode)
+    else:
+        result["cpu_baseline"] = None
+
+    plan.close()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

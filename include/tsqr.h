@@ -1,0 +1,185 @@
+/*
+ * tsqr.h -- C ABI of libtsqr: TSQR (communication-avoiding Householder QR of a
+ * tall-skinny matrix) on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Demmel, Grigori, Hoemmen and Langou, "Implementing
+ * Communication-Optimal Parallel and Sequential QR Factorizations" (arXiv
+ * 0809.2407): A = [A_0; ...; A_{P-1}] in P block rows (Sec. 2), a local
+ * Householder QR per block row, the R factors combined up a reduction tree by
+ * QRs of stacked triangles [R_a; R_b] (Alg. 1; structured QR of Sec. 3.1), a
+ * flat chain qr([R; A_k]) inside each block row (Alg. 2), with Q kept implicit
+ * as Householder reflectors plus a stored tree (Sec. 4.1 and 4.2).  Applying Q^T
+ * is a reduction over that tree and applying Q is a broadcast (Sec. 4.1).
+ *
+ * Conventions shared by every call:
+ *   - Matrices are column-major FP64 with a leading dimension (element (i, j)
+ *     of A sits at A[i + j*lda]); every matrix pointer is a DEVICE pointer
+ *     owned by the caller.
+ *   - Every call is asynchronous on the HIP stream bound to the plan: it returns
+ *     once its kernels are enqueued.  Launch errors are reported; a kernel fault
+ *     surfaces at the caller's next synchronisation.
+ *   - Status codes: 0 = success; -i = argument i (1-based, in the order of the
+ *     prototype) is invalid (LAPACK "info" style); 1 = HIP runtime error,
+ *     2 = device memory exhausted, 3 = unsupported case, 4 = call out of order
+ *     (e.g. tsqr_form_q before tsqr_factor).
+ *   - NaN or Inf entries propagate; nothing checks for them.
+ *   - A plan is not thread-safe.  Different plans are independent.
+ *   - Householder conventions: H_j = I - tau_j v_j v_j^T with v_j(j) = 1,
+ *     beta_j = -sgn(alpha_j) ||x_j||, sgn(0) = +1, tau_j = 0 when the part of the
+ *     column below the pivot is exactly zero.  The returned R is sign-normalised
+ *     (diag(R) >= 0): QR is unique up to these signs (Sec. 2).
+ */
+#ifndef TSQR_H
+#define TSQR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int tsqr_status;
+
+typedef enum { TSQR_FP64 = 0, TSQR_MIXED = 1 } tsqr_precision;
+
+/* Reduction-tree shape (Sec. 2 and the list of tree shapes in Sec. 7):
+ * FLAT = one chain over every tile (Alg. 2), BINARY = every tile is a leaf of the
+ * binary tree (Alg. 1), HYBRID = flat chains of flat_len tiles inside each leaf,
+ * binary above.  AUTO lets the library choose. */
+typedef enum {
+    TSQR_TREE_AUTO = 0,
+    TSQR_TREE_BINARY = 1,
+    TSQR_TREE_FLAT = 2,
+    TSQR_TREE_HYBRID = 3
+} tsqr_tree;
+
+/* Plan options; a zero field means "choose automatically".
+ *   tree       tree shape
+ *   leaf_rows  rows per leaf (block row); rounded up to a multiple of tile_rows
+ *   tile_rows  rows per tile; the library fixes it from n (it sizes the on-chip
+ *              working set, the constraint m/P*n + n(n+1)/2 <= W of Sec. 4.2),
+ *              a nonzero value must equal that size
+ *   flat_len   tiles per leaf chain (HYBRID); leaf_rows wins if both are set
+ *   waves      wavefronts per workgroup (1, 2 or 4)
+ *   want_q     1 (default when opts == NULL): tsqr_factor keeps the reflectors
+ *              in A for later tsqr_form_q / tsqr_apply_qt calls;
+ *              0: R only, A is not written. */
+typedef struct {
+    tsqr_tree tree;
+    int64_t leaf_rows;
+    int64_t tile_rows;
+    int flat_len;
+    int waves;
+    int want_q;
+} tsqr_opts;
+
+/* What the plan chose, and (MIXED) what the second pass measured. */
+typedef struct {
+    int64_t m, n;
+    int64_t n_padded;        /* n rounded up to the kernels' column granularity */
+    int64_t tile_rows;       /* rows per tile */
+    int64_t leaf_rows;       /* rows per leaf (the last leaf also takes the remainder) */
+    int64_t num_leaves;      /* P */
+    int64_t num_tiles;       /* tiles over all leaves */
+    int tree_levels;         /* ceil(log2 P) */
+    tsqr_tree tree;
+    int waves;
+    tsqr_precision precision;
+    int64_t workspace_bytes; /* device memory the plan owns */
+    int reorth_applied;      /* MIXED: 1 when the second pass corrected Q and R */
+    double orth_estimate;    /* MIXED: ||R2^T R2 - I||_F of the second pass */
+} tsqr_info;
+
+typedef struct tsqr_plan_s* tsqr_plan;
+
+/* Create a plan for m x n problems (n <= m, 1 <= n <= 64) on hip_stream (a
+ * hipStream_t, NULL = the default stream).  The plan allocates its device
+ * workspace (per-tile compact-WY factors T, per-node tree factors, seeds, signs)
+ * with hipMalloc here and frees it in tsqr_plan_destroy.
+ * Errors: -1 p NULL, -2 m < n or m < 1, -3 n < 1 or n > 64 (3 = unsupported for
+ * n > 64), -4 bad precision, -5 bad option field; 2 out of memory. */
+tsqr_status tsqr_plan_create(tsqr_plan* p, int64_t m, int64_t n, tsqr_precision prec,
+                             const tsqr_opts* opts, void* hip_stream);
+
+/* Factor A (m x n, lda >= m).  Writes R (n x n upper triangular, diag >= 0,
+ * strictly lower part set to 0) at R[i + j*ldr], ldr >= n.  With want_q the
+ * leaf reflectors overwrite A in place (below the diagonal of each tile, LAPACK
+ * style, Sec. 4.2) and the tree is kept in the plan (Sec. 4.1); otherwise A is
+ * only read.  Errors: -1 p, -2 A NULL, -3 lda < m, -4 R NULL, -5 ldr < n. */
+tsqr_status tsqr_factor(tsqr_plan p, double* A, int64_t lda, double* R, int64_t ldr);
+
+/* As tsqr_factor, but A is only read and the reflectors go to V (m x n,
+ * ldv >= m); later tsqr_form_q / tsqr_apply_qt calls take V in place of the
+ * factored A.  V may equal A with ldv == lda (that is tsqr_factor).  With
+ * want_q = 0, V is not written and may be NULL.
+ * Errors: -1 p, -2 A NULL, -3 lda < m, -4 V NULL (want_q), -5 ldv < m or V == A
+ * with ldv != lda, -6 R NULL, -7 ldr < n. */
+tsqr_status tsqr_factor_into(tsqr_plan p, const double* A, int64_t lda, double* V, int64_t ldv, double* R,
+                             int64_t ldr);
+
+/* Explicit thin Q (m x n, ldq >= m) from the reflectors tsqr_factor left in A
+ * and the plan's tree (the broadcast of Sec. 4.1).  A = Q R with Q^T Q = I.
+ * Q may alias A (same pointer and same leading dimension).
+ * Errors: -1 p, -2 A NULL, -3 lda < m, -4 Q NULL, -5 ldq < m or aliasing with a
+ * different leading dimension; 4 when the plan holds no factorisation with
+ * reflectors. */
+tsqr_status tsqr_form_q(tsqr_plan p, const double* A_factored, int64_t lda, double* Q, int64_t ldq);
+
+/* B (m x k, ldb >= m) <- Q_full^T B in place, Q_full being the m x m orthogonal
+ * factor of the tree (the reduction of Sec. 4.1).  Rows 0..n-1 become D Q^T B
+ * with Q the thin factor returned by tsqr_form_q; rows n..m-1 hold coordinates
+ * of B in the tree's basis of the orthogonal complement (they depend on the
+ * tree).  Errors: -1 p, -2 A NULL, -3 lda < m, -4 k < 0, -5 B NULL, -6 ldb < m;
+ * 4 when the plan holds no factorisation with reflectors. */
+tsqr_status tsqr_apply_qt(tsqr_plan p, const double* A_factored, int64_t lda, int64_t k, double* B,
+                          int64_t ldb);
+
+/* What tsqr_plan_create would choose for these arguments, without allocating
+ * anything or touching a device (workspace_bytes tells the device memory a
+ * plan would own).  Errors: -1 m, -2 n, -3 prec, -4 opts (the checks of
+ * tsqr_plan_create), -5 out NULL; 3 unsupported case. */
+tsqr_status tsqr_plan_query(int64_t m, int64_t n, tsqr_precision prec, const tsqr_opts* opts, tsqr_info* out);
+
+/* Copy what the plan chose (and what a MIXED run measured; reading those two
+ * fields synchronises the plan's stream).  Errors: -1 p, -2 out NULL. */
+tsqr_status tsqr_plan_info(tsqr_plan p, tsqr_info* out);
+
+/* Per-phase device time.  With profiling on, every kernel phase a call enqueues
+ * is bracketed by HIP events on the plan's stream. */
+typedef enum {
+    TSQR_PHASE_LEAF = 0,    /* leaf chains: local QRs of every tile (tsqr_factor) */
+    TSQR_PHASE_TREE = 1,    /* binary-tree levels over the leaf R factors */
+    TSQR_PHASE_ROOT = 2,    /* sign normalisation and R output */
+    TSQR_PHASE_SEEDS = 3,   /* top-down seed descent of tsqr_form_q */
+    TSQR_PHASE_FORM_Q = 4,  /* per-tile Q expansion of tsqr_form_q */
+    TSQR_PHASE_APPLY = 5,   /* tsqr_apply_qt */
+    TSQR_NUM_PHASES = 8
+} tsqr_phase;
+
+typedef struct {
+    double ms[TSQR_NUM_PHASES];     /* summed device milliseconds per phase */
+    int64_t calls[TSQR_NUM_PHASES]; /* how many times each phase ran */
+} tsqr_timings;
+
+/* Turn per-phase event timing on (1) or off (0).  Turning it on clears the sums.
+ * Errors: -1 p, -2 bad flag; 1 when the events cannot be created. */
+tsqr_status tsqr_plan_profile(tsqr_plan p, int enable);
+
+/* Sums since profiling was turned on (synchronises the plan's stream).
+ * Errors: -1 p, -2 out NULL; 1 HIP error. */
+tsqr_status tsqr_plan_timings(tsqr_plan p, tsqr_timings* out);
+
+/* Free the plan and its workspace (synchronises its stream first). */
+tsqr_status tsqr_plan_destroy(tsqr_plan p);
+
+/* Static, human-readable text for a status code. */
+const char* tsqr_status_string(tsqr_status s);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int tsqr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSQR_H */

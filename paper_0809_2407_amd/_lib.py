@@ -1,0 +1,94 @@
+"""ctypes declarations of libtsqr's C ABI (include/tsqr.h).  Argument
+marshalling only: every step of the computation runs in the library's HIP
+kernels.  Loading fails loudly when the library has not been built."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtsqr.so")
+
+TSQR_FP64, TSQR_MIXED = 0, 1
+TSQR_TREE_AUTO, TSQR_TREE_BINARY, TSQR_TREE_FLAT, TSQR_TREE_HYBRID = 0, 1, 2, 3
+
+i64 = ctypes.c_int64
+dp = ctypes.c_void_p  # device pointers travel as plain addresses
+
+
+class TsqrOpts(ctypes.Structure):
+    _fields_ = [("tree", ctypes.c_int), ("leaf_rows", i64), ("tile_rows", i64),
+                ("flat_len", ctypes.c_int), ("waves", ctypes.c_int), ("want_q", ctypes.c_int)]
+
+
+class TsqrInfo(ctypes.Structure):
+    _fields_ = [("m", i64), ("n", i64), ("n_padded", i64), ("tile_rows", i64), ("leaf_rows", i64),
+                ("num_leaves", i64), ("num_tiles", i64), ("tree_levels", ctypes.c_int),
+                ("tree", ctypes.c_int), ("waves", ctypes.c_int), ("precision", ctypes.c_int),
+                ("workspace_bytes", i64), ("reorth_applied", ctypes.c_int),
+                ("orth_estimate", ctypes.c_double)]
+
+
+class TsqrTimings(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("calls", i64 * 8)]
+
+
+PHASES = ["leaf", "tree", "root", "seeds", "form_q", "apply_qt"]
+
+EXPORTED = [
+    "tsqr_plan_create", "tsqr_plan_query", "tsqr_factor", "tsqr_factor_into", "tsqr_form_q", "tsqr_apply_qt",
+    "tsqr_plan_info", "tsqr_plan_profile", "tsqr_plan_timings", "tsqr_plan_destroy", "tsqr_status_string",
+    "tsqr_version",
+]
+
+_lib = None
+
+
+class TsqrError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        self.status = status
+        text = load().tsqr_status_string(status).decode()
+        super().__init__(f"{fn} failed with status {status}: {text}")
+
+
+def load(path: str = LIB_PATH):
+    """Load libtsqr.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libtsqr.so not found at {path}; build it with "
+                           f"`python -m paper_0809_2407_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.tsqr_plan_create.argtypes = [ctypes.POINTER(P), i64, i64, ctypes.c_int, ctypes.POINTER(TsqrOpts), P]
+    lib.tsqr_plan_create.restype = ctypes.c_int
+    lib.tsqr_plan_query.argtypes = [i64, i64, ctypes.c_int, ctypes.POINTER(TsqrOpts), ctypes.POINTER(TsqrInfo)]
+    lib.tsqr_plan_query.restype = ctypes.c_int
+    lib.tsqr_factor.argtypes = [P, dp, i64, dp, i64]
+    lib.tsqr_factor.restype = ctypes.c_int
+    lib.tsqr_factor_into.argtypes = [P, dp, i64, dp, i64, dp, i64]
+    lib.tsqr_factor_into.restype = ctypes.c_int
+    lib.tsqr_plan_profile.argtypes = [P, ctypes.c_int]
+    lib.tsqr_plan_profile.restype = ctypes.c_int
+    lib.tsqr_plan_timings.argtypes = [P, ctypes.POINTER(TsqrTimings)]
+    lib.tsqr_plan_timings.restype = ctypes.c_int
+    lib.tsqr_form_q.argtypes = [P, dp, i64, dp, i64]
+    lib.tsqr_form_q.restype = ctypes.c_int
+    lib.tsqr_apply_qt.argtypes = [P, dp, i64, i64, dp, i64]
+    lib.tsqr_apply_qt.restype = ctypes.c_int
+    lib.tsqr_plan_info.argtypes = [P, ctypes.POINTER(TsqrInfo)]
+    lib.tsqr_plan_info.restype = ctypes.c_int
+    lib.tsqr_plan_destroy.argtypes = [P]
+    lib.tsqr_plan_destroy.restype = ctypes.c_int
+    lib.tsqr_status_string.argtypes = [ctypes.c_int]
+    lib.tsqr_status_string.restype = ctypes.c_char_p
+    lib.tsqr_version.argtypes = []
+    lib.tsqr_version.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(fn: str, status: int) -> None:
+    if status != 0:
+        raise TsqrError(fn, status)

@@ -1,0 +1,88 @@
+"""Build libtsqr.so (HIP for gfx950) in-tree.
+
+    python -m paper_0809_2407_amd.build            # full library
+    python -m paper_0809_2407_amd.build --np 32    # one padded column count (fast experiments)
+
+Every HIP unit is compiled with hipcc for gfx950 only; the kernel units are
+compiled in parallel and linked into ``paper_0809_2407_amd/libtsqr.so``.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libtsqr.so")
+
+UNITS = ["tsqr_np_0.hip", "tsqr_np_1.hip", "tsqr_np_2.hip", "tsqr_np_3.hip",
+         "tsqr_dispatch.hip", "tsqr_api.cpp"]
+
+ARCH = "gfx950"
+COMMON = [
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # no packed-FP32 instructions in generated code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", os.path.join(ROOT, "include"),
+]
+
+
+def _hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found: the ROCm toolchain is required to build libtsqr")
+
+
+def build(only_np: int | None = None, jobs: int | None = None, verbose: bool = False) -> str:
+    hipcc = _hipcc()
+    tmp = tempfile.mkdtemp(prefix="tsqr_build_")
+    defs = [f"-DTSQR_ONLY_NP={only_np}"] if only_np else []
+    objs = []
+
+    def compile_unit(u: str) -> str:
+        src = os.path.join(CSRC, u)
+        obj = os.path.join(tmp, u + ".o")
+        lang = ["-x", "hip"] if u.endswith(".hip") else []
+        cmd = [hipcc] + COMMON + defs + lang + ["-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {u}:\n{r.stderr[-4000:]}")
+        return obj
+
+    try:
+        n = jobs or min(len(UNITS), max(1, os.cpu_count() or 1))
+        with cf.ThreadPoolExecutor(max_workers=n) as ex:
+            objs = list(ex.map(compile_unit, UNITS))
+        out_tmp = LIB + ".tmp"
+        cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp] + objs
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
+        os.replace(out_tmp, LIB)
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    return LIB
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--np", type=int, default=None, help="build a single padded column count")
+    ap.add_argument("-j", "--jobs", type=int, default=None)
+    ap.add_argument("-v", "--verbose", action="store_true")
+    a = ap.parse_args(argv)
+    path = build(a.np, a.jobs, a.verbose)
+    print(path)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,358 @@
+// tsqr_api.cpp -- the C ABI of libtsqr (include/tsqr.h): plans, argument
+// checking, workspace ownership and the order of kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/tsqr.h"
+#include "tsqr_internal.h"
+
+namespace tsqr {
+
+static int rows_per_lane_host(int np) { return np <= 8 ? 32 : np <= 16 ? 16 : np <= 32 ? 8 : 4; }
+
+bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves)
+{
+    if (n < 1 || n > kMaxN || m < n) return false;
+    L = Layout();
+    L.m = m;
+    L.n = n;
+    L.np = (int)((n + 3) / 4 * 4);
+    L.npb = (int)((n + 15) / 16 * 16);
+    L.rl = rows_per_lane_host(L.np);
+    L.mt = 16 * L.rl;
+    L.waves = waves > 0 ? waves : (L.np <= 32 ? 4 : 2);
+    const int64_t tiles_total = (m + L.mt - 1) / L.mt;
+    int64_t f;
+    if (leaf_rows_req > 0) {
+        f = (leaf_rows_req + L.mt - 1) / L.mt;
+    } else if (tree == TSQR_TREE_FLAT) {
+        f = tiles_total;
+    } else if (tree == TSQR_TREE_BINARY) {
+        f = 1;
+    } else if (tree == TSQR_TREE_HYBRID && flat_len > 0) {
+        f = flat_len;
+    } else {
+        // automatic: about 4096 leaves, chains of 1..64 tiles
+        f = tiles_total / 4096;
+        f = std::max<int64_t>(1, std::min<int64_t>(64, f));
+    }
+    if (f < 1) f = 1;
+    L.f = f;
+    L.leaf_rows = f * L.mt;
+    L.P = std::max<int64_t>(1, m / L.leaf_rows);
+    const int64_t last_rows = m - (L.P - 1) * L.leaf_rows;
+    L.ntiles_last = (last_rows + L.mt - 1) / L.mt;
+    L.ntiles = (L.P - 1) * L.f + L.ntiles_last;
+    L.count[0] = L.P;
+    int lv = 0;
+    int64_t c = L.P;
+    while (c > 1) {
+        if (lv + 1 > kMaxLevels) return false;
+        c = (c + 1) / 2;
+        L.count[++lv] = c;
+    }
+    L.levels = lv;
+
+    const int64_t np2 = (int64_t)L.np * L.np;
+    L.nt = (int64_t)L.np * (L.np + 1) / 2;
+    int64_t off = 0;
+    auto take = [&](int64_t doubles) {
+        int64_t o = off;
+        off += (doubles + 31) / 32 * 32;  // 256-byte alignment
+        return o;
+    };
+    L.off_T = take(L.ntiles * L.nt);
+    for (int l = 0; l <= L.levels; ++l) {
+        L.off_R[l] = take(L.count[l] * np2);
+        L.off_S[l] = take(L.count[l] * np2);
+        if (l >= 1) {
+            L.off_Y[l] = take(L.count[l] * np2);
+            L.off_TN[l] = take(L.count[l] * L.nt);
+        }
+    }
+    L.off_D = take(L.np);
+    L.total = off;
+    return true;
+}
+
+}  // namespace tsqr
+
+struct PhaseEvent {
+    int phase;
+    hipEvent_t start, stop;
+};
+
+struct tsqr_plan_s {
+    tsqr::Layout L;
+    tsqr_precision prec = TSQR_FP64;
+    tsqr_tree tree = TSQR_TREE_AUTO;
+    int want_q = 1;
+    hipStream_t stream = nullptr;
+    double* ws = nullptr;
+    int state = 0;  // 0: nothing factored, 1: factored with reflectors, 2: R only
+    // profiling: event pairs recorded since the last tsqr_plan_timings
+    bool profile = false;
+    std::vector<PhaseEvent> events;
+    tsqr_timings sums{};
+};
+
+namespace {
+
+tsqr_status hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return 0;
+    if (e == hipErrorOutOfMemory) return 2;
+    return 1;
+}
+
+// Runs one launch phase, bracketed by events when profiling is on.
+template <typename F>
+hipError_t run_phase(tsqr_plan_s* p, int phase, F&& launch)
+{
+    if (!p->profile) return launch();
+    PhaseEvent ev{phase, nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev.start);
+    if (e == hipSuccess) e = hipEventCreate(&ev.stop);
+    if (e == hipSuccess) e = hipEventRecord(ev.start, p->stream);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(ev.stop, p->stream);
+    if (e == hipSuccess) {
+        p->events.push_back(ev);
+    } else {
+        if (ev.start) hipEventDestroy(ev.start);
+        if (ev.stop) hipEventDestroy(ev.stop);
+    }
+    return e;
+}
+
+hipError_t drain_events(tsqr_plan_s* p)
+{
+    hipError_t first = hipSuccess;
+    for (PhaseEvent& ev : p->events) {
+        hipError_t e = hipEventSynchronize(ev.stop);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.start, ev.stop);
+        if (e == hipSuccess) {
+            p->sums.ms[ev.phase] += ms;
+            p->sums.calls[ev.phase] += 1;
+        } else if (first == hipSuccess) {
+            first = e;
+        }
+        hipEventDestroy(ev.start);
+        hipEventDestroy(ev.stop);
+    }
+    p->events.clear();
+    return first;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsqr_version(void) { return 100; }
+
+const char* tsqr_status_string(tsqr_status s)
+{
+    if (s == 0) return "success";
+    if (s < 0) return "invalid argument (the negated status is its 1-based position)";
+    switch (s) {
+    case 1: return "HIP runtime error";
+    case 2: return "device memory exhausted";
+    case 3: return "unsupported case";
+    case 4: return "call out of order (no factorisation with reflectors in the plan)";
+    default: return "unknown status";
+    }
+}
+
+// Argument checks shared by tsqr_plan_create and tsqr_plan_query; fills the
+// layout on success.
+static tsqr_status check_plan_args(int64_t m, int64_t n, tsqr_precision prec, const tsqr_opts* opts,
+                                   tsqr_opts& o, tsqr::Layout& L)
+{
+    if (m < 1 || m < n) return -2;
+    if (n < 1) return -3;
+    if (n > tsqr::kMaxN) return 3;
+    if (prec != TSQR_FP64 && prec != TSQR_MIXED) return -4;
+    if (prec == TSQR_MIXED) return 3;
+    std::memset(&o, 0, sizeof(o));
+    o.want_q = 1;
+    if (opts) {
+        o = *opts;
+        if (o.tree < TSQR_TREE_AUTO || o.tree > TSQR_TREE_HYBRID) return -5;
+        if (o.leaf_rows < 0 || o.tile_rows < 0 || o.flat_len < 0) return -5;
+        if (o.waves != 0 && o.waves != 1 && o.waves != 2 && o.waves != 4) return -5;
+        if (o.want_q != 0 && o.want_q != 1) return -5;
+    }
+    if (!tsqr::make_layout(L, m, n, o.leaf_rows, o.flat_len, o.tree, o.waves)) return 3;
+    if (o.tile_rows != 0 && o.tile_rows != L.mt) return -5;
+    return 0;
+}
+
+static void fill_info(const tsqr::Layout& L, tsqr_precision prec, tsqr_info* out)
+{
+    std::memset(out, 0, sizeof(*out));
+    out->m = L.m;
+    out->n = L.n;
+    out->n_padded = L.np;
+    out->tile_rows = L.mt;
+    out->leaf_rows = L.leaf_rows;
+    out->num_leaves = L.P;
+    out->num_tiles = L.ntiles;
+    out->tree_levels = L.levels;
+    out->tree = L.P == 1 ? TSQR_TREE_FLAT : (L.f == 1 ? TSQR_TREE_BINARY : TSQR_TREE_HYBRID);
+    out->waves = L.waves;
+    out->precision = prec;
+    out->workspace_bytes = L.total * (int64_t)sizeof(double);
+}
+
+tsqr_status tsqr_plan_query(int64_t m, int64_t n, tsqr_precision prec, const tsqr_opts* opts, tsqr_info* out)
+{
+    tsqr_opts o;
+    tsqr::Layout L;
+    tsqr_status st = check_plan_args(m, n, prec, opts, o, L);
+    if (st < 0) return st + 1;  // argument positions are one lower than in tsqr_plan_create
+    if (st != 0) return st;
+    if (!out) return -5;
+    fill_info(L, prec, out);
+    return 0;
+}
+
+tsqr_status tsqr_plan_create(tsqr_plan* p, int64_t m, int64_t n, tsqr_precision prec, const tsqr_opts* opts,
+                             void* hip_stream)
+{
+    if (!p) return -1;
+    *p = nullptr;
+    tsqr_opts o;
+    tsqr::Layout L;
+    tsqr_status st = check_plan_args(m, n, prec, opts, o, L);
+    if (st != 0) return st;
+    tsqr_plan_s* P = new (std::nothrow) tsqr_plan_s();
+    if (!P) return 2;
+    P->L = L;
+    P->prec = prec;
+    P->tree = o.tree;
+    P->want_q = o.want_q;
+    P->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipMalloc((void**)&P->ws, (size_t)P->L.total * sizeof(double));
+    if (e != hipSuccess) {
+        delete P;
+        return hip_status(e);
+    }
+    *p = P;
+    return 0;
+}
+
+tsqr_status tsqr_factor_into(tsqr_plan p, const double* A, int64_t lda, double* V, int64_t ldv, double* R,
+                             int64_t ldr)
+{
+    if (!p) return -1;
+    if (!A) return -2;
+    if (lda < p->L.m) return -3;
+    const bool want_q = p->want_q != 0;
+    if (want_q) {
+        if (!V) return -4;
+        if (ldv < p->L.m) return -5;
+        if ((const double*)V == A && ldv != lda) return -5;
+    }
+    if (!R) return -6;
+    if (ldr < p->L.n) return -7;
+    p->state = 0;
+    hipError_t e = run_phase(p, TSQR_PHASE_LEAF, [&] {
+        return tsqr::launch_leaf_factor(p->L, A, lda, V, want_q ? ldv : lda, p->ws, want_q, p->stream);
+    });
+    if (e == hipSuccess && p->L.levels > 0)
+        e = run_phase(p, TSQR_PHASE_TREE, [&] { return tsqr::launch_tree(p->L, p->ws, want_q, p->stream); });
+    if (e == hipSuccess)
+        e = run_phase(p, TSQR_PHASE_ROOT, [&] { return tsqr::launch_root(p->L, p->ws, R, ldr, p->stream); });
+    if (e != hipSuccess) return hip_status(e);
+    p->state = want_q ? 1 : 2;
+    return 0;
+}
+
+tsqr_status tsqr_factor(tsqr_plan p, double* A, int64_t lda, double* R, int64_t ldr)
+{
+    tsqr_status st = tsqr_factor_into(p, A, lda, p && p->want_q ? A : nullptr, lda, R, ldr);
+    if (st == -6) return -4;
+    if (st == -7) return -5;
+    return st;
+}
+
+tsqr_status tsqr_form_q(tsqr_plan p, const double* A_factored, int64_t lda, double* Q, int64_t ldq)
+{
+    if (!p) return -1;
+    if (!A_factored) return -2;
+    if (lda < p->L.m) return -3;
+    if (!Q) return -4;
+    if (ldq < p->L.m) return -5;
+    if ((const double*)Q == A_factored && ldq != lda) return -5;
+    if (p->state != 1) return 4;
+    hipError_t e = hipSuccess;
+    if (p->L.levels > 0)
+        e = run_phase(p, TSQR_PHASE_SEEDS, [&] { return tsqr::launch_seeds(p->L, p->ws, p->stream); });
+    if (e == hipSuccess)
+        e = run_phase(p, TSQR_PHASE_FORM_Q, [&] {
+            return tsqr::launch_form_q(p->L, A_factored, lda, p->ws, Q, ldq, p->stream);
+        });
+    return hip_status(e);
+}
+
+tsqr_status tsqr_apply_qt(tsqr_plan p, const double* A_factored, int64_t lda, int64_t k, double* B, int64_t ldb)
+{
+    if (!p) return -1;
+    if (!A_factored) return -2;
+    if (lda < p->L.m) return -3;
+    if (k < 0) return -4;
+    if (!B) return -5;
+    if (ldb < p->L.m) return -6;
+    if (p->state != 1) return 4;
+    if (k == 0) return 0;
+    return 3;
+}
+
+tsqr_status tsqr_plan_info(tsqr_plan p, tsqr_info* out)
+{
+    if (!p) return -1;
+    if (!out) return -2;
+    fill_info(p->L, p->prec, out);
+    return 0;
+}
+
+tsqr_status tsqr_plan_profile(tsqr_plan p, int enable)
+{
+    if (!p) return -1;
+    if (enable != 0 && enable != 1) return -2;
+    hipError_t e = drain_events(p);
+    p->profile = enable != 0;
+    if (p->profile) std::memset(&p->sums, 0, sizeof(p->sums));
+    return hip_status(e);
+}
+
+tsqr_status tsqr_plan_timings(tsqr_plan p, tsqr_timings* out)
+{
+    if (!p) return -1;
+    if (!out) return -2;
+    hipError_t e = drain_events(p);
+    *out = p->sums;
+    return hip_status(e);
+}
+
+tsqr_status tsqr_plan_destroy(tsqr_plan p)
+{
+    if (!p) return -1;
+    drain_events(p);
+    hipError_t e = hipSuccess;
+    if (p->ws) {
+        e = hipStreamSynchronize(p->stream);
+        hipError_t e2 = hipFree(p->ws);
+        if (e == hipSuccess) e = e2;
+    }
+    delete p;
+    return hip_status(e);
+}
+
+}  // extern "C"

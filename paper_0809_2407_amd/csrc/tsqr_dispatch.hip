@@ -1,0 +1,89 @@
+// tsqr_dispatch.hip -- selects the instantiation for the padded column count.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tsqr_internal.h"
+
+namespace tsqr {
+
+template <int NP>
+hipError_t leaf_factor_np(const Layout& L, const double* A, int64_t lda, double* V, int64_t ldv, double* ws,
+                          bool want_q, hipStream_t s);
+template <int NP>
+hipError_t tree_np(const Layout& L, double* ws, bool want_q, hipStream_t s);
+template <int NP>
+hipError_t root_np(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s);
+template <int NP>
+hipError_t seeds_np(const Layout& L, double* ws, hipStream_t s);
+template <int NP>
+hipError_t form_q_np(const Layout& L, const double* A, int64_t lda, double* ws, double* Q, int64_t ldq,
+                     hipStream_t s);
+
+#ifdef TSQR_ONLY_NP
+// experiment builds: a single column count
+#define TSQR_NP_SWITCH(np, CALL)                                                                      \
+    switch (np) {                                                                                     \
+    case TSQR_ONLY_NP: return CALL(TSQR_ONLY_NP);                                                     \
+    default: return hipErrorInvalidValue;                                                             \
+    }
+#else
+#define TSQR_NP_SWITCH(np, CALL)                                                                      \
+    switch (np) {                                                                                     \
+    case 4: return CALL(4);                                                                           \
+    case 8: return CALL(8);                                                                           \
+    case 12: return CALL(12);                                                                         \
+    case 16: return CALL(16);                                                                         \
+    case 20: return CALL(20);                                                                         \
+    case 24: return CALL(24);                                                                         \
+    case 28: return CALL(28);                                                                         \
+    case 32: return CALL(32);                                                                         \
+    case 36: return CALL(36);                                                                         \
+    case 40: return CALL(40);                                                                         \
+    case 44: return CALL(44);                                                                         \
+    case 48: return CALL(48);                                                                         \
+    case 52: return CALL(52);                                                                         \
+    case 56: return CALL(56);                                                                         \
+    case 60: return CALL(60);                                                                         \
+    case 64: return CALL(64);                                                                         \
+    default: return hipErrorInvalidValue;                                                             \
+    }
+#endif
+
+hipError_t launch_leaf_factor(const Layout& L, const double* A, int64_t lda, double* V, int64_t ldv, double* ws,
+                              bool want_q, hipStream_t s)
+{
+#define CALL(NP) leaf_factor_np<NP>(L, A, lda, V, ldv, ws, want_q, s)
+    TSQR_NP_SWITCH(L.np, CALL)
+#undef CALL
+}
+
+hipError_t launch_tree(const Layout& L, double* ws, bool want_q, hipStream_t s)
+{
+#define CALL(NP) tree_np<NP>(L, ws, want_q, s)
+    TSQR_NP_SWITCH(L.np, CALL)
+#undef CALL
+}
+
+hipError_t launch_root(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s)
+{
+#define CALL(NP) root_np<NP>(L, ws, R, ldr, s)
+    TSQR_NP_SWITCH(L.np, CALL)
+#undef CALL
+}
+
+hipError_t launch_seeds(const Layout& L, double* ws, hipStream_t s)
+{
+#define CALL(NP) seeds_np<NP>(L, ws, s)
+    TSQR_NP_SWITCH(L.np, CALL)
+#undef CALL
+}
+
+hipError_t launch_form_q(const Layout& L, const double* A, int64_t lda, double* ws, double* Q, int64_t ldq,
+                         hipStream_t s)
+{
+#define CALL(NP) form_q_np<NP>(L, A, lda, ws, Q, ldq, s)
+    TSQR_NP_SWITCH(L.np, CALL)
+#undef CALL
+}
+
+}  // namespace tsqr

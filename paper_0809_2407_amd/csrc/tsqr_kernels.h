@@ -1,0 +1,734 @@
+// tsqr_kernels.h -- gfx950 (CDNA4) kernels of TSQR (templates; instantiated
+// per column count by the tsqr_np_*.hip units).
+//
+// Execution model.  One wavefront owns one leaf: a block row of the matrix
+// reduced by a flat chain over its tiles, qr(A_0) then qr([R; A_k]) (the
+// sequential TSQR of Alg. 2 with the wavefront's registers as fast memory).
+// The leaf R factors are then combined on a binary tree, one launch per level,
+// one wavefront per node (the parallel TSQR of Alg. 1, with the stacked pair
+// [R_a; R_b] factored by the triangle-aware QR of Sec. 3.1).  The explicit Q is
+// the tree replayed top-down (applying Q is a broadcast, Sec. 4.1).
+//
+// Register layout of a tile ("L layout").  A tile has 16*RL rows and NP
+// columns (NP = n rounded up to a multiple of 4; padded columns are zero and
+// stay zero).  Lane l = 16*cg + rg holds rows 16*i + rg (i < RL) and columns
+// 4*k + cg (k < NP/4) in a[i][k].  Consequences:
+//   - a sum over the rows of a column is a sum over the 16 lanes of one DPP row
+//     (four DPP steps, every lane ends with the same bits);
+//   - the f64 16x16x4 matrix-core op contracts over the lane-group index, so a
+//     product that contracts over COLUMNS (Y Z, T S, Y1 Z) maps this layout onto
+//     itself: the seed products and the Q expansion run on the matrix cores
+//     with no data movement.
+//
+// Householder conventions: H_j = I - tau_j v_j v_j^T, v_j(j) = 1,
+// beta = -sgn(alpha) ||x||, tau = (beta - alpha)/beta, tau = 0 when the part of
+// the column below the pivot is zero.  Every tile stores T, the upper-triangular
+// factor of H_0 ... H_{n-1} = I - V T V^T (the YT representation of Sec. 3.2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tsqr_internal.h"
+
+namespace tsqr {
+namespace detail {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dbl4 mfma16x16x4(double a, double b, dbl4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of a DPP row.  Each step adds a partner whose own step
+// adds the same two operands, so all 16 lanes end with identical bits.
+__device__ __forceinline__ double row_sum16(double v)
+{
+    v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);  // row_half_mirror
+    v += dpp_move<0x140>(v);  // row_mirror
+    return v;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+__host__ __device__ constexpr int rows_per_lane(int np)
+{
+    return np <= 8 ? 32 : np <= 16 ? 16 : np <= 32 ? 8 : 4;
+}
+__host__ __device__ constexpr int round16(int np) { return (np + 15) / 16 * 16; }
+__host__ __device__ constexpr int packed_size(int np) { return np * (np + 1) / 2; }
+// per-wave LDS of the factor kernels: R, Gram entries, reflector broadcast, tau
+__host__ __device__ constexpr int factor_lds_doubles(int np, int tile_rows)
+{
+    return 2 * np * np + tile_rows + np;
+}
+
+// --------------------------------------------------------------------------
+// Householder QR of one tile held in the L layout.
+//
+// FIRST:  the tile is A_0 of a chain; plain Householder on it (reflector j has
+//         v(j) = 1, zeros above, y below).  Its top NP rows end up holding R.
+// !FIRST: the tile is the rectangle under the running triangle R (kept in LDS
+//         at Rs, column-major NP x NP): the QR of [R; A_k] with reflectors
+//         [e_j; y_j] (Alg. 2; triangle on a rectangle, Sec. 3.1).  R is updated
+//         in place, the tile is overwritten by the y_j.
+// WANT_T: also record the Gram entries v_c^T v_j (c < j) in Gs and tau in taus
+//         so that T can be formed afterwards.
+// --------------------------------------------------------------------------
+template <int NP, int RL, bool FIRST, bool WANT_T>
+__device__ __forceinline__ void factor_tile(double (&a)[RL][NP / 4], double* Rs, double* Gs, double* vb,
+                                            double* taus, int lane)
+{
+    constexpr int KC = NP / 4;
+    const int cg = lane >> 4, rg = lane & 15;
+#pragma unroll
+    for (int kb = 0; kb < KC; ++kb) {
+#pragma unroll 1
+        for (int cgj = 0; cgj < 4; ++cgj) {
+            const int j = 4 * kb + cgj;
+            // squared norm of the part of column j below the pivot
+            double sp = 0.0;
+#pragma unroll
+            for (int i = 0; i < RL; ++i) {
+                double x = a[i][kb];
+                if (FIRST && 16 * i + rg <= j) x = 0.0;
+                sp = fma(x, x, sp);
+            }
+            const double s = readlane_d(row_sum16(sp), cgj * 16);
+            double alpha;
+            if (FIRST) alpha = readlane_d(a[kb >> 2][kb], cgj * 16 + (j & 15));
+            else alpha = Rs[j + j * NP];
+            double tau = 0.0, beta = alpha, scale = 0.0;
+            if (s != 0.0) {
+                const double nrm = sqrt(fma(alpha, alpha, s));
+                beta = alpha < 0.0 ? nrm : -nrm;
+                tau = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+            }
+            // the reflector, scaled in place by its owner lanes, broadcast through LDS
+            if (cg == cgj) {
+#pragma unroll
+                for (int i = 0; i < RL; ++i) {
+                    const int r = 16 * i + rg;
+                    double v;
+                    if (FIRST) {
+                        if (r > j) {
+                            a[i][kb] *= scale;
+                            v = a[i][kb];
+                        } else {
+                            v = (r == j) ? 1.0 : 0.0;
+                        }
+                    } else {
+                        a[i][kb] *= scale;
+                        v = a[i][kb];
+                    }
+                    vb[r] = v;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            double vr[RL];
+#pragma unroll
+            for (int i = 0; i < RL; ++i) vr[i] = vb[16 * i + rg];
+            // dot products of v_j with the columns this lane holds
+            double d[KC];
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                d[k] = 0.0;
+                if (!WANT_T && k < kb) continue;
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < RL; ++i) acc = fma(vr[i], a[i][k], acc);
+                d[k] = row_sum16(acc);
+            }
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                if (!WANT_T && k < kb) continue;
+                const int c = 4 * k + cg;
+                const bool trailing = (k > kb) || (k == kb && cg > cgj);
+                const bool earlier = (k < kb) || (k == kb && cg < cgj);
+                if (trailing) {
+                    double w = d[k];
+                    double rjc = 0.0;
+                    if (!FIRST) {
+                        rjc = Rs[j + c * NP];
+                        w += rjc;
+                    }
+                    const double tw = tau * w;
+#pragma unroll
+                    for (int i = 0; i < RL; ++i) a[i][k] = fma(-tw, vr[i], a[i][k]);
+                    if (!FIRST && rg == 0) Rs[j + c * NP] = rjc - tw;
+                } else if (WANT_T && earlier) {
+                    if (rg == 0) Gs[c + j * NP] = d[k];
+                }
+            }
+            if (FIRST) {
+                if (cg == cgj && rg == (j & 15)) a[kb >> 2][kb] = beta;
+            } else {
+                if (lane == 0) Rs[j + j * NP] = beta;
+            }
+            if (lane == 0) taus[j] = tau;
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+// T of H_0 ... H_{NP-1} = I - V T V^T from the Gram entries G(c, j) = v_c^T v_j
+// (c < j) and tau: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).
+// Lane t < NP builds row t; T is written packed (column j at j(j+1)/2).
+template <int NP>
+__device__ __forceinline__ void build_T(const double* Gs, const double* taus, double* __restrict__ Tout, int lane)
+{
+    double tr[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) tr[j] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const double tj = taus[j];
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < j; ++k) acc = fma(tr[k], Gs[k + j * NP], acc);
+        const double v = (lane < j) ? -tj * acc : (lane == j ? tj : 0.0);
+        tr[j] = v;
+        if (lane <= j) Tout[j * (j + 1) / 2 + lane] = v;
+        // keep the loads of later columns from being hoisted all at once
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Tile load/store in the L layout.  The per-lane part of the address
+// (row rg, column cg) is one loop-invariant offset; the rest is uniform, so the
+// compiler does not keep one address per element alive across the chain.
+template <int NP, int RL>
+__device__ __forceinline__ void load_tile(double (&a)[RL][NP / 4], const double* __restrict__ tb, int64_t lda,
+                                          int64_t lane_off, int64_t valid, int n, int rg, int cg)
+{
+    constexpr int KC = NP / 4, MT = 16 * RL;
+    if (valid == MT && n == NP) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const double* cb = tb + (int64_t)(4 * k) * lda + lane_off;
+#pragma unroll
+            for (int i = 0; i < RL; ++i) a[i][k] = cb[16 * i];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const double* cb = tb + (int64_t)(4 * k) * lda + lane_off;
+            const bool cv = 4 * k + cg < n;
+#pragma unroll
+            for (int i = 0; i < RL; ++i) a[i][k] = (cv && 16 * i + rg < valid) ? cb[16 * i] : 0.0;
+        }
+    }
+}
+
+template <int NP, int RL>
+__device__ __forceinline__ void store_tile(const double (&a)[RL][NP / 4], double* __restrict__ tb, int64_t lda,
+                                           int64_t lane_off, int64_t valid, int n, int rg, int cg)
+{
+    constexpr int KC = NP / 4, MT = 16 * RL;
+    if (valid == MT && n == NP) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            double* cb = tb + (int64_t)(4 * k) * lda + lane_off;
+#pragma unroll
+            for (int i = 0; i < RL; ++i) cb[16 * i] = a[i][k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            double* cb = tb + (int64_t)(4 * k) * lda + lane_off;
+            const bool cv = 4 * k + cg < n;
+#pragma unroll
+            for (int i = 0; i < RL; ++i)
+                if (cv && 16 * i + rg < valid) cb[16 * i] = a[i][k];
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Leaf kernel: one wavefront per leaf, the flat chain over its tiles.
+// --------------------------------------------------------------------------
+template <int NP, bool WANT_Q>
+__global__ void __launch_bounds__(256) k_leaf_factor(const double* A, int64_t lda, double* V, int64_t ldv, int64_t m, int n,
+                                                     int64_t P, int64_t leaf_rows, int64_t f,
+                                                     double* __restrict__ Ttile, double* __restrict__ Rleaf)
+{
+    constexpr int RL = rows_per_lane(NP), KC = NP / 4, MT = 16 * RL, NT = packed_size(NP);
+    constexpr int WS = factor_lds_doubles(NP, MT);
+    extern __shared__ double smem[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cg = lane >> 4, rg = lane & 15;
+    const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (leaf >= P) return;
+    double* Rs = smem + wave * WS;
+    double* Gs = Rs + NP * NP;
+    double* vb = Gs + NP * NP;
+    double* taus = vb + MT;
+
+    const int64_t row0 = leaf * leaf_rows;
+    const int64_t rows = (leaf == P - 1) ? (m - row0) : leaf_rows;
+    const int64_t ntl = (rows + MT - 1) / MT;
+    const int64_t lane_off = rg + (int64_t)cg * lda;
+    const int64_t lane_off_v = rg + (int64_t)cg * ldv;
+    double a[RL][KC];
+    for (int64_t t = 0; t < ntl; ++t) {
+        const int64_t t0 = row0 + t * MT;
+        const int64_t valid = (rows - t * MT) < MT ? (rows - t * MT) : MT;
+        load_tile<NP, RL>(a, A + t0, lda, lane_off, valid, n, rg, cg);
+        if (t == 0) {
+            factor_tile<NP, RL, true, WANT_Q>(a, Rs, Gs, vb, taus, lane);
+            // the tile's top NP rows hold R on and above the diagonal
+#pragma unroll
+            for (int i = 0; i < (NP + 15) / 16; ++i) {
+                const int r = 16 * i + rg;
+                if (r < NP) {
+#pragma unroll
+                    for (int k = 0; k < KC; ++k) {
+                        const int c = 4 * k + cg;
+                        Rs[r + c * NP] = (r <= c) ? a[i][k] : 0.0;
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            factor_tile<NP, RL, false, WANT_Q>(a, Rs, Gs, vb, taus, lane);
+        }
+        if (WANT_Q) {
+            store_tile<NP, RL>(a, V + t0, ldv, lane_off_v, valid, n, rg, cg);
+            build_T<NP>(Gs, taus, Ttile + (leaf * f + t) * NT, lane);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    double* Ro = Rleaf + leaf * NP * NP;
+    for (int idx = lane; idx < NP * NP; idx += 64) Ro[idx] = Rs[idx];
+}
+
+// --------------------------------------------------------------------------
+// One level of the binary tree: node q stacks R_{2q} on R_{2q+1} (lower index
+// on top) and factors the pair; an odd last entry is passed up unchanged
+// (Alg. 1).  Y1 (upper triangular) and T of the node are kept for the
+// broadcast of Q.
+// --------------------------------------------------------------------------
+template <int NP, bool WANT_Q>
+__global__ void __launch_bounds__(256) k_tree_level(const double* __restrict__ Rin, int64_t cin,
+                                                    double* __restrict__ Rout, double* __restrict__ Ynode,
+                                                    double* __restrict__ Tnode, int64_t cout)
+{
+    constexpr int RLN = (NP + 15) / 16, KC = NP / 4, MTN = 16 * RLN, NT = packed_size(NP);
+    constexpr int WS = factor_lds_doubles(NP, MTN);
+    extern __shared__ double smem[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cg = lane >> 4, rg = lane & 15;
+    const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (q >= cout) return;
+    const int64_t ia = 2 * q, ib = 2 * q + 1;
+    const double* Ra = Rin + ia * NP * NP;
+    double* Ro = Rout + q * NP * NP;
+    if (ib >= cin) {
+        for (int idx = lane; idx < NP * NP; idx += 64) Ro[idx] = Ra[idx];
+        return;
+    }
+    double* Rs = smem + wave * WS;
+    double* Gs = Rs + NP * NP;
+    double* vb = Gs + NP * NP;
+    double* taus = vb + MTN;
+    for (int idx = lane; idx < NP * NP; idx += 64) Rs[idx] = Ra[idx];
+    const double* Rb = Rin + ib * NP * NP;
+    double a[RLN][KC];
+#pragma unroll
+    for (int i = 0; i < RLN; ++i) {
+        const int r = 16 * i + rg;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const int c = 4 * k + cg;
+            a[i][k] = (r < NP) ? Rb[r + c * NP] : 0.0;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    factor_tile<NP, RLN, false, WANT_Q>(a, Rs, Gs, vb, taus, lane);
+    if (WANT_Q) {
+        build_T<NP>(Gs, taus, Tnode + q * NT, lane);
+        double* Y = Ynode + q * NP * NP;
+#pragma unroll
+        for (int i = 0; i < RLN; ++i) {
+            const int r = 16 * i + rg;
+            if (r < NP) {
+#pragma unroll
+                for (int k = 0; k < KC; ++k) Y[r + (4 * k + cg) * NP] = a[i][k];
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int idx = lane; idx < NP * NP; idx += 64) Ro[idx] = Rs[idx];
+}
+
+// --------------------------------------------------------------------------
+// Root: signs D = diag(sgn(R_jj)) (sgn(0) = +1), the user's R = D R with its
+// strictly lower part zeroed, and the root seed diag(D) of the broadcast.
+// --------------------------------------------------------------------------
+template <int NP>
+__global__ void __launch_bounds__(64) k_root(const double* __restrict__ Rroot, int n, double* __restrict__ R,
+                                             int64_t ldr, double* __restrict__ Dsig, double* __restrict__ Sroot)
+{
+    const int lane = threadIdx.x;
+    for (int idx = lane; idx < NP * NP; idx += 64) {
+        const int i = idx % NP, j = idx / NP;
+        const double di = Rroot[i + i * NP] < 0.0 ? -1.0 : 1.0;
+        if (i < n && j < n) R[i + (int64_t)j * ldr] = (i <= j) ? di * Rroot[idx] : 0.0;
+        if (Sroot) Sroot[idx] = (i == j) ? di : 0.0;
+    }
+    if (lane < NP) Dsig[lane] = Rroot[lane + lane * NP] < 0.0 ? -1.0 : 1.0;
+}
+
+// Matrix-core product Z = T S for NP x NP operands: T packed upper triangular in
+// global memory, S in registers with Sr[s][jb] = S(4s + cg, 16jb + rg).  The
+// result comes back in the same register layout.
+template <int NP>
+__device__ __forceinline__ void tri_times_regs(const double* __restrict__ T, const double (&Sr)[round16(NP) / 4][round16(NP) / 16],
+                                               double (&Zr)[round16(NP) / 4][round16(NP) / 16], int lane)
+{
+    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
+    const int cg = lane >> 4, rg = lane & 15;
+#pragma unroll
+    for (int ib = 0; ib < JB; ++ib) {
+        double tv[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int r = 16 * ib + rg, c = 4 * s + cg;
+            tv[s] = (r <= c && c < NP) ? T[c * (c + 1) / 2 + r] : 0.0;
+        }
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) {
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) acc = mfma16x16x4(tv[s], Sr[s][jb], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Zr[4 * ib + r][jb] = acc[r];
+        }
+    }
+}
+
+template <int NP>
+__device__ __forceinline__ void load_seed(const double* __restrict__ S, double (&Sr)[round16(NP) / 4][round16(NP) / 16],
+                                          int lane)
+{
+    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
+    const int cg = lane >> 4, rg = lane & 15;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) {
+            const int r = 4 * s + cg, c = 16 * jb + rg;
+            Sr[s][jb] = (r < NP && c < NP) ? S[r + c * NP] : 0.0;
+        }
+}
+
+template <int NP>
+__device__ __forceinline__ void store_seed(double* __restrict__ S, const double (&Sr)[round16(NP) / 4][round16(NP) / 16],
+                                           int lane)
+{
+    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
+    const int cg = lane >> 4, rg = lane & 15;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) {
+            const int r = 4 * s + cg, c = 16 * jb + rg;
+            if (r < NP && c < NP) S[r + c * NP] = Sr[s][jb];
+        }
+}
+
+// --------------------------------------------------------------------------
+// One level of the top-down seed descent.  A node with seed S hands
+// (I - T) S = S - Z to its top child and -Y1 Z to its bottom child, Z = T S
+// (from (I - [I; Y1] T [I; Y1]^T) [S; 0]).  A pass-through node hands S down.
+// --------------------------------------------------------------------------
+template <int NP>
+__global__ void __launch_bounds__(256) k_seed_level(const double* __restrict__ Sp, const double* __restrict__ Ynode,
+                                                    const double* __restrict__ Tnode, int64_t cin,
+                                                    double* __restrict__ Sc, int64_t cout)
+{
+    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, NT = packed_size(NP);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cg = lane >> 4, rg = lane & 15;
+    const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (q >= cout) return;
+    const int64_t ia = 2 * q, ib = 2 * q + 1;
+    const double* S = Sp + q * NP * NP;
+    if (ib >= cin) {
+        for (int idx = lane; idx < NP * NP; idx += 64) Sc[ia * NP * NP + idx] = S[idx];
+        return;
+    }
+    double Sr[KS][JB], Zr[KS][JB];
+    load_seed<NP>(S, Sr, lane);
+    tri_times_regs<NP>(Tnode + q * NT, Sr, Zr, lane);
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) Sr[s][jb] -= Zr[s][jb];
+    store_seed<NP>(Sc + ia * NP * NP, Sr, lane);
+    // bottom child: -Y1 Z, Y1 read as the A operand straight from memory
+    const double* Y = Ynode + q * NP * NP;
+    double* Sb = Sc + ib * NP * NP;
+#pragma unroll
+    for (int ibk = 0; ibk < JB; ++ibk) {
+        double yv[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int r = 16 * ibk + rg, c = 4 * s + cg;
+            yv[s] = (r < NP && c < NP) ? Y[r + c * NP] : 0.0;
+        }
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) {
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) acc = mfma16x16x4(yv[s], Zr[s][jb], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * ibk + cg + 4 * r, col = 16 * jb + rg;
+                if (row < NP && col < NP) Sb[row + col * NP] = -acc[r];
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Q kernel: one wavefront per leaf, its chain replayed from the last tile to
+// the first.  Tile k > 0: Z = T_k S_k, Q_k = -Y_k Z, S_{k-1} = S_k - Z.
+// Tile 0: W = V_top^T S_0, Z = T_0 W, Q_0 = [S_0; 0] - V_0 Z.
+// The products run on the matrix cores; Q may alias V.
+// --------------------------------------------------------------------------
+template <int NP>
+__global__ void __launch_bounds__(256) k_form_q(const double* V, int64_t lda, int64_t m, int n, int64_t P,
+                                                int64_t leaf_rows, int64_t f, const double* __restrict__ Ttile,
+                                                const double* __restrict__ Sleaf, double* Q, int64_t ldq)
+{
+    constexpr int RL = rows_per_lane(NP), KC = NP / 4, MT = 16 * RL;
+    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, NT = packed_size(NP);
+    extern __shared__ double smem[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cg = lane >> 4, rg = lane & 15;
+    const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (leaf >= P) return;
+    double* S0 = smem + wave * NPB * NPB;  // S_0 staged for the [S_0; 0] term
+
+    const int64_t row0 = leaf * leaf_rows;
+    const int64_t rows = (leaf == P - 1) ? (m - row0) : leaf_rows;
+    const int64_t ntl = (rows + MT - 1) / MT;
+    double Sr[KS][JB], Zr[KS][JB];
+    load_seed<NP>(Sleaf + leaf * NP * NP, Sr, lane);
+    for (int64_t t = ntl - 1; t >= 0; --t) {
+        const double* T = Ttile + (leaf * f + t) * NT;
+        const int64_t t0 = row0 + t * MT;
+        const int64_t valid = (rows - t * MT) < MT ? (rows - t * MT) : MT;
+        if (t > 0) {
+            tri_times_regs<NP>(T, Sr, Zr, lane);
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int jb = 0; jb < JB; ++jb) Sr[s][jb] -= Zr[s][jb];
+        } else {
+            // W = V_top^T S_0 with V_top the unit lower triangle of the tile's top rows
+            double Wr[KS][JB];
+#pragma unroll
+            for (int ib = 0; ib < JB; ++ib) {
+                double vt[KS];
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    const int r = 4 * s + cg, c = 16 * ib + rg;  // V_top(r, c)
+                    double v = 0.0;
+                    if (r < NP && c < NP) {
+                        if (r == c) v = 1.0;
+                        else if (r > c && r < valid && c < n) v = V[t0 + r + (int64_t)c * lda];
+                    }
+                    vt[s] = v;
+                }
+#pragma unroll
+                for (int jb = 0; jb < JB; ++jb) {
+                    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int s = 0; s < KS; ++s) acc = mfma16x16x4(vt[s], Sr[s][jb], acc);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Wr[4 * ib + r][jb] = acc[r];
+                }
+            }
+            tri_times_regs<NP>(T, Wr, Zr, lane);
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int jb = 0; jb < JB; ++jb) {
+                    const int r = 4 * s + cg, c = 16 * jb + rg;
+                    S0[r + c * NPB] = Sr[s][jb];
+                }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // expansion Q_t = [S_0; 0] (t == 0 only) - V_t Z, 16 rows at a time
+        double nz[KC][JB];
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+#pragma unroll
+            for (int jb = 0; jb < JB; ++jb) nz[k][jb] = -Zr[k][jb];
+#pragma unroll 2
+        for (int i = 0; i < RL; ++i) {
+            const int rl = 16 * i + rg;
+            const bool rv = rl < valid;
+            const int64_t row = t0 + rl;
+            double y[KC];
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const int c = 4 * k + cg;
+                y[k] = (rv && c < n) ? V[row + (int64_t)c * lda] : 0.0;
+                if (t == 0 && rl < NP) y[k] = (rl > c) ? y[k] : (rl == c ? 1.0 : 0.0);
+            }
+#pragma unroll
+            for (int jb = 0; jb < JB; ++jb) {
+                dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < KC; ++k) acc = mfma16x16x4(nz[k][jb], y[k], acc);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = 16 * jb + cg + 4 * r;
+                    if (rv && c < n) {
+                        double v = acc[r];
+                        if (t == 0 && rl < NP) v += S0[rl + c * NPB];
+                        Q[row + (int64_t)c * ldq] = v;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename K>
+void allow_lds(K kernel, size_t bytes)
+{
+    if (bytes > 64 * 1024)
+        hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes);
+}
+
+inline unsigned grid_for(int64_t items, int waves) { return (unsigned)((items + waves - 1) / waves); }
+
+template <int NP>
+hipError_t leaf_factor_np(const Layout& L, const double* A, int64_t lda, double* V, int64_t ldv, double* ws,
+                          bool want_q, hipStream_t s)
+{
+    constexpr int MT = 16 * rows_per_lane(NP);
+    const size_t lds = (size_t)L.waves * factor_lds_doubles(NP, MT) * sizeof(double);
+    const dim3 grid(grid_for(L.P, L.waves)), block(64 * L.waves);
+    if (want_q) {
+        allow_lds(k_leaf_factor<NP, true>, lds);
+        hipLaunchKernelGGL((k_leaf_factor<NP, true>), grid, block, lds, s, A, lda, V, ldv, L.m, (int)L.n, L.P,
+                           L.leaf_rows, L.f, ws + L.off_T, ws + L.off_R[0]);
+    } else {
+        allow_lds(k_leaf_factor<NP, false>, lds);
+        hipLaunchKernelGGL((k_leaf_factor<NP, false>), grid, block, lds, s, A, lda, V, ldv, L.m, (int)L.n, L.P,
+                           L.leaf_rows, L.f, ws + L.off_T, ws + L.off_R[0]);
+    }
+    return hipGetLastError();
+}
+
+template <int NP>
+hipError_t tree_np(const Layout& L, double* ws, bool want_q, hipStream_t s)
+{
+    constexpr int MTN = 16 * ((NP + 15) / 16);
+    const int waves = NP <= 32 ? 4 : 2;  // per-wave LDS grows as NP^2
+    const size_t lds = (size_t)waves * factor_lds_doubles(NP, MTN) * sizeof(double);
+    for (int l = 1; l <= L.levels; ++l) {
+        const dim3 grid(grid_for(L.count[l], waves)), block(64 * waves);
+        if (want_q) {
+            allow_lds(k_tree_level<NP, true>, lds);
+            hipLaunchKernelGGL((k_tree_level<NP, true>), grid, block, lds, s, ws + L.off_R[l - 1], L.count[l - 1],
+                               ws + L.off_R[l], ws + L.off_Y[l], ws + L.off_TN[l], L.count[l]);
+        } else {
+            allow_lds(k_tree_level<NP, false>, lds);
+            hipLaunchKernelGGL((k_tree_level<NP, false>), grid, block, lds, s, ws + L.off_R[l - 1],
+                               L.count[l - 1], ws + L.off_R[l], ws + L.off_Y[l], ws + L.off_TN[l], L.count[l]);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int NP>
+hipError_t root_np(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_root<NP>), dim3(1), dim3(64), 0, s, ws + L.off_R[L.levels], (int)L.n, R, ldr,
+                       ws + L.off_D, ws + L.off_S[L.levels]);
+    return hipGetLastError();
+}
+
+template <int NP>
+hipError_t seeds_np(const Layout& L, double* ws, hipStream_t s)
+{
+    const int waves = 4;
+    for (int l = L.levels; l >= 1; --l) {
+        const dim3 grid(grid_for(L.count[l], waves)), block(64 * waves);
+        hipLaunchKernelGGL((k_seed_level<NP>), grid, block, 0, s, ws + L.off_S[l], ws + L.off_Y[l],
+                           ws + L.off_TN[l], L.count[l - 1], ws + L.off_S[l - 1], L.count[l]);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int NP>
+hipError_t form_q_np(const Layout& L, const double* A, int64_t lda, double* ws, double* Q, int64_t ldq,
+                     hipStream_t s)
+{
+    constexpr int NPB = round16(NP);
+    const size_t lds = (size_t)L.waves * NPB * NPB * sizeof(double);
+    const dim3 grid(grid_for(L.P, L.waves)), block(64 * L.waves);
+    allow_lds(k_form_q<NP>, lds);
+    hipLaunchKernelGGL((k_form_q<NP>), grid, block, lds, s, A, lda, L.m, (int)L.n, L.P, L.leaf_rows, L.f,
+                       ws + L.off_T, ws + L.off_S[0], Q, ldq);
+    return hipGetLastError();
+}
+
+}  // namespace detail
+
+template <int NP>
+hipError_t leaf_factor_np(const Layout& L, const double* A, int64_t lda, double* V, int64_t ldv, double* ws,
+                          bool want_q, hipStream_t s)
+{
+    return detail::leaf_factor_np<NP>(L, A, lda, V, ldv, ws, want_q, s);
+}
+template <int NP>
+hipError_t tree_np(const Layout& L, double* ws, bool want_q, hipStream_t s)
+{
+    return detail::tree_np<NP>(L, ws, want_q, s);
+}
+template <int NP>
+hipError_t root_np(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s)
+{
+    return detail::root_np<NP>(L, ws, R, ldr, s);
+}
+template <int NP>
+hipError_t seeds_np(const Layout& L, double* ws, hipStream_t s)
+{
+    return detail::seeds_np<NP>(L, ws, s);
+}
+template <int NP>
+hipError_t form_q_np(const Layout& L, const double* A, int64_t lda, double* ws, double* Q, int64_t ldq,
+                     hipStream_t s)
+{
+    return detail::form_q_np<NP>(L, A, lda, ws, Q, ldq, s);
+}
+
+}  // namespace tsqr

@@ -1,0 +1,156 @@
+"""Python binding of libtsqr with the C ABI's names.  torch supplies device
+memory and the current HIP stream; the binding only marshals pointers, leading
+dimensions and options.
+
+Matrices are column-major: an m x n matrix with leading dimension ld is a torch
+tensor of shape (m, n) and strides (1, ld), e.g. ``colmajor(m, n)`` or
+``T.t()`` for a contiguous (n, ld) tensor T.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import (PHASES, TSQR_FP64, TSQR_MIXED, TSQR_TREE_AUTO, TSQR_TREE_BINARY, TSQR_TREE_FLAT,
+                   TSQR_TREE_HYBRID, TsqrInfo, TsqrOpts, TsqrTimings, check)
+
+_TREES = {"auto": TSQR_TREE_AUTO, "binary": TSQR_TREE_BINARY, "flat": TSQR_TREE_FLAT,
+          "hybrid": TSQR_TREE_HYBRID}
+_PREC = {"fp64": TSQR_FP64, "mixed": TSQR_MIXED}
+
+
+def colmajor(m: int, n: int, device="cuda", ld: Optional[int] = None, dtype=torch.float64) -> torch.Tensor:
+    """An uninitialised m x n column-major tensor with leading dimension ld."""
+    ld = m if ld is None else ld
+    return torch.empty((n, ld), dtype=dtype, device=device).t()[:m]
+
+
+def to_colmajor(X: torch.Tensor, device="cuda") -> torch.Tensor:
+    Y = colmajor(X.shape[0], X.shape[1], device=device, dtype=torch.float64)
+    Y.copy_(X)
+    return Y
+
+
+def _ld(X: torch.Tensor, rows: int, name: str) -> int:
+    if X.dim() != 2 or X.dtype != torch.float64:
+        raise ValueError(f"{name}: a 2-D float64 tensor is required")
+    if not X.is_cuda:
+        raise ValueError(f"{name}: a device tensor is required")
+    if X.shape[0] != rows:
+        raise ValueError(f"{name}: expected {rows} rows, got {X.shape[0]}")
+    if X.stride(0) != 1 and X.shape[0] > 1:
+        raise ValueError(f"{name}: must be column-major (stride (1, ld))")
+    return max(X.stride(1), rows) if X.shape[1] > 1 else max(rows, 1)
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def plan_query(m: int, n: int, precision: str = "fp64", tree: str = "auto", leaf_rows: int = 0,
+               tile_rows: int = 0, flat_len: int = 0, waves: int = 0, want_q: bool = True) -> dict:
+    """tsqr_plan_query: what a plan would choose (no device needed)."""
+    lib = _lib.load()
+    opts = TsqrOpts(_TREES[tree], int(leaf_rows), int(tile_rows), int(flat_len), int(waves), 1 if want_q else 0)
+    out = TsqrInfo()
+    check("tsqr_plan_query", lib.tsqr_plan_query(int(m), int(n), _PREC[precision], ctypes.byref(opts),
+                                                 ctypes.byref(out)))
+    return {f: getattr(out, f) for f, _ in TsqrInfo._fields_}
+
+
+class Plan:
+    """tsqr_plan_create / tsqr_factor / tsqr_form_q / tsqr_apply_qt /
+    tsqr_plan_info / tsqr_plan_destroy."""
+
+    def __init__(self, m: int, n: int, precision: str = "fp64", tree: str = "auto", leaf_rows: int = 0,
+                 tile_rows: int = 0, flat_len: int = 0, waves: int = 0, want_q: bool = True, stream=None):
+        self._lib = _lib.load()
+        self.m, self.n = int(m), int(n)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        opts = TsqrOpts(_TREES[tree], int(leaf_rows), int(tile_rows), int(flat_len), int(waves),
+                        1 if want_q else 0)
+        h = ctypes.c_void_p()
+        check("tsqr_plan_create", self._lib.tsqr_plan_create(ctypes.byref(h), self.m, self.n, _PREC[precision],
+                                                              ctypes.byref(opts), _stream_handle(self.stream)))
+        self._h = h
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            check("tsqr_plan_destroy", self._lib.tsqr_plan_destroy(h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def info(self) -> dict:
+        out = TsqrInfo()
+        check("tsqr_plan_info", self._lib.tsqr_plan_info(self._h, ctypes.byref(out)))
+        return {f: getattr(out, f) for f, _ in TsqrInfo._fields_}
+
+    def factor(self, A: torch.Tensor, R: Optional[torch.Tensor] = None) -> torch.Tensor:
+        lda = _ld(A, self.m, "A")
+        if R is None:
+            R = colmajor(self.n, self.n, device=A.device)
+        ldr = _ld(R, self.n, "R")
+        check("tsqr_factor", self._lib.tsqr_factor(self._h, A.data_ptr(), lda, R.data_ptr(), ldr))
+        return R
+
+    def factor_into(self, A: torch.Tensor, V: Optional[torch.Tensor], R: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """tsqr_factor_into: A is only read; the reflectors go to V."""
+        lda = _ld(A, self.m, "A")
+        if R is None:
+            R = colmajor(self.n, self.n, device=A.device)
+        ldr = _ld(R, self.n, "R")
+        vptr, ldv = (V.data_ptr(), _ld(V, self.m, "V")) if V is not None else (0, self.m)
+        check("tsqr_factor_into", self._lib.tsqr_factor_into(self._h, A.data_ptr(), lda, vptr, ldv,
+                                                             R.data_ptr(), ldr))
+        return R
+
+    def profile(self, enable: bool = True) -> None:
+        check("tsqr_plan_profile", self._lib.tsqr_plan_profile(self._h, 1 if enable else 0))
+
+    def timings(self) -> dict:
+        """Summed device milliseconds and call counts per phase since profile()."""
+        out = TsqrTimings()
+        check("tsqr_plan_timings", self._lib.tsqr_plan_timings(self._h, ctypes.byref(out)))
+        return {name: (out.ms[i], out.calls[i]) for i, name in enumerate(PHASES)}
+
+    def form_q(self, A: torch.Tensor, Q: Optional[torch.Tensor] = None) -> torch.Tensor:
+        lda = _ld(A, self.m, "A")
+        if Q is None:
+            Q = colmajor(self.m, self.n, device=A.device)
+        ldq = _ld(Q, self.m, "Q")
+        check("tsqr_form_q", self._lib.tsqr_form_q(self._h, A.data_ptr(), lda, Q.data_ptr(), ldq))
+        return Q
+
+    def apply_qt(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
+        lda = _ld(A, self.m, "A")
+        ldb = _ld(B, self.m, "B")
+        check("tsqr_apply_qt", self._lib.tsqr_apply_qt(self._h, A.data_ptr(), lda, B.shape[1], B.data_ptr(), ldb))
+        return B
+
+
+def qr(A: torch.Tensor, **plan_kw):
+    """Thin QR of a column-major device matrix: returns (Q, R); A is overwritten
+    by the reflectors."""
+    m, n = A.shape
+    with Plan(m, n, **plan_kw) as p:
+        R = p.factor(A)
+        Q = p.form_q(A)
+        torch.cuda.current_stream().synchronize()
+    return Q, R

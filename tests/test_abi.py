@@ -1,0 +1,109 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/tsqr.h declares, rejects bad arguments before touching a device, and
+its layout (leaves, tiles, tree) follows the paper's partition rules."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "tsqr.h")).read()
+    return sorted(set(re.findall(r"\b(tsqr_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    from paper_0809_2407_amd import _lib
+    assert _declared_functions() == sorted(_lib.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_0809_2407_amd import _lib
+    lib = _lib.load()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_version():
+    from paper_0809_2407_amd import _lib
+    lib = _lib.load()
+    assert lib.tsqr_status_string(0) == b"success"
+    assert b"invalid argument" in lib.tsqr_status_string(-2)
+    assert b"out of order" in lib.tsqr_status_string(4)
+    assert lib.tsqr_version() >= 100
+
+
+def test_argument_errors_without_device():
+    from paper_0809_2407_amd import _lib
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.tsqr_plan_create(None, 100, 4, 0, None, None) == -1
+    assert lib.tsqr_plan_create(ctypes.byref(h), 3, 4, 0, None, None) == -2  # m < n
+    assert lib.tsqr_plan_create(ctypes.byref(h), 0, 0, 0, None, None) == -2
+    assert lib.tsqr_plan_create(ctypes.byref(h), 100, 0, 0, None, None) == -3
+    assert lib.tsqr_plan_create(ctypes.byref(h), 1000, 65, 0, None, None) == 3  # n > 64 unsupported
+    assert lib.tsqr_plan_create(ctypes.byref(h), 1000, 8, 7, None, None) == -4
+    bad = _lib.TsqrOpts(9, 0, 0, 0, 0, 1)
+    assert lib.tsqr_plan_create(ctypes.byref(h), 1000, 8, 0, ctypes.byref(bad), None) == -5
+    bad = _lib.TsqrOpts(0, 0, 0, 0, 3, 1)  # waves must be 1, 2 or 4
+    assert lib.tsqr_plan_create(ctypes.byref(h), 1000, 8, 0, ctypes.byref(bad), None) == -5
+    assert lib.tsqr_factor(None, 1, 1, 1, 1) == -1
+    assert lib.tsqr_form_q(None, 1, 1, 1, 1) == -1
+    assert lib.tsqr_apply_qt(None, 1, 1, 1, 1, 1) == -1
+    assert lib.tsqr_plan_info(None, None) == -1
+    assert lib.tsqr_plan_destroy(None) == -1
+    out = _lib.TsqrInfo()
+    assert lib.tsqr_plan_query(3, 4, 0, None, ctypes.byref(out)) == -1
+    assert lib.tsqr_plan_query(100, 0, 0, None, ctypes.byref(out)) == -2
+    assert lib.tsqr_plan_query(100, 4, 5, None, ctypes.byref(out)) == -3
+    assert lib.tsqr_plan_query(100, 4, 0, None, None) == -5
+
+
+def _query(**kw):
+    from paper_0809_2407_amd.tsqr import plan_query
+    return plan_query(**kw)
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 8, 16, 17, 20, 32, 33, 48, 64])
+def test_tile_rows_respect_fast_memory_bound(n):
+    """m/P * n + n(n+1)/2 <= W (Sec. 4.2) with W the per-wavefront register
+    budget for the tile (64 doubles per lane, 4096 per wavefront)."""
+    q = _query(m=1 << 20, n=n)
+    np_ = q["n_padded"]
+    assert np_ % 4 == 0 and np_ >= n and np_ - n < 4
+    assert q["tile_rows"] * np_ <= 64 * 64
+    assert q["tile_rows"] >= np_
+
+
+def test_leaf_partition_last_leaf_absorbs_remainder():
+    q = _query(m=4096, n=16, leaf_rows=512)
+    assert q["num_leaves"] == 8 and q["tree_levels"] == 3 and q["tree"] == 1 + 2  # hybrid: 2 tiles per leaf
+    q = _query(m=4096 + 300, n=16, leaf_rows=512)
+    assert q["num_leaves"] == 8  # 300 extra rows go to the last leaf
+    assert q["num_tiles"] == 7 * 2 + (512 + 300 + 255) // 256
+    q = _query(m=500, n=16, leaf_rows=512)
+    assert q["num_leaves"] == 1 and q["tree_levels"] == 0
+
+
+def test_tree_shapes():
+    b = _query(m=1 << 16, n=32, tree="binary")
+    assert b["leaf_rows"] == b["tile_rows"] and b["num_leaves"] == (1 << 16) // b["tile_rows"]
+    f = _query(m=1 << 16, n=32, tree="flat")
+    assert f["num_leaves"] == 1 and f["tree_levels"] == 0
+    h = _query(m=1 << 16, n=32, tree="hybrid", flat_len=8)
+    assert h["leaf_rows"] == 8 * h["tile_rows"]
+    assert h["tree_levels"] == (h["num_leaves"] - 1).bit_length()
+
+
+def test_levels_match_binary_pairing():
+    for P in [1, 2, 3, 5, 8, 13, 4096, 4097]:
+        q = _query(m=P * 128, n=32, leaf_rows=128)
+        assert q["num_leaves"] == P
+        L, c = 0, P
+        while c > 1:
+            c = (c + 1) // 2
+            L += 1
+        assert q["tree_levels"] == L
