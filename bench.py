@@ -99,6 +99,9 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 24)
     ap.add_argument("--no-check", action="store_true", help="skip the accuracy check after timing")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="before warm-up, run one plain device copy of m x n doubles (8mn bytes read, "
+                         "8mn written) so that hardware byte counters can be scaled against it")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -128,6 +131,12 @@ def main(argv=None) -> int:
         if mode == "rq":
             plan.form_q(V, Q)
 
+    if args.calibrate_copy:
+        Cdst = T.colmajor(m, n)
+        Cdst.copy_(A)
+        torch.cuda.synchronize()
+        del Cdst
+        log(f"calibration copy: {8 * m * n} bytes read, {8 * m * n} bytes written")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

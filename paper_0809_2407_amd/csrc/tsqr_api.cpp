@@ -13,8 +13,6 @@
 
 namespace tsqr {
 
-static int rows_per_lane_host(int np) { return np <= 8 ? 32 : np <= 16 ? 16 : np <= 32 ? 8 : 4; }
-
 bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves)
 {
     if (n < 1 || n > kMaxN || m < n) return false;
@@ -23,8 +21,7 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
     L.n = n;
     L.np = (int)((n + 3) / 4 * 4);
     L.npb = (int)((n + 15) / 16 * 16);
-    L.rl = rows_per_lane_host(L.np);
-    L.mt = 16 * L.rl;
+    L.mt = tile_rows_for(L.np);
     L.waves = waves > 0 ? waves : (L.np <= 32 ? 4 : 2);
     const int64_t tiles_total = (m + L.mt - 1) / L.mt;
     int64_t f;

@@ -10,13 +10,22 @@ namespace tsqr {
 constexpr int kMaxLevels = 48;
 constexpr int kMaxN = 64;
 
+// Rows per tile for a padded column count np: about 4096 tile elements per
+// wavefront (64 doubles per lane, the register budget of the leaf kernel), a
+// multiple of 16, at most 512.  This is the fast-memory constraint of
+// sequential TSQR (tile rows * n + n(n+1)/2 <= W) with W a wavefront's
+// registers; the triangle R itself lives in LDS.
+__host__ __device__ constexpr int tile_rows_for(int np)
+{
+    return (4096 / np / 16 * 16) > 512 ? 512 : (4096 / np / 16 * 16);
+}
+
 // Geometry of one TSQR problem: tiles, leaves (flat chains of tiles) and the
 // binary tree over the leaves, plus the offsets of every workspace buffer.
 struct Layout {
     int64_t m = 0, n = 0;
     int np = 0;          // n rounded up to a multiple of 4 (kernel column granularity)
     int npb = 0;         // n rounded up to a multiple of 16 (matrix-core block)
-    int rl = 0;          // 16-row slots per lane: a tile has 16*rl rows
     int64_t mt = 0;      // tile rows
     int waves = 0;       // wavefronts per workgroup of the leaf kernel
     int64_t f = 0;       // tiles per leaf chain (every leaf but the last)

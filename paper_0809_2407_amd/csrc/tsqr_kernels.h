@@ -43,19 +43,21 @@ __device__ __forceinline__ dbl4 mfma16x16x4(double a, double b, dbl4 c)
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the 16 lanes of a DPP row.  Each step adds a partner whose own step
-// adds the same two operands, so all 16 lanes end with identical bits.
-__device__ __forceinline__ double row_sum16(double v)
+// Sum over groups of LR consecutive lanes (LR = 8 or 16, inside one DPP row).
+// Each step adds a partner whose own step adds the same two operands, so all
+// lanes of a group end with identical bits.
+template <int LR>
+__device__ __forceinline__ double group_sum(double v)
 {
-    v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_move<0x141>(v);  // row_half_mirror
-    v += dpp_move<0x140>(v);  // row_mirror
+    v += dpp_move<0xB1>(v);       // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);       // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);      // row_half_mirror: lane i <-> 7-i within 8
+    if (LR == 16) v += dpp_move<0x140>(v);  // row_mirror: lane i <-> 15-i within 16
     return v;
 }
 
@@ -66,20 +68,56 @@ __device__ __forceinline__ double readlane_d(double v, int lane)
     return __hiloint2double(hi, lo);
 }
 
-__host__ __device__ constexpr int rows_per_lane(int np)
+// 1/p to about one ulp: hardware reciprocal and two Newton steps.
+__device__ __forceinline__ double recip(double p)
 {
-    return np <= 8 ? 32 : np <= 16 ? 16 : np <= 32 ? 8 : 4;
+    double r = __builtin_amdgcn_rcp(p);
+    double e = fma(-p, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-p, r, 1.0);
+    return fma(r, e, r);
 }
+
+// sqrt for positive normal arguments: hardware reciprocal square root and one
+// Goldschmidt/Newton refinement of both the root and its half-reciprocal
+// (no rescaling of subnormal or huge inputs).
+__device__ __forceinline__ double sqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+
 __host__ __device__ constexpr int round16(int np) { return (np + 15) / 16 * 16; }
+// Leading dimension of the triangle R in LDS: odd, so that the columns a
+// wavefront touches at once fall into different banks.
+__host__ __device__ constexpr int rs_ld(int np) { return np + 1; }
+// Stride (doubles) between the per-lane segments of the reflector broadcast
+// buffer: s = 2 mod 4, so that 8 or 16 segments read 16 bytes at a time hit
+// disjoint banks, and 16-byte aligned.
+__host__ __device__ constexpr int vb_stride(int rl) { return (rl % 4 == 2) ? rl : (rl % 4 == 3) ? rl + 3 : (rl % 4 == 1) ? rl + 1 : rl + 2; }
 __host__ __device__ constexpr int packed_size(int np) { return np * (np + 1) / 2; }
+// Column groups of the factor layout: 8 when NP is a multiple of 8, else 4.
+__host__ __device__ constexpr int col_groups(int np) { return np % 8 == 0 ? 8 : 4; }
+// The Gram area of the factor kernels also serves as the 16-row chunk buffer of
+// gram_mfma (16 x (np+1) doubles).
+__host__ __device__ constexpr int gram_area(int np) { return np * np > 16 * (np + 1) ? np * np : 16 * (np + 1); }
 // per-wave LDS of the factor kernels: R, Gram entries, reflector broadcast, tau
 __host__ __device__ constexpr int factor_lds_doubles(int np, int tile_rows)
 {
-    return 2 * np * np + tile_rows + np;
+    return np * rs_ld(np) + gram_area(np) + (64 / (np % 8 == 0 ? 8 : 4)) * vb_stride(tile_rows / (64 / (np % 8 == 0 ? 8 : 4))) + np;
 }
 
 // --------------------------------------------------------------------------
-// Householder QR of one tile held in the L layout.
+// Householder QR of one tile held in registers.
+//
+// Layout: LC column groups of LR = 64/LC lanes; lane l = LR*cg + rg holds rows
+// LR*i + rg (i < RL) and columns LC*k + cg (k < NP/LC) in a[i][k].  A sum over
+// the rows of a column is a sum over the LR lanes of one group (DPP steps).
 //
 // FIRST:  the tile is A_0 of a chain; plain Householder on it (reflector j has
 //         v(j) = 1, zeros above, y below).  Its top NP rows end up holding R.
@@ -87,104 +125,195 @@ __host__ __device__ constexpr int factor_lds_doubles(int np, int tile_rows)
 //         at Rs, column-major NP x NP): the QR of [R; A_k] with reflectors
 //         [e_j; y_j] (Alg. 2; triangle on a rectangle, Sec. 3.1).  R is updated
 //         in place, the tile is overwritten by the y_j.
-// WANT_T: also record the Gram entries v_c^T v_j (c < j) in Gs and tau in taus
-//         so that T can be formed afterwards.
+// tau_j is recorded in taus for the compact-WY factor T (see gram_mfma and
+// build_T).
+//
+// A reflector column is left unscaled in the registers while the tile is
+// factored (y = x * sc, sc[k] holds the scale of the lane's column k, 1 for a
+// column that is not a reflector yet); scale_tile applies it at the end.
+// The magnitudes are assumed to keep (alpha - beta) * beta within the normal
+// FP64 range (no scaling of the column norm).
 // --------------------------------------------------------------------------
-template <int NP, int RL, bool FIRST, bool WANT_T>
-__device__ __forceinline__ void factor_tile(double (&a)[RL][NP / 4], double* Rs, double* Gs, double* vb,
-                                            double* taus, int lane)
+template <int NP, int RL, int LC, bool FIRST>
+__device__ __forceinline__ void factor_tile(double (&a)[RL][NP / LC], double (&sc)[NP / LC], double* Rs,
+                                            double* vb, double* taus, int lane)
 {
-    constexpr int KC = NP / 4;
-    const int cg = lane >> 4, rg = lane & 15;
+    constexpr int KC = NP / LC, LR = 64 / LC, RLD = rs_ld(NP);
+    const int cg = lane / LR, rg = lane % LR;
+    double* my_vb = vb + rg * vb_stride(RL);  // this lane's rows of the broadcast reflector
+#pragma unroll
+    for (int k = 0; k < KC; ++k) sc[k] = 1.0;
 #pragma unroll
     for (int kb = 0; kb < KC; ++kb) {
+        const int ij = (LC * kb) / LR;   // register slot of the pivot rows of this block
+        const int rg0 = (LC * kb) % LR;  // lane (within a group) of the block's first pivot row
 #pragma unroll 1
-        for (int cgj = 0; cgj < 4; ++cgj) {
-            const int j = 4 * kb + cgj;
-            // squared norm of the part of column j below the pivot
-            double sp = 0.0;
+        for (int cgj = 0; cgj < LC; ++cgj) {
+            const int j = LC * kb + cgj;
+            // squared norm of the part of column j below the pivot (two chains)
+            double sp0 = 0.0, sp1 = 0.0;
 #pragma unroll
             for (int i = 0; i < RL; ++i) {
                 double x = a[i][kb];
-                if (FIRST && 16 * i + rg <= j) x = 0.0;
-                sp = fma(x, x, sp);
+                if (FIRST && LR * i + rg <= j) x = 0.0;
+                if (i & 1) sp1 = fma(x, x, sp1);
+                else sp0 = fma(x, x, sp0);
             }
-            const double s = readlane_d(row_sum16(sp), cgj * 16);
+            const double s = readlane_d(group_sum<LR>(sp0 + sp1), cgj * LR);
             double alpha;
-            if (FIRST) alpha = readlane_d(a[kb >> 2][kb], cgj * 16 + (j & 15));
-            else alpha = Rs[j + j * NP];
-            double tau = 0.0, beta = alpha, scale = 0.0;
-            if (s != 0.0) {
-                const double nrm = sqrt(fma(alpha, alpha, s));
-                beta = alpha < 0.0 ? nrm : -nrm;
-                tau = (beta - alpha) / beta;
-                scale = 1.0 / (alpha - beta);
-            }
-            // the reflector, scaled in place by its owner lanes, broadcast through LDS
-            if (cg == cgj) {
+            if (FIRST) alpha = readlane_d(a[ij][kb], cgj * LR + rg0 + cgj);
+            else alpha = Rs[j + j * RLD];
+            // beta = -sgn(alpha) ||x||, tau = (beta - alpha)/beta = -d/beta, scale = 1/d
+            // with d = alpha - beta; tau = 0 (H_j = I) when the part below the
+            // pivot is zero.  Branch-free: the selects discard the inf/NaN of s == 0.
+            const bool nz = s != 0.0;
+            const double nrm = sqrt_pos(fma(alpha, alpha, s));
+            const double bn = alpha < 0.0 ? nrm : -nrm;
+            const double dd = alpha - bn;
+            const double rr = recip(dd * bn);
+            const double beta = nz ? bn : alpha;
+            const double scale = nz ? bn * rr : 0.0;
+            const double tau = nz ? -(dd * dd) * rr : 0.0;
+            // the reflector: its owner lanes scale and broadcast it through LDS
+            const bool owner = cg == cgj;
+            if (owner) {
 #pragma unroll
                 for (int i = 0; i < RL; ++i) {
-                    const int r = 16 * i + rg;
-                    double v;
-                    if (FIRST) {
-                        if (r > j) {
-                            a[i][kb] *= scale;
-                            v = a[i][kb];
-                        } else {
-                            v = (r == j) ? 1.0 : 0.0;
-                        }
-                    } else {
-                        a[i][kb] *= scale;
-                        v = a[i][kb];
-                    }
-                    vb[r] = v;
+                    const int row = LR * i + rg;
+                    double v = a[i][kb] * scale;
+                    if (FIRST) v = row > j ? v : (row == j ? 1.0 : 0.0);
+                    my_vb[i] = v;
                 }
+                sc[kb] = scale;
             }
+            // the other lanes read what the owners wrote: the compiler reasons per
+            // lane, so this barrier keeps their loads after the owners' stores
             __builtin_amdgcn_wave_barrier();
             double vr[RL];
 #pragma unroll
-            for (int i = 0; i < RL; ++i) vr[i] = vb[16 * i + rg];
-            // dot products of v_j with the columns this lane holds
+            for (int i = 0; i < RL; ++i) vr[i] = my_vb[i];
+            // dot products of v_j with the trailing columns this lane holds (two chains)
             double d[KC];
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
                 d[k] = 0.0;
-                if (!WANT_T && k < kb) continue;
-                double acc = 0.0;
+                if (k < kb) continue;
+                double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
-                for (int i = 0; i < RL; ++i) acc = fma(vr[i], a[i][k], acc);
-                d[k] = row_sum16(acc);
+                for (int i = 0; i < RL; ++i) {
+                    if (i & 1) acc1 = fma(vr[i], a[i][k], acc1);
+                    else acc0 = fma(vr[i], a[i][k], acc0);
+                }
+                d[k] = group_sum<LR>(acc0 + acc1);
             }
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
-                if (!WANT_T && k < kb) continue;
-                const int c = 4 * k + cg;
-                const bool trailing = (k > kb) || (k == kb && cg > cgj);
-                const bool earlier = (k < kb) || (k == kb && cg < cgj);
-                if (trailing) {
-                    double w = d[k];
-                    double rjc = 0.0;
-                    if (!FIRST) {
-                        rjc = Rs[j + c * NP];
-                        w += rjc;
-                    }
-                    const double tw = tau * w;
-#pragma unroll
-                    for (int i = 0; i < RL; ++i) a[i][k] = fma(-tw, vr[i], a[i][k]);
-                    if (!FIRST && rg == 0) Rs[j + c * NP] = rjc - tw;
-                } else if (WANT_T && earlier) {
-                    if (rg == 0) Gs[c + j * NP] = d[k];
+                const int c = LC * k + cg;
+                if (k < kb) continue;
+                // k == kb: only the columns right of the pivot are trailing
+                const bool trailing = (k > kb) || (cg > cgj);
+                double w = d[k];
+                double rjc = 0.0;
+                if (!FIRST) {
+                    rjc = Rs[j + c * RLD];
+                    w += rjc;
                 }
+                const double tw = trailing ? tau * w : 0.0;
+#pragma unroll
+                for (int i = 0; i < RL; ++i) a[i][k] = fma(-tw, vr[i], a[i][k]);
+                if (!FIRST && rg == 0 && trailing) Rs[j + c * RLD] = rjc - tw;
             }
             if (FIRST) {
-                if (cg == cgj && rg == (j & 15)) a[kb >> 2][kb] = beta;
+                if (owner && rg == rg0 + cgj) a[ij][kb] = beta;
             } else {
-                if (lane == 0) Rs[j + j * NP] = beta;
+                if (lane == 0) Rs[j + j * RLD] = beta;
             }
             if (lane == 0) taus[j] = tau;
-            __builtin_amdgcn_wave_barrier();
         }
     }
+    // R and tau are read by other lanes after the tile
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Applies the deferred reflector scales: y = x * sc below the diagonal (FIRST)
+// or in every row (chained tiles).
+template <int NP, int RL, int LC, bool FIRST>
+__device__ __forceinline__ void scale_tile(double (&a)[RL][NP / LC], const double (&sc)[NP / LC], int lane)
+{
+    constexpr int KC = NP / LC, LR = 64 / LC;
+    const int cg = lane / LR, rg = lane % LR;
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+            if (FIRST) a[i][k] = (LR * i + rg > LC * k + cg) ? a[i][k] * sc[k] : a[i][k];
+            else a[i][k] *= sc[k];
+        }
+}
+
+// Gram matrix G = V^T V of a factored tile on the matrix cores.  The tile sits
+// in registers in the factor layout (rows on the lanes of a group), which the
+// f64 16x16x4 op cannot contract over; so 16-row chunks go through LDS (cb,
+// 16 x (NP+1) doubles) and are read back with rows on the lane-group index:
+// lane (q, p) takes rows 4s + q and column 16b + p, the operand layout of both
+// V^T (A) and V (B).  Reflectors: FIRST tiles have v_c(r) = 0 above the
+// diagonal and 1 on it; chained tiles [e_c; y_c] contribute y_c^T y_d
+// (c != d).  Writes the strictly upper part G(c, d), c < d, to Gs.
+template <int NP, int RL, int LC, bool FIRST>
+__device__ __forceinline__ void gram_mfma(const double (&a)[RL][NP / LC], double* cb, double* Gs, int lane)
+{
+    constexpr int KC = NP / LC, LR = 64 / LC, MT = LR * RL, LDP = NP + 1;
+    constexpr int NPB = round16(NP), JB = NPB / 16;
+    static_assert(MT % 16 == 0, "gram_mfma reads whole 16-row chunks");
+    const int cg = lane / LR, rg = lane % LR;
+    const int q = lane >> 4, p = lane & 15;
+    dbl4 acc[JB][JB];
+#pragma unroll
+    for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) acc[ib][jb] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c0 = 0; c0 < MT; c0 += 16) {
+        // this lane's rows inside the chunk [c0, c0 + 16)
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+            const int row = LR * i + rg;
+            if (LR * i + LR <= c0 || LR * i >= c0 + 16) continue;  // slot outside the chunk (compile-time test
+            if (row < c0 || row >= c0 + 16) continue;               // on i, runtime on rg)
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const int col = LC * k + cg;
+                double v = a[i][k];
+                if (FIRST) v = row > col ? v : (row == col ? 1.0 : 0.0);
+                cb[(row - c0) * LDP + col] = v;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            double vv[JB];
+#pragma unroll
+            for (int b = 0; b < JB; ++b) {
+                const int col = 16 * b + p;
+                vv[b] = col < NP ? cb[(4 * s + q) * LDP + col] : 0.0;
+            }
+#pragma unroll
+            for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+                for (int jb = ib; jb < JB; ++jb) acc[ib][jb] = mfma16x16x4(vv[ib], vv[jb], acc[ib][jb]);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+        for (int jb = ib; jb < JB; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * ib + q + 4 * r, col = 16 * jb + p;
+                if (row < col && col < NP) Gs[row + col * NP] = acc[ib][jb][r];
+            }
+    __builtin_amdgcn_wave_barrier();
 }
 
 // T of H_0 ... H_{NP-1} = I - V T V^T from the Gram entries G(c, j) = v_c^T v_j
@@ -210,52 +339,52 @@ __device__ __forceinline__ void build_T(const double* Gs, const double* taus, do
     }
 }
 
-// Tile load/store in the L layout.  The per-lane part of the address
+// Tile load/store in the factor layout.  The per-lane part of the address
 // (row rg, column cg) is one loop-invariant offset; the rest is uniform, so the
 // compiler does not keep one address per element alive across the chain.
-template <int NP, int RL>
-__device__ __forceinline__ void load_tile(double (&a)[RL][NP / 4], const double* __restrict__ tb, int64_t lda,
+template <int NP, int RL, int LC>
+__device__ __forceinline__ void load_tile(double (&a)[RL][NP / LC], const double* tb, int64_t lda,
                                           int64_t lane_off, int64_t valid, int n, int rg, int cg)
 {
-    constexpr int KC = NP / 4, MT = 16 * RL;
+    constexpr int KC = NP / LC, LR = 64 / LC, MT = LR * RL;
     if (valid == MT && n == NP) {
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
-            const double* cb = tb + (int64_t)(4 * k) * lda + lane_off;
+            const double* cb = tb + (int64_t)(LC * k) * lda + lane_off;
 #pragma unroll
-            for (int i = 0; i < RL; ++i) a[i][k] = cb[16 * i];
+            for (int i = 0; i < RL; ++i) a[i][k] = cb[LR * i];
         }
     } else {
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
-            const double* cb = tb + (int64_t)(4 * k) * lda + lane_off;
-            const bool cv = 4 * k + cg < n;
+            const double* cb = tb + (int64_t)(LC * k) * lda + lane_off;
+            const bool cv = LC * k + cg < n;
 #pragma unroll
-            for (int i = 0; i < RL; ++i) a[i][k] = (cv && 16 * i + rg < valid) ? cb[16 * i] : 0.0;
+            for (int i = 0; i < RL; ++i) a[i][k] = (cv && LR * i + rg < valid) ? cb[LR * i] : 0.0;
         }
     }
 }
 
-template <int NP, int RL>
-__device__ __forceinline__ void store_tile(const double (&a)[RL][NP / 4], double* __restrict__ tb, int64_t lda,
+template <int NP, int RL, int LC>
+__device__ __forceinline__ void store_tile(const double (&a)[RL][NP / LC], double* tb, int64_t lda,
                                            int64_t lane_off, int64_t valid, int n, int rg, int cg)
 {
-    constexpr int KC = NP / 4, MT = 16 * RL;
+    constexpr int KC = NP / LC, LR = 64 / LC, MT = LR * RL;
     if (valid == MT && n == NP) {
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
-            double* cb = tb + (int64_t)(4 * k) * lda + lane_off;
+            double* cb = tb + (int64_t)(LC * k) * lda + lane_off;
 #pragma unroll
-            for (int i = 0; i < RL; ++i) cb[16 * i] = a[i][k];
+            for (int i = 0; i < RL; ++i) cb[LR * i] = a[i][k];
         }
     } else {
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
-            double* cb = tb + (int64_t)(4 * k) * lda + lane_off;
-            const bool cv = 4 * k + cg < n;
+            double* cb = tb + (int64_t)(LC * k) * lda + lane_off;
+            const bool cv = LC * k + cg < n;
 #pragma unroll
             for (int i = 0; i < RL; ++i)
-                if (cv && 16 * i + rg < valid) cb[16 * i] = a[i][k];
+                if (cv && LR * i + rg < valid) cb[LR * i] = a[i][k];
         }
     }
 }
@@ -264,58 +393,70 @@ __device__ __forceinline__ void store_tile(const double (&a)[RL][NP / 4], double
 // Leaf kernel: one wavefront per leaf, the flat chain over its tiles.
 // --------------------------------------------------------------------------
 template <int NP, bool WANT_Q>
-__global__ void __launch_bounds__(256) k_leaf_factor(const double* A, int64_t lda, double* V, int64_t ldv, int64_t m, int n,
-                                                     int64_t P, int64_t leaf_rows, int64_t f,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_leaf_factor(const double* A, int64_t lda, double* V, int64_t ldv,
+                                                     int64_t m, int n, int64_t P, int64_t leaf_rows, int64_t f,
                                                      double* __restrict__ Ttile, double* __restrict__ Rleaf)
 {
-    constexpr int RL = rows_per_lane(NP), KC = NP / 4, MT = 16 * RL, NT = packed_size(NP);
+    constexpr int LC = col_groups(NP), LR = 64 / LC, MT = tile_rows_for(NP), RL = MT / LR, KC = NP / LC;
+    constexpr int NT = packed_size(NP);
     constexpr int WS = factor_lds_doubles(NP, MT);
     extern __shared__ double smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int cg = lane >> 4, rg = lane & 15;
+    const int cg = lane / LR, rg = lane % LR;
     const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (leaf >= P) return;
     double* Rs = smem + wave * WS;
-    double* Gs = Rs + NP * NP;
-    double* vb = Gs + NP * NP;
-    double* taus = vb + MT;
+    double* Gs = Rs + NP * rs_ld(NP);
+    double* vb = Gs + gram_area(NP);
+    double* taus = vb + LR * vb_stride(RL);
 
     const int64_t row0 = leaf * leaf_rows;
     const int64_t rows = (leaf == P - 1) ? (m - row0) : leaf_rows;
     const int64_t ntl = (rows + MT - 1) / MT;
     const int64_t lane_off = rg + (int64_t)cg * lda;
     const int64_t lane_off_v = rg + (int64_t)cg * ldv;
-    double a[RL][KC];
-    for (int64_t t = 0; t < ntl; ++t) {
-        const int64_t t0 = row0 + t * MT;
-        const int64_t valid = (rows - t * MT) < MT ? (rows - t * MT) : MT;
-        load_tile<NP, RL>(a, A + t0, lda, lane_off, valid, n, rg, cg);
-        if (t == 0) {
-            factor_tile<NP, RL, true, WANT_Q>(a, Rs, Gs, vb, taus, lane);
-            // the tile's top NP rows hold R on and above the diagonal
+    double a[RL][KC], sc[KC];
+    // tile 0 (peeled: a branch between the two factor variants inside the
+    // loop would make the register allocator keep two copies of the tile)
+    {
+        const int64_t valid = rows < MT ? rows : MT;
+        load_tile<NP, RL, LC>(a, A + row0, lda, lane_off, valid, n, rg, cg);
+        factor_tile<NP, RL, LC, true>(a, sc, Rs, vb, taus, lane);
+        // the tile's top NP rows hold R on and above the diagonal
 #pragma unroll
-            for (int i = 0; i < (NP + 15) / 16; ++i) {
-                const int r = 16 * i + rg;
-                if (r < NP) {
+        for (int i = 0; i < (NP + LR - 1) / LR; ++i) {
+            const int r = LR * i + rg;
+            if (r < NP) {
 #pragma unroll
-                    for (int k = 0; k < KC; ++k) {
-                        const int c = 4 * k + cg;
-                        Rs[r + c * NP] = (r <= c) ? a[i][k] : 0.0;
-                    }
+                for (int k = 0; k < KC; ++k) {
+                    const int c = LC * k + cg;
+                    Rs[r + c * rs_ld(NP)] = (r <= c) ? a[i][k] : 0.0;
                 }
             }
-            __builtin_amdgcn_wave_barrier();
-        } else {
-            factor_tile<NP, RL, false, WANT_Q>(a, Rs, Gs, vb, taus, lane);
         }
+        __builtin_amdgcn_wave_barrier();
         if (WANT_Q) {
-            store_tile<NP, RL>(a, V + t0, ldv, lane_off_v, valid, n, rg, cg);
+            scale_tile<NP, RL, LC, true>(a, sc, lane);
+            store_tile<NP, RL, LC>(a, V + row0, ldv, lane_off_v, valid, n, rg, cg);
+            gram_mfma<NP, RL, LC, true>(a, Gs, Gs, lane);
+            build_T<NP>(Gs, taus, Ttile + (leaf * f) * NT, lane);
+        }
+    }
+    for (int64_t t = 1; t < ntl; ++t) {
+        const int64_t t0 = row0 + t * MT;
+        const int64_t valid = (rows - t * MT) < MT ? (rows - t * MT) : MT;
+        load_tile<NP, RL, LC>(a, A + t0, lda, lane_off, valid, n, rg, cg);
+        factor_tile<NP, RL, LC, false>(a, sc, Rs, vb, taus, lane);
+        if (WANT_Q) {
+            scale_tile<NP, RL, LC, false>(a, sc, lane);
+            store_tile<NP, RL, LC>(a, V + t0, ldv, lane_off_v, valid, n, rg, cg);
+            gram_mfma<NP, RL, LC, false>(a, Gs, Gs, lane);
             build_T<NP>(Gs, taus, Ttile + (leaf * f + t) * NT, lane);
         }
     }
     __builtin_amdgcn_wave_barrier();
     double* Ro = Rleaf + leaf * NP * NP;
-    for (int idx = lane; idx < NP * NP; idx += 64) Ro[idx] = Rs[idx];
+    for (int idx = lane; idx < NP * NP; idx += 64) Ro[idx] = Rs[(idx % NP) + (idx / NP) * rs_ld(NP)];
 }
 
 // --------------------------------------------------------------------------
@@ -329,11 +470,14 @@ __global__ void __launch_bounds__(256) k_tree_level(const double* __restrict__ R
                                                     double* __restrict__ Rout, double* __restrict__ Ynode,
                                                     double* __restrict__ Tnode, int64_t cout)
 {
-    constexpr int RLN = (NP + 15) / 16, KC = NP / 4, MTN = 16 * RLN, NT = packed_size(NP);
+    constexpr int LC = col_groups(NP), LR = 64 / LC, KC = NP / LC;
+    // the node tile holds R_b (NP rows), padded with zero rows to whole 16-row
+    // chunks of gram_mfma
+    constexpr int RLN = round16(NP) / LR, MTN = LR * RLN, NT = packed_size(NP);
     constexpr int WS = factor_lds_doubles(NP, MTN);
     extern __shared__ double smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int cg = lane >> 4, rg = lane & 15;
+    const int cg = lane / LR, rg = lane % LR;
     const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (q >= cout) return;
     const int64_t ia = 2 * q, ib = 2 * q + 1;
@@ -344,37 +488,39 @@ __global__ void __launch_bounds__(256) k_tree_level(const double* __restrict__ R
         return;
     }
     double* Rs = smem + wave * WS;
-    double* Gs = Rs + NP * NP;
-    double* vb = Gs + NP * NP;
-    double* taus = vb + MTN;
-    for (int idx = lane; idx < NP * NP; idx += 64) Rs[idx] = Ra[idx];
+    double* Gs = Rs + NP * rs_ld(NP);
+    double* vb = Gs + gram_area(NP);
+    double* taus = vb + LR * vb_stride(RLN);
+    for (int idx = lane; idx < NP * NP; idx += 64) Rs[(idx % NP) + (idx / NP) * rs_ld(NP)] = Ra[idx];
     const double* Rb = Rin + ib * NP * NP;
-    double a[RLN][KC];
+    double a[RLN][KC], sc[KC];
 #pragma unroll
     for (int i = 0; i < RLN; ++i) {
-        const int r = 16 * i + rg;
+        const int r = LR * i + rg;
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
-            const int c = 4 * k + cg;
+            const int c = LC * k + cg;
             a[i][k] = (r < NP) ? Rb[r + c * NP] : 0.0;
         }
     }
     __builtin_amdgcn_wave_barrier();
-    factor_tile<NP, RLN, false, WANT_Q>(a, Rs, Gs, vb, taus, lane);
+    factor_tile<NP, RLN, LC, false>(a, sc, Rs, vb, taus, lane);
     if (WANT_Q) {
+        scale_tile<NP, RLN, LC, false>(a, sc, lane);
+        gram_mfma<NP, RLN, LC, false>(a, Gs, Gs, lane);
         build_T<NP>(Gs, taus, Tnode + q * NT, lane);
         double* Y = Ynode + q * NP * NP;
 #pragma unroll
         for (int i = 0; i < RLN; ++i) {
-            const int r = 16 * i + rg;
+            const int r = LR * i + rg;
             if (r < NP) {
 #pragma unroll
-                for (int k = 0; k < KC; ++k) Y[r + (4 * k + cg) * NP] = a[i][k];
+                for (int k = 0; k < KC; ++k) Y[r + (LC * k + cg) * NP] = a[i][k];
             }
         }
     }
     __builtin_amdgcn_wave_barrier();
-    for (int idx = lane; idx < NP * NP; idx += 64) Ro[idx] = Rs[idx];
+    for (int idx = lane; idx < NP * NP; idx += 64) Ro[idx] = Rs[(idx % NP) + (idx / NP) * rs_ld(NP)];
 }
 
 // --------------------------------------------------------------------------
@@ -514,11 +660,11 @@ __global__ void __launch_bounds__(256) k_seed_level(const double* __restrict__ S
 // The products run on the matrix cores; Q may alias V.
 // --------------------------------------------------------------------------
 template <int NP>
-__global__ void __launch_bounds__(256) k_form_q(const double* V, int64_t lda, int64_t m, int n, int64_t P,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_form_q(const double* V, int64_t lda, int64_t m, int n, int64_t P,
                                                 int64_t leaf_rows, int64_t f, const double* __restrict__ Ttile,
                                                 const double* __restrict__ Sleaf, double* Q, int64_t ldq)
 {
-    constexpr int RL = rows_per_lane(NP), KC = NP / 4, MT = 16 * RL;
+    constexpr int MT = tile_rows_for(NP), RL = MT / 16, KC = NP / 4;
     constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, NT = packed_size(NP);
     extern __shared__ double smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -628,7 +774,7 @@ template <int NP>
 hipError_t leaf_factor_np(const Layout& L, const double* A, int64_t lda, double* V, int64_t ldv, double* ws,
                           bool want_q, hipStream_t s)
 {
-    constexpr int MT = 16 * rows_per_lane(NP);
+    constexpr int MT = tile_rows_for(NP);
     const size_t lds = (size_t)L.waves * factor_lds_doubles(NP, MT) * sizeof(double);
     const dim3 grid(grid_for(L.P, L.waves)), block(64 * L.waves);
     if (want_q) {
@@ -646,7 +792,7 @@ hipError_t leaf_factor_np(const Layout& L, const double* A, int64_t lda, double*
 template <int NP>
 hipError_t tree_np(const Layout& L, double* ws, bool want_q, hipStream_t s)
 {
-    constexpr int MTN = 16 * ((NP + 15) / 16);
+    constexpr int MTN = round16(NP);
     const int waves = NP <= 32 ? 4 : 2;  // per-wave LDS grows as NP^2
     const size_t lds = (size_t)waves * factor_lds_doubles(NP, MTN) * sizeof(double);
     for (int l = 1; l <= L.levels; ++l) {
