@@ -65,6 +65,41 @@ def make_input(w: dict, seed: int):
     return A, sig
 
 
+def sources_sha256() -> str:
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    here = os.path.dirname(os.path.abspath(__file__))
+    for f in sorted(glob.glob(os.path.join(here, "paper_0809_2407_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(m: int, n: int, kernel: str):
+    """HBM bytes (read + write) of one launch of `kernel` from the committed
+    rocprofv3 byte-counter summary under profiles/, or None when no summary
+    matches this workload and the current kernel sources."""
+    import glob
+    import re
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    sha = sources_sha256()
+    for f in sorted(glob.glob(os.path.join(here, "profiles", "*.md"))):
+        text = open(f).read()
+        for blk in re.findall(r"```json\n(.*?)\n```", text, flags=re.S):
+            try:
+                d = json.loads(blk)
+            except ValueError:
+                continue
+            if d.get("workload_m") == m and d.get("workload_n") == n and d.get("sources_sha256") == sha:
+                k = d.get("kernels", {}).get(kernel)
+                if k:
+                    return k["read_bytes"] + k["write_bytes"]
+    return None
+
+
 def cpu_baseline(A_dev, info: dict, sample_rows: int, mode: str):
     """The oracle as it stands, on the first sample_rows rows of the same input,
     on the host cores (tree of the same shape: same leaf and tile rows)."""
@@ -161,7 +196,8 @@ def main(argv=None) -> int:
     dom_ms = ph[dom][0] / max(1, ph[dom][1])
     achieved = phase_bytes[dom] / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(m, n, dom) if mode == "rq" else None,
+                "kernel": dom,
                 "kernel_ms": dom_ms, "bytes_per_launch": phase_bytes[dom]}
     path_bytes = (32.0 if mode == "rq" else 8.0) * m * n
     t_roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), path_bytes / (HBM_PEAK_GBS * 1e9))
