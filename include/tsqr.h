@@ -129,8 +129,10 @@ tsqr_status tsqr_form_q(tsqr_plan p, const double* A_factored, int64_t lda, doub
  * factor of the tree (the reduction of Sec. 4.1).  Rows 0..n-1 become D Q^T B
  * with Q the thin factor returned by tsqr_form_q; rows n..m-1 hold coordinates
  * of B in the tree's basis of the orthogonal complement (they depend on the
- * tree).  Errors: -1 p, -2 A NULL, -3 lda < m, -4 k < 0, -5 B NULL, -6 ldb < m;
- * 4 when the plan holds no factorisation with reflectors. */
+ * tree).  k = 0 returns 0 at once (B may then be NULL).  Right-hand sides are
+ * processed 32 at a time.  Errors: -1 p, -2 A NULL, -3 lda < m, -4 k < 0,
+ * -5 B NULL, -6 ldb < m; 4 when the plan holds no factorisation with
+ * reflectors. */
 tsqr_status tsqr_apply_qt(tsqr_plan p, const double* A_factored, int64_t lda, int64_t k, double* B,
                           int64_t ldb);
 

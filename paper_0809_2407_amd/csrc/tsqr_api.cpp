@@ -304,11 +304,14 @@ tsqr_status tsqr_apply_qt(tsqr_plan p, const double* A_factored, int64_t lda, in
     if (!A_factored) return -2;
     if (lda < p->L.m) return -3;
     if (k < 0) return -4;
+    if (k == 0) return 0;  // nothing to apply; B may be NULL
     if (!B) return -5;
     if (ldb < p->L.m) return -6;
     if (p->state != 1) return 4;
-    if (k == 0) return 0;
-    return 3;
+    hipError_t e = run_phase(p, TSQR_PHASE_APPLY, [&] {
+        return tsqr::launch_apply_qt(p->L, A_factored, lda, k, B, ldb, p->ws, p->stream);
+    });
+    return hip_status(e);
 }
 
 tsqr_status tsqr_plan_info(tsqr_plan p, tsqr_info* out)

@@ -18,6 +18,9 @@ hipError_t seeds_np(const Layout& L, double* ws, hipStream_t s);
 template <int NP>
 hipError_t form_q_np(const Layout& L, const double* A, int64_t lda, double* ws, double* Q, int64_t ldq,
                      hipStream_t s);
+template <int NP>
+hipError_t apply_qt_np(const Layout& L, const double* A, int64_t lda, int64_t k, double* B, int64_t ldb,
+                       double* ws, hipStream_t s);
 
 #ifdef TSQR_ONLY_NP
 // experiment builds: a single column count
@@ -82,6 +85,14 @@ hipError_t launch_form_q(const Layout& L, const double* A, int64_t lda, double* 
                          hipStream_t s)
 {
 #define CALL(NP) form_q_np<NP>(L, A, lda, ws, Q, ldq, s)
+    TSQR_NP_SWITCH(L.np, CALL)
+#undef CALL
+}
+
+hipError_t launch_apply_qt(const Layout& L, const double* A, int64_t lda, int64_t k, double* B, int64_t ldb,
+                           double* ws, hipStream_t s)
+{
+#define CALL(NP) apply_qt_np<NP>(L, A, lda, k, B, ldb, ws, s)
     TSQR_NP_SWITCH(L.np, CALL)
 #undef CALL
 }

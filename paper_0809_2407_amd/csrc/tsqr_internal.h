@@ -59,5 +59,7 @@ hipError_t launch_root(const Layout& L, double* ws, double* R, int64_t ldr, hipS
 hipError_t launch_seeds(const Layout& L, double* ws, hipStream_t s);
 hipError_t launch_form_q(const Layout& L, const double* A, int64_t lda, double* ws, double* Q, int64_t ldq,
                          hipStream_t s);
+hipError_t launch_apply_qt(const Layout& L, const double* A, int64_t lda, int64_t k, double* B, int64_t ldb,
+                           double* ws, hipStream_t s);
 
 }  // namespace tsqr

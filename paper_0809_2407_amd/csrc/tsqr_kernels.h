@@ -760,6 +760,258 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     }
 }
 
+// --------------------------------------------------------------------------
+// Q^T B, the reduction of Sec. 4.1, for up to kApplyCols right-hand sides per
+// launch.  An NP x kApplyCols block X (C, W, D) lives in registers as
+// Xr[s][jb] = X(4s + q, 16jb + p) with q = lane / 16, p = lane % 16: the
+// B-operand layout of the f64 16x16x4 op, in which products with T^T and Y1
+// come back.
+// --------------------------------------------------------------------------
+constexpr int kApplyCols = 32;
+
+// X = T^T D, T packed upper triangular (T^T(r, c) = T(c, r), c <= r).
+template <int NP>
+__device__ __forceinline__ void trit_times_regs(const double* __restrict__ T,
+                                                const double (&Dr)[round16(NP) / 4][kApplyCols / 16],
+                                                double (&Xr)[round16(NP) / 4][kApplyCols / 16], int lane)
+{
+    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, JK = kApplyCols / 16;
+    const int q = lane >> 4, p = lane & 15;
+#pragma unroll
+    for (int ib = 0; ib < JB; ++ib) {
+        double tv[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int r = 16 * ib + p, c = 4 * s + q;  // A(r, c) = T(c, r)
+            tv[s] = (c <= r && r < NP) ? T[r * (r + 1) / 2 + c] : 0.0;
+        }
+#pragma unroll
+        for (int jb = 0; jb < JK; ++jb) {
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) acc = mfma16x16x4(tv[s], Dr[s][jb], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Xr[4 * ib + r][jb] = acc[r];
+        }
+    }
+}
+
+// Leaf chain: tile 0 B_0 <- B_0 - V_0 T_0^T V_0^T B_0 and C = its top NP rows;
+// tile k > 0: D = C + Y_k^T B_k, X = T_k^T D, C <- C - X, B_k <- B_k - Y_k X.
+// C goes back to the leaf's top rows at the end.  W = Y^T B contracts over
+// rows, so Y and B are read with rows on the lane-group index for it; the
+// update reads Y with rows on the lanes of a group (the layout of the leaf
+// kernel), which makes B^T - X^T Y^T land in B's own coalesced layout.
+template <int NP>
+__global__ void __launch_bounds__(256) k_apply_leaf(const double* __restrict__ V, int64_t lda, double* B,
+                                                    int64_t ldb, int kc, int64_t m, int n, int64_t P,
+                                                    int64_t leaf_rows, int64_t f, const double* __restrict__ Ttile)
+{
+    constexpr int MT = tile_rows_for(NP), NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
+    constexpr int JK = kApplyCols / 16, KC4 = NP / 4, NT = packed_size(NP);
+    extern __shared__ double smem[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = lane >> 4, p = lane & 15;
+    const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (leaf >= P) return;
+    double* cbuf = smem + wave * NP * kApplyCols;  // top NP rows of the updated tile 0
+
+    const int64_t row0 = leaf * leaf_rows;
+    const int64_t rows = (leaf == P - 1) ? (m - row0) : leaf_rows;
+    const int64_t ntl = (rows + MT - 1) / MT;
+    double Cr[KS][JK];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int jb = 0; jb < JK; ++jb) Cr[s][jb] = 0.0;
+    for (int64_t t = 0; t < ntl; ++t) {
+        const int64_t t0 = row0 + t * MT;
+        const int64_t valid = (rows - t * MT) < MT ? (rows - t * MT) : MT;
+        const bool first = t == 0;
+        // W = Y^T B_t
+        dbl4 wacc[JB][JK];
+#pragma unroll
+        for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < JK; ++jb) wacc[ib][jb] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int s = 0; s < MT / 4; ++s) {
+            const int r = 4 * s + q;
+            const bool rv = r < valid;
+            double yv[JB], bv[JK];
+#pragma unroll
+            for (int b = 0; b < JB; ++b) {
+                const int c = 16 * b + p;
+                double y = (rv && c < n) ? V[t0 + r + (int64_t)c * lda] : 0.0;
+                if (first) y = c < NP ? (r > c ? y : (r == c ? 1.0 : 0.0)) : 0.0;
+                yv[b] = y;
+            }
+#pragma unroll
+            for (int jb = 0; jb < JK; ++jb) {
+                const int c = 16 * jb + p;
+                bv[jb] = (rv && c < kc) ? B[t0 + r + (int64_t)c * ldb] : 0.0;
+            }
+#pragma unroll
+            for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+                for (int jb = 0; jb < JK; ++jb) wacc[ib][jb] = mfma16x16x4(yv[ib], bv[jb], wacc[ib][jb]);
+        }
+        double Dr[KS][JK], Xr[KS][JK];
+#pragma unroll
+        for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int jb = 0; jb < JK; ++jb)
+                    Dr[4 * ib + r][jb] = (first ? 0.0 : Cr[4 * ib + r][jb]) + wacc[ib][jb][r];
+        trit_times_regs<NP>(Ttile + (leaf * f + t) * NT, Dr, Xr, lane);
+        if (!first) {
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int jb = 0; jb < JK; ++jb) Cr[s][jb] -= Xr[s][jb];
+        }
+        // B_t <- B_t - Y X, 16 rows at a time (B^T - X^T Y^T on the matrix cores)
+#pragma unroll 2
+        for (int i = 0; i < MT / 16; ++i) {
+            const int rl = 16 * i + p;
+            const bool rv = rl < valid;
+            const int64_t row = t0 + rl;
+            double y[KC4];
+#pragma unroll
+            for (int s = 0; s < KC4; ++s) {
+                const int c = 4 * s + q;
+                double v = (rv && c < n) ? V[row + (int64_t)c * lda] : 0.0;
+                if (first && rl < NP) v = rl > c ? v : (rl == c ? 1.0 : 0.0);
+                y[s] = v;
+            }
+#pragma unroll
+            for (int jb = 0; jb < JK; ++jb) {
+                dbl4 acc;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = 16 * jb + q + 4 * r;
+                    acc[r] = (rv && c < kc) ? B[row + (int64_t)c * ldb] : 0.0;
+                }
+#pragma unroll
+                for (int s = 0; s < KC4; ++s) acc = mfma16x16x4(-Xr[s][jb], y[s], acc);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = 16 * jb + q + 4 * r;
+                    if (rv && c < kc) B[row + (int64_t)c * ldb] = acc[r];
+                    if (first && rl < NP) cbuf[rl * kApplyCols + c] = acc[r];
+                }
+            }
+        }
+        if (first) {
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int jb = 0; jb < JK; ++jb) {
+                    const int r = 4 * s + q, c = 16 * jb + p;
+                    Cr[s][jb] = r < NP ? cbuf[r * kApplyCols + c] : 0.0;
+                }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int jb = 0; jb < JK; ++jb) {
+            const int r = 4 * s + q, c = 16 * jb + p;
+            if (r < NP && r < rows && c < kc) B[row0 + r + (int64_t)c * ldb] = Cr[s][jb];
+        }
+}
+
+// One tree level of Q^T B: node q stacks the tops C_a (first leaf of its top
+// child) and C_b (first leaf of its bottom child): D = C_a + Y1^T C_b,
+// X = T^T D, C_a <- C_a - X, C_b <- C_b - Y1 X.
+template <int NP>
+__global__ void __launch_bounds__(256) k_apply_tree(double* B, int64_t ldb, int kc, int64_t leaf_rows,
+                                                    int64_t span, const double* __restrict__ Ynode,
+                                                    const double* __restrict__ Tnode, int64_t cin, int64_t cout)
+{
+    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, JK = kApplyCols / 16, NT = packed_size(NP);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = lane >> 4, p = lane & 15;
+    const int64_t nq = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (nq >= cout) return;
+    const int64_t ia = 2 * nq, ib = 2 * nq + 1;
+    if (ib >= cin) return;  // passes up unchanged
+    double* Ba = B + ia * span * leaf_rows;
+    double* Bb = B + ib * span * leaf_rows;
+    double Car[KS][JK], Cbr[KS][JK], Dr[KS][JK], Xr[KS][JK];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int jb = 0; jb < JK; ++jb) {
+            const int r = 4 * s + q, c = 16 * jb + p;
+            const bool v = r < NP && c < kc;
+            Car[s][jb] = v ? Ba[r + (int64_t)c * ldb] : 0.0;
+            Cbr[s][jb] = v ? Bb[r + (int64_t)c * ldb] : 0.0;
+        }
+    const double* Y = Ynode + nq * NP * NP;
+    // D = C_a + Y1^T C_b
+#pragma unroll
+    for (int ibk = 0; ibk < JB; ++ibk) {
+        double yt[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int r = 4 * s + q, kk = 16 * ibk + p;  // A(kk, r) = Y1(r, kk)
+            yt[s] = (r < NP && kk < NP) ? Y[r + kk * NP] : 0.0;
+        }
+#pragma unroll
+        for (int jb = 0; jb < JK; ++jb) {
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) acc = mfma16x16x4(yt[s], Cbr[s][jb], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Dr[4 * ibk + r][jb] = Car[4 * ibk + r][jb] + acc[r];
+        }
+    }
+    trit_times_regs<NP>(Tnode + nq * NT, Dr, Xr, lane);
+    // C_b -= Y1 X
+#pragma unroll
+    for (int ibk = 0; ibk < JB; ++ibk) {
+        double yv[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int r = 16 * ibk + p, kk = 4 * s + q;
+            yv[s] = (r < NP && kk < NP) ? Y[r + kk * NP] : 0.0;
+        }
+#pragma unroll
+        for (int jb = 0; jb < JK; ++jb) {
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) acc = mfma16x16x4(yv[s], Xr[s][jb], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Cbr[4 * ibk + r][jb] -= acc[r];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int jb = 0; jb < JK; ++jb) {
+            const int r = 4 * s + q, c = 16 * jb + p;
+            if (r < NP && c < kc) {
+                Ba[r + (int64_t)c * ldb] = Car[s][jb] - Xr[s][jb];
+                Bb[r + (int64_t)c * ldb] = Cbr[s][jb];
+            }
+        }
+}
+
+// Root of Q^T B: rows 0..n-1 <- D rows 0..n-1.
+template <int NP>
+__global__ void __launch_bounds__(256) k_apply_signs(double* B, int64_t ldb, int n, int kc,
+                                                     const double* __restrict__ Dsig)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * kc) return;
+    const int r = idx % n, c = idx / n;
+    B[r + (int64_t)c * ldb] *= Dsig[r];
+}
+
 template <typename K>
 void allow_lds(K kernel, size_t bytes)
 {
@@ -847,6 +1099,36 @@ hipError_t form_q_np(const Layout& L, const double* A, int64_t lda, double* ws, 
     return hipGetLastError();
 }
 
+template <int NP>
+hipError_t apply_qt_np(const Layout& L, const double* A, int64_t lda, int64_t k, double* B, int64_t ldb, double* ws,
+                       hipStream_t s)
+{
+    const size_t lds = (size_t)L.waves * NP * kApplyCols * sizeof(double);
+    allow_lds(k_apply_leaf<NP>, lds);
+    for (int64_t c0 = 0; c0 < k; c0 += kApplyCols) {
+        const int kc = (int)((k - c0) < kApplyCols ? (k - c0) : kApplyCols);
+        double* Bc = B + c0 * ldb;
+        hipLaunchKernelGGL((k_apply_leaf<NP>), dim3(grid_for(L.P, L.waves)), dim3(64 * L.waves), lds, s, A, lda,
+                           Bc, ldb, kc, L.m, (int)L.n, L.P, L.leaf_rows, L.f, ws + L.off_T);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        int64_t span = 1;
+        for (int l = 1; l <= L.levels; ++l) {
+            hipLaunchKernelGGL((k_apply_tree<NP>), dim3(grid_for(L.count[l], 4)), dim3(256), 0, s, Bc, ldb, kc,
+                               L.leaf_rows, span, ws + L.off_Y[l], ws + L.off_TN[l], L.count[l - 1], L.count[l]);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            span *= 2;
+        }
+        const int cnt = (int)L.n * kc;
+        hipLaunchKernelGGL((k_apply_signs<NP>), dim3((cnt + 255) / 256), dim3(256), 0, s, Bc, ldb, (int)L.n, kc,
+                           ws + L.off_D);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace detail
 
 template <int NP>
@@ -875,6 +1157,12 @@ hipError_t form_q_np(const Layout& L, const double* A, int64_t lda, double* ws, 
                      hipStream_t s)
 {
     return detail::form_q_np<NP>(L, A, lda, ws, Q, ldq, s);
+}
+template <int NP>
+hipError_t apply_qt_np(const Layout& L, const double* A, int64_t lda, int64_t k, double* B, int64_t ldb,
+                       double* ws, hipStream_t s)
+{
+    return detail::apply_qt_np<NP>(L, A, lda, k, B, ldb, ws, s);
 }
 
 }  // namespace tsqr
