@@ -30,6 +30,13 @@ WORKLOADS = {
     "tsqr_fp64_r_m16777216_n32_kappa1e12": dict(m=1 << 24, n=32, decades=12.0, mode="r"),
     # m = 4096, n = 16, A iid N(0,1), 8 leaves of 512 rows, binary tree over them
     "tsqr_fp64_rq_m4096_n16_gaussian": dict(m=4096, n=16, decades=None, mode="rq", leaf_rows=512),
+    # m = 2^24, n = 64, sigma log-spaced 1 .. 1e-6 (the matrix of the mixed-precision comparison)
+    "tsqr_fp64_rq_m16777216_n64_kappa1e6": dict(m=1 << 24, n=64, decades=6.0, mode="rq"),
+    "tsqr_fp64_r_m16777216_n64_kappa1e6": dict(m=1 << 24, n=64, decades=6.0, mode="r"),
+    # s-step monomial basis of the 2-D 5-point Laplacian on a 2048 x 2048 grid (n = 17), R + Q,
+    # then Q^T applied to 32 iid N(0,1) right-hand sides
+    "tsqr_fp64_rq_qtb_krylov_m4194304_n17_k32": dict(m=2048 * 2048, n=17, decades=None, mode="rq",
+                                                     krylov=(2048, 16), rhs=32),
 }
 DEFAULT = "tsqr_fp64_rq_m16777216_n32_kappa1e12"
 
@@ -55,7 +62,11 @@ def make_input(w: dict, seed: int):
     from paper_0809_2407_amd import tsqr as T
 
     m, n = w["m"], w["n"]
-    if w["decades"] is None:
+    if "krylov" in w:
+        g, s_ = w["krylov"]
+        A = T.to_colmajor(torch.from_numpy(synth.krylov_basis(g, s_, seed)))
+        sig = None
+    elif w["decades"] is None:
         A = T.to_colmajor(torch.from_numpy(synth.gaussian(m, n, seed)))
         sig = None
     else:
@@ -160,11 +171,20 @@ def main(argv=None) -> int:
     V = T.colmajor(m, n) if mode == "rq" else None
     Q = T.colmajor(m, n) if mode == "rq" else None
     R = T.colmajor(n, n)
+    k_rhs = w.get("rhs", 0)
+    if k_rhs:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(args.seed + 1)
+        B0 = torch.randn((k_rhs, m), generator=g, device="cuda", dtype=torch.float64).t()
+        B = T.colmajor(m, k_rhs)
 
     def step():
         plan.factor_into(A, V, R)
         if mode == "rq":
             plan.form_q(V, Q)
+        if k_rhs:
+            B.copy_(B0)
+            plan.apply_qt(V, B)
 
     if args.calibrate_copy:
         Cdst = T.colmajor(m, n)
@@ -189,6 +209,8 @@ def main(argv=None) -> int:
     log(f"timed {args.steps} steps: {ms_step:.4f} ms/step; phases {ph}")
 
     fl = flops_rq(m, n) if mode == "rq" else flops_r(m, n)
+    if k_rhs:
+        fl += 4.0 * m * n * k_rhs  # Q^T B on k columns
     value = fl / (ms_step * 1e-3) / 1e9
     # dominant kernel: the phase with the largest device time
     phase_bytes = {"leaf": (16.0 if mode == "rq" else 8.0) * m * n, "form_q": 16.0 * m * n}
@@ -199,7 +221,7 @@ def main(argv=None) -> int:
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(m, n, dom) if mode == "rq" else None,
                 "kernel": dom,
                 "kernel_ms": dom_ms, "bytes_per_launch": phase_bytes[dom]}
-    path_bytes = (32.0 if mode == "rq" else 8.0) * m * n
+    path_bytes = (32.0 if mode == "rq" else 8.0) * m * n + (8.0 * m * n + 16.0 * m * k_rhs if k_rhs else 0.0)
     t_roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), path_bytes / (HBM_PEAK_GBS * 1e9))
 
     result = {
@@ -225,7 +247,14 @@ def main(argv=None) -> int:
             E = torch.addmm(A, Q, R, alpha=-1.0)
             bwd = float(torch.linalg.norm(E) / nA)
             del E
-            G = Q.t() @ Q
+            # Q^T Q as a sum over row blocks: one GEMM with k = m accumulates
+            # an error near sqrt(m) eps, above the orthogonality being measured
+            nb = 4096
+            while m % nb:
+                nb //= 2
+            Qb = Q.t().reshape(n, nb, m // nb).permute(1, 0, 2).contiguous()
+            G = torch.bmm(Qb, Qb.transpose(1, 2).contiguous()).sum(dim=0)
+            del Qb
             orth = float(torch.linalg.norm(G - torch.eye(n, dtype=G.dtype, device=G.device)))
         result["accuracy"] = {"backward_error": bwd, "orthogonality": orth, "bound": 20 * n * 2.0 ** -53}
         log(f"accuracy {result['accuracy']}")

@@ -26,6 +26,7 @@
 // factor of H_0 ... H_{n-1} = I - V T V^T (the YT representation of Sec. 3.2).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 #include "tsqr_internal.h"
@@ -67,6 +68,42 @@ __device__ __forceinline__ double readlane_d(double v, int lane)
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
     return __hiloint2double(hi, lo);
 }
+
+// An opaque copy of a value: per-lane offsets derived from it inside a loop are
+// recomputed there (a few integer ops) instead of being hoisted out of the
+// loop and kept live, or spilled, across it.
+__device__ __forceinline__ int opaque(int x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// The wavefront's index in its block, as a wave-uniform (scalar) value, so
+// that addresses derived from it stay in scalar registers.
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// Loads and stores at a wave-uniform base plus a 32-bit per-lane byte offset,
+// the form that addresses through a scalar base register.
+__device__ __forceinline__ double ld_at(const double* base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ __forceinline__ void st_at(double* base, uint32_t byte_off, double v)
+{
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+__device__ __forceinline__ double ld_at(const double* base, uint64_t byte_off)
+{
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ __forceinline__ void st_at(double* base, uint64_t byte_off, double v)
+{
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+// True when the byte offset of element (15, 3) of a 16 x 4 block with leading
+// dimension ld fits in 32 bits, so 32-bit per-lane offsets can be used.
+inline bool lane_offsets_fit_32(int64_t ld) { return (uint64_t)(15 + 3 * ld) * 8u < (1ull << 32); }
 
 // 1/p to about one ulp: hardware reciprocal and two Newton steps.
 __device__ __forceinline__ double recip(double p)
@@ -401,7 +438,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     constexpr int NT = packed_size(NP);
     constexpr int WS = factor_lds_doubles(NP, MT);
     extern __shared__ double smem[];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = wave_index(), lane = threadIdx.x & 63;
     const int cg = lane / LR, rg = lane % LR;
     const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (leaf >= P) return;
@@ -476,7 +513,7 @@ __global__ void __launch_bounds__(256) k_tree_level(const double* __restrict__ R
     constexpr int RLN = round16(NP) / LR, MTN = LR * RLN, NT = packed_size(NP);
     constexpr int WS = factor_lds_doubles(NP, MTN);
     extern __shared__ double smem[];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = wave_index(), lane = threadIdx.x & 63;
     const int cg = lane / LR, rg = lane % LR;
     const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (q >= cout) return;
@@ -544,57 +581,66 @@ __global__ void __launch_bounds__(64) k_root(const double* __restrict__ Rroot, i
 // Matrix-core product Z = T S for NP x NP operands: T packed upper triangular in
 // global memory, S in registers with Sr[s][jb] = S(4s + cg, 16jb + rg).  The
 // result comes back in the same register layout.
-template <int NP>
-__device__ __forceinline__ void tri_times_regs(const double* __restrict__ T, const double (&Sr)[round16(NP) / 4][round16(NP) / 16],
-                                               double (&Zr)[round16(NP) / 4][round16(NP) / 16], int lane)
+template <int NP, int JW = round16(NP) / 16>
+__device__ __forceinline__ void tri_times_regs(const double* __restrict__ T, const double (&Sr)[round16(NP) / 4][JW],
+                                               double (&Zr)[round16(NP) / 4][JW], int lane)
 {
     constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
-    const int cg = lane >> 4, rg = lane & 15;
+    const int ln = opaque(lane);
+    const int cg = ln >> 4, rg = ln & 15;
 #pragma unroll
     for (int ib = 0; ib < JB; ++ib) {
+        // T(16 ib + p, 4 s + q) vanishes for 4 s + 3 < 16 ib: those k-steps are skipped
         double tv[KS];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
+        for (int s = 4 * ib; s < KS; ++s) {
             const int r = 16 * ib + rg, c = 4 * s + cg;
-            tv[s] = (r <= c && c < NP) ? T[c * (c + 1) / 2 + r] : 0.0;
+            const bool ok = r <= c && c < NP;
+            // unconditional load, in bounds
+            const double v = ld_at(T, (uint32_t)(ok ? c * (c + 1) / 2 + r : 0) * 8u);
+            tv[s] = ok ? v : 0.0;
         }
 #pragma unroll
-        for (int jb = 0; jb < JB; ++jb) {
+        for (int jb = 0; jb < JW; ++jb) {
             dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int s = 0; s < KS; ++s) acc = mfma16x16x4(tv[s], Sr[s][jb], acc);
+            for (int s = 4 * ib; s < KS; ++s) acc = mfma16x16x4(tv[s], Sr[s][jb], acc);
 #pragma unroll
             for (int r = 0; r < 4; ++r) Zr[4 * ib + r][jb] = acc[r];
         }
     }
 }
 
-template <int NP>
-__device__ __forceinline__ void load_seed(const double* __restrict__ S, double (&Sr)[round16(NP) / 4][round16(NP) / 16],
-                                          int lane)
+// Columns 16 j0 .. 16 (j0 + JW) - 1 of an NP x NP seed (column-major, leading
+// dimension NP) into / out of the register layout above.
+template <int NP, int JW = round16(NP) / 16>
+__device__ __forceinline__ void load_seed(const double* __restrict__ S, double (&Sr)[round16(NP) / 4][JW], int lane,
+                                          int j0 = 0)
 {
-    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
+    constexpr int NPB = round16(NP), KS = NPB / 4;
     const int cg = lane >> 4, rg = lane & 15;
 #pragma unroll
     for (int s = 0; s < KS; ++s)
 #pragma unroll
-        for (int jb = 0; jb < JB; ++jb) {
-            const int r = 4 * s + cg, c = 16 * jb + rg;
-            Sr[s][jb] = (r < NP && c < NP) ? S[r + c * NP] : 0.0;
+        for (int jb = 0; jb < JW; ++jb) {
+            const int r = 4 * s + cg, c = 16 * (j0 + jb) + rg;
+            const bool ok = r < NP && c < NP;
+            const double v = S[ok ? r + c * NP : 0];
+            Sr[s][jb] = ok ? v : 0.0;
         }
 }
 
-template <int NP>
-__device__ __forceinline__ void store_seed(double* __restrict__ S, const double (&Sr)[round16(NP) / 4][round16(NP) / 16],
-                                           int lane)
+template <int NP, int JW = round16(NP) / 16>
+__device__ __forceinline__ void store_seed(double* __restrict__ S, const double (&Sr)[round16(NP) / 4][JW], int lane,
+                                           int j0 = 0)
 {
-    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
+    constexpr int NPB = round16(NP), KS = NPB / 4;
     const int cg = lane >> 4, rg = lane & 15;
 #pragma unroll
     for (int s = 0; s < KS; ++s)
 #pragma unroll
-        for (int jb = 0; jb < JB; ++jb) {
-            const int r = 4 * s + cg, c = 16 * jb + rg;
+        for (int jb = 0; jb < JW; ++jb) {
+            const int r = 4 * s + cg, c = 16 * (j0 + jb) + rg;
             if (r < NP && c < NP) S[r + c * NP] = Sr[s][jb];
         }
 }
@@ -610,7 +656,7 @@ __global__ void __launch_bounds__(256) k_seed_level(const double* __restrict__ S
                                                     double* __restrict__ Sc, int64_t cout)
 {
     constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, NT = packed_size(NP);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = wave_index(), lane = threadIdx.x & 63;
     const int cg = lane >> 4, rg = lane & 15;
     const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (q >= cout) return;
@@ -654,105 +700,147 @@ __global__ void __launch_bounds__(256) k_seed_level(const double* __restrict__ S
 }
 
 // --------------------------------------------------------------------------
-// Q kernel: one wavefront per leaf, its chain replayed from the last tile to
-// the first.  Tile k > 0: Z = T_k S_k, Q_k = -Y_k Z, S_{k-1} = S_k - Z.
+// Q kernel: a leaf's chain replayed from the last tile to the first.
+// Tile k > 0: Z = T_k S_k, Q_k = -Y_k Z, S_{k-1} = S_k - Z.
 // Tile 0: W = V_top^T S_0, Z = T_0 W, Q_0 = [S_0; 0] - V_0 Z.
-// The products run on the matrix cores; Q may alias V.
+// Every step acts on the seed's columns independently, so a leaf may be split
+// over several wavefronts, each owning 16 JW of the seed's (and Q's) columns;
+// they read the same V tiles at about the same time, the second read coming
+// from L2.  The products run on the matrix cores; Q may alias V.
 // --------------------------------------------------------------------------
-template <int NP>
+constexpr int fq_col_blocks(int np) { return round16(np) / 16 <= 3 ? round16(np) / 16 : 1; }
+
+template <int NP, bool WIDE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_form_q(const double* V, int64_t lda, int64_t m, int n, int64_t P,
                                                 int64_t leaf_rows, int64_t f, const double* __restrict__ Ttile,
                                                 const double* __restrict__ Sleaf, double* Q, int64_t ldq)
 {
     constexpr int MT = tile_rows_for(NP), RL = MT / 16, KC = NP / 4;
     constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, NT = packed_size(NP);
+    constexpr int JW = fq_col_blocks(NP), SPLIT = JB / JW;
+    constexpr int FQU = NP > 48 ? 1 : 2;  // row blocks in flight; more spills at the widest tiles
+    static_assert(JB % JW == 0, "column window must divide the padded width");
     extern __shared__ double smem[];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = wave_index(), lane = threadIdx.x & 63;
     const int cg = lane >> 4, rg = lane & 15;
-    const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    const int64_t leaf = gw / SPLIT;
+    const int j0 = (int)(gw % SPLIT) * JW;
     if (leaf >= P) return;
-    double* S0 = smem + wave * NPB * NPB;  // S_0 staged for the [S_0; 0] term
+    // the seed window lives in LDS between tile steps (each lane owns the
+    // elements of its register layout); at tile 0 it is S_0 for the [S_0; 0] term
+    double* Ss = smem + wave * NPB * 16 * JW;
 
     const int64_t row0 = leaf * leaf_rows;
     const int64_t rows = (leaf == P - 1) ? (m - row0) : leaf_rows;
     const int64_t ntl = (rows + MT - 1) / MT;
-    double Sr[KS][JB], Zr[KS][JB];
-    load_seed<NP>(Sleaf + leaf * NP * NP, Sr, lane);
+    {
+        double Sr[KS][JW];
+        load_seed<NP, JW>(Sleaf + leaf * NP * NP, Sr, lane, j0);
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int jb = 0; jb < JW; ++jb) Ss[4 * s + cg + (16 * jb + rg) * NPB] = Sr[s][jb];
+    }
     for (int64_t t = ntl - 1; t >= 0; --t) {
+        const int ln = opaque(lane);
+        const int lcg = ln >> 4, lrg = ln & 15;
+        // per-lane byte offsets within a 16 x 4 block of V and of Q (64-bit
+        // only for leading dimensions past 32-bit reach)
+        using off_t = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+        const off_t lane_v = (off_t)(lrg + lcg * lda) * 8u;
+        const off_t lane_q = (off_t)(lrg + lcg * ldq) * 8u;
+        // last column group: columns past n read column n - 1 instead (then zeroed)
+        const int cl_last = 4 * (KC - 1) + lcg < n ? lcg : n - 1 - 4 * (KC - 1);
+        const off_t lane_vl = (off_t)(lrg + cl_last * lda) * 8u;
         const double* T = Ttile + (leaf * f + t) * NT;
         const int64_t t0 = row0 + t * MT;
         const int64_t valid = (rows - t * MT) < MT ? (rows - t * MT) : MT;
-        if (t > 0) {
-            tri_times_regs<NP>(T, Sr, Zr, lane);
+        double Zr[KS][JW];
+        {
+            double Sr[KS][JW];
 #pragma unroll
             for (int s = 0; s < KS; ++s)
 #pragma unroll
-                for (int jb = 0; jb < JB; ++jb) Sr[s][jb] -= Zr[s][jb];
-        } else {
-            // W = V_top^T S_0 with V_top the unit lower triangle of the tile's top rows
-            double Wr[KS][JB];
+                for (int jb = 0; jb < JW; ++jb) Sr[s][jb] = Ss[4 * s + cg + (16 * jb + rg) * NPB];
+            if (t > 0) {
+                tri_times_regs<NP, JW>(T, Sr, Zr, lane);
 #pragma unroll
-            for (int ib = 0; ib < JB; ++ib) {
-                double vt[KS];
+                for (int s = 0; s < KS; ++s)
 #pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    const int r = 4 * s + cg, c = 16 * ib + rg;  // V_top(r, c)
-                    double v = 0.0;
-                    if (r < NP && c < NP) {
-                        if (r == c) v = 1.0;
-                        else if (r > c && r < valid && c < n) v = V[t0 + r + (int64_t)c * lda];
+                    for (int jb = 0; jb < JW; ++jb) Ss[4 * s + cg + (16 * jb + rg) * NPB] = Sr[s][jb] - Zr[s][jb];
+            } else {
+                // W = V_top^T S_0 with V_top the unit lower triangle of the tile's top rows
+                double Wr[KS][JW];
+#pragma unroll
+                for (int ib = 0; ib < JB; ++ib) {
+                    // V_top(4 s + q, 16 ib + p) vanishes for 4 s + 3 < 16 ib
+                    double vt[KS];
+#pragma unroll
+                    for (int s = 4 * ib; s < KS; ++s) {
+                        const int r = 4 * s + cg, c = 16 * ib + rg;  // V_top(r, c)
+                        const bool ok = r > c && r < valid && c < n;
+                        const double v = V[t0 + (ok ? r + (int64_t)c * lda : 0)];
+                        vt[s] = ok ? v : (r == c && r < NP ? 1.0 : 0.0);
                     }
-                    vt[s] = v;
+#pragma unroll
+                    for (int jb = 0; jb < JW; ++jb) {
+                        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int s = 4 * ib; s < KS; ++s) acc = mfma16x16x4(vt[s], Sr[s][jb], acc);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) Wr[4 * ib + r][jb] = acc[r];
+                    }
                 }
-#pragma unroll
-                for (int jb = 0; jb < JB; ++jb) {
-                    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int s = 0; s < KS; ++s) acc = mfma16x16x4(vt[s], Sr[s][jb], acc);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) Wr[4 * ib + r][jb] = acc[r];
-                }
+                tri_times_regs<NP, JW>(T, Wr, Zr, lane);
+                __builtin_amdgcn_wave_barrier();  // S_0 is read across lanes below
             }
-            tri_times_regs<NP>(T, Wr, Zr, lane);
-#pragma unroll
-            for (int s = 0; s < KS; ++s)
-#pragma unroll
-                for (int jb = 0; jb < JB; ++jb) {
-                    const int r = 4 * s + cg, c = 16 * jb + rg;
-                    S0[r + c * NPB] = Sr[s][jb];
-                }
-            __builtin_amdgcn_wave_barrier();
         }
         // expansion Q_t = [S_0; 0] (t == 0 only) - V_t Z, 16 rows at a time
-        double nz[KC][JB];
-#pragma unroll
-        for (int k = 0; k < KC; ++k)
-#pragma unroll
-            for (int jb = 0; jb < JB; ++jb) nz[k][jb] = -Zr[k][jb];
-#pragma unroll 2
+        const bool full = valid == MT;  // every row of the tile exists
+#pragma unroll FQU
         for (int i = 0; i < RL; ++i) {
-            const int rl = 16 * i + rg;
+            const int rl = 16 * i + lrg;
             const bool rv = rl < valid;
-            const int64_t row = t0 + rl;
+            const double* vb = V + t0 + 16 * i;
             double y[KC];
+            if (full) {
+                // only the last group of four columns can reach past n (NP = n rounded up to 4)
 #pragma unroll
-            for (int k = 0; k < KC; ++k) {
-                const int c = 4 * k + cg;
-                y[k] = (rv && c < n) ? V[row + (int64_t)c * lda] : 0.0;
-                if (t == 0 && rl < NP) y[k] = (rl > c) ? y[k] : (rl == c ? 1.0 : 0.0);
+                for (int k = 0; k < KC - 1; ++k) y[k] = ld_at(vb + (int64_t)(4 * k) * lda, lane_v);
+                const double yl = ld_at(vb + (int64_t)(4 * (KC - 1)) * lda, lane_vl);
+                y[KC - 1] = 4 * (KC - 1) + lcg < n ? yl : 0.0;
+            } else {
+                // ragged tile or padded columns: clamp to an element that exists, then zero
+                const int rc = rv ? rl : (int)valid - 1;
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const int c = 4 * k + lcg, cc = c < n ? c : n - 1;
+                    const double v = V[t0 + rc + (int64_t)cc * lda];
+                    y[k] = (rv && c < n) ? v : 0.0;
+                }
             }
+            if (t == 0) {
 #pragma unroll
-            for (int jb = 0; jb < JB; ++jb) {
+                for (int k = 0; k < KC; ++k) {
+                    const int c = 4 * k + lcg;
+                    if (rl < NP) y[k] = (rl > c) ? y[k] : (rl == c ? 1.0 : 0.0);
+                }
+            }
+            double* qb = Q + t0 + 16 * i + (int64_t)(16 * j0) * ldq;
+#pragma unroll
+            for (int jb = 0; jb < JW; ++jb) {
                 dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int k = 0; k < KC; ++k) acc = mfma16x16x4(nz[k][jb], y[k], acc);
+                for (int k = 0; k < KC; ++k) acc = mfma16x16x4(Zr[k][jb], y[k], acc);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int c = 16 * jb + cg + 4 * r;
-                    if (rv && c < n) {
-                        double v = acc[r];
-                        if (t == 0 && rl < NP) v += S0[rl + c * NPB];
-                        Q[row + (int64_t)c * ldq] = v;
+                    const int cl = 16 * jb + lcg + 4 * r, c = 16 * j0 + cl;
+                    // the window spans round16(NP) columns: those at or past n are never stored
+                    if (c < n && (full || rv)) {
+                        double v = -acc[r];
+                        if (t == 0 && rl < NP) v += Ss[rl + cl * NPB];
+                        st_at(qb + (int64_t)(16 * jb + 4 * r) * ldq, lane_q, v);
                     }
                 }
             }
@@ -810,7 +898,7 @@ __global__ void __launch_bounds__(256) k_apply_leaf(const double* __restrict__ V
     constexpr int MT = tile_rows_for(NP), NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
     constexpr int JK = kApplyCols / 16, KC4 = NP / 4, NT = packed_size(NP);
     extern __shared__ double smem[];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = wave_index(), lane = threadIdx.x & 63;
     const int q = lane >> 4, p = lane & 15;
     const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (leaf >= P) return;
@@ -933,7 +1021,7 @@ __global__ void __launch_bounds__(256) k_apply_tree(double* B, int64_t ldb, int 
                                                     const double* __restrict__ Tnode, int64_t cin, int64_t cout)
 {
     constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, JK = kApplyCols / 16, NT = packed_size(NP);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = wave_index(), lane = threadIdx.x & 63;
     const int q = lane >> 4, p = lane & 15;
     const int64_t nq = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (nq >= cout) return;
@@ -1090,12 +1178,18 @@ template <int NP>
 hipError_t form_q_np(const Layout& L, const double* A, int64_t lda, double* ws, double* Q, int64_t ldq,
                      hipStream_t s)
 {
-    constexpr int NPB = round16(NP);
-    const size_t lds = (size_t)L.waves * NPB * NPB * sizeof(double);
-    const dim3 grid(grid_for(L.P, L.waves)), block(64 * L.waves);
-    allow_lds(k_form_q<NP>, lds);
-    hipLaunchKernelGGL((k_form_q<NP>), grid, block, lds, s, A, lda, L.m, (int)L.n, L.P, L.leaf_rows, L.f,
-                       ws + L.off_T, ws + L.off_S[0], Q, ldq);
+    constexpr int NPB = round16(NP), JW = fq_col_blocks(NP), SPLIT = NPB / 16 / JW;
+    const size_t lds = (size_t)L.waves * NPB * 16 * JW * sizeof(double);
+    const dim3 grid(grid_for(L.P * SPLIT, L.waves)), block(64 * L.waves);
+    if (lane_offsets_fit_32(lda) && lane_offsets_fit_32(ldq)) {
+        allow_lds(k_form_q<NP, false>, lds);
+        hipLaunchKernelGGL((k_form_q<NP, false>), grid, block, lds, s, A, lda, L.m, (int)L.n, L.P, L.leaf_rows,
+                           L.f, ws + L.off_T, ws + L.off_S[0], Q, ldq);
+    } else {
+        allow_lds(k_form_q<NP, true>, lds);
+        hipLaunchKernelGGL((k_form_q<NP, true>), grid, block, lds, s, A, lda, L.m, (int)L.n, L.P, L.leaf_rows,
+                           L.f, ws + L.off_T, ws + L.off_S[0], Q, ldq);
+    }
     return hipGetLastError();
 }
 

@@ -154,3 +154,43 @@ def test_call_order_errors():
             p.form_q(A)
         assert e.value.status == 4
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("m,n", [(3000, 17), (4100, 24), (2500, 40), (1500, 64), (777, 3)])
+def test_writes_stay_inside_the_outputs(m, n):
+    """V, Q and B sit inside larger buffers filled with a sentinel: every
+    element outside the m x n (m x k) operands keeps it.  Widths that are not
+    a multiple of 16 exercise the padded column windows of the kernels."""
+    torch = need_gpu()
+    from paper_0809_2407_amd import tsqr as T
+
+    A = synth.gaussian(m, n, seed=600 + n)
+    k, pad_r, pad_c = 7, 5, 9
+    sentinel = -12345.0
+
+    def guarded(rows, cols):
+        buf = torch.full((cols + pad_c, rows + pad_r), sentinel, dtype=torch.float64, device="cuda")
+        return buf, buf.t()[:rows, :cols]  # column-major view, ld = rows + pad_r
+
+    def outside_untouched(buf, rows, cols):
+        h = buf.cpu().numpy()  # (cols + pad_c, ld)
+        mask = np.ones_like(h, dtype=bool)
+        mask[:cols, :rows] = False
+        return bool(np.all(h[mask] == sentinel))
+
+    Ad = T.to_colmajor(torch.from_numpy(A))
+    Vbuf, V = guarded(m, n)
+    Qbuf, Q = guarded(m, n)
+    Bbuf, B = guarded(m, k)
+    B.copy_(torch.from_numpy(synth.gaussian(m, k, seed=601)))
+    announce(f"guard regions {m}x{n}")
+    with T.Plan(m, n) as p:
+        R = p.factor_into(Ad, V)
+        p.form_q(V, Q)
+        p.apply_qt(V, B)
+        torch.cuda.synchronize()
+    assert outside_untouched(Vbuf, m, n)
+    assert outside_untouched(Qbuf, m, n)
+    assert outside_untouched(Bbuf, m, k)
+    Qh, Rh = Q.cpu().numpy(), R.cpu().numpy()
+    assert backward_error(A, Qh, Rh) <= fp64_bound(n)
