@@ -33,6 +33,9 @@ WORKLOADS = {
     # m = 2^24, n = 64, sigma log-spaced 1 .. 1e-6 (the matrix of the mixed-precision comparison)
     "tsqr_fp64_rq_m16777216_n64_kappa1e6": dict(m=1 << 24, n=64, decades=6.0, mode="rq"),
     "tsqr_fp64_r_m16777216_n64_kappa1e6": dict(m=1 << 24, n=64, decades=6.0, mode="r"),
+    # the same matrix on the mixed-precision path (FP32 first pass, FP64 second pass)
+    "tsqr_mixed_rq_m16777216_n64_kappa1e6": dict(m=1 << 24, n=64, decades=6.0, mode="rq", precision="mixed"),
+    "tsqr_mixed_rq_m16777216_n32_kappa1e12": dict(m=1 << 24, n=32, decades=12.0, mode="rq", precision="mixed"),
     # s-step monomial basis of the 2-D 5-point Laplacian on a 2048 x 2048 grid (n = 17), R + Q,
     # then Q^T applied to 32 iid N(0,1) right-hand sides
     "tsqr_fp64_rq_qtb_krylov_m4194304_n17_k32": dict(m=2048 * 2048, n=17, decades=None, mode="rq",
@@ -165,10 +168,12 @@ def main(argv=None) -> int:
     m, n, mode = w["m"], w["n"], w["mode"]
     log(f"workload {args.workload}: generating input")
     A, sig = make_input(w, args.seed)
-    plan = T.Plan(m, n, leaf_rows=w.get("leaf_rows", 0), want_q=(mode == "rq"))
+    mixed = w.get("precision", "fp64") == "mixed"
+    plan = T.Plan(m, n, precision="mixed" if mixed else "fp64", leaf_rows=w.get("leaf_rows", 0),
+                  want_q=(mode == "rq"))
     info = plan.info()
     log(f"plan: {info}")
-    V = T.colmajor(m, n) if mode == "rq" else None
+    V = T.colmajor(m, n) if mode == "rq" and not mixed else None
     Q = T.colmajor(m, n) if mode == "rq" else None
     R = T.colmajor(n, n)
     k_rhs = w.get("rhs", 0)
@@ -179,7 +184,7 @@ def main(argv=None) -> int:
         B = T.colmajor(m, k_rhs)
 
     def step():
-        plan.factor_into(A, V, R)
+        plan.factor_into(A, V, R)  # a MIXED plan keeps its reflectors itself (V is None)
         if mode == "rq":
             plan.form_q(V, Q)
         if k_rhs:
@@ -213,22 +218,29 @@ def main(argv=None) -> int:
         fl += 4.0 * m * n * k_rhs  # Q^T B on k columns
     value = fl / (ms_step * 1e-3) / 1e9
     # dominant kernel: the phase with the largest device time
-    phase_bytes = {"leaf": (16.0 if mode == "rq" else 8.0) * m * n, "form_q": 16.0 * m * n}
+    if mixed:
+        # A read (FP64) + V32 written; V32 read + Q1 written; Q1 read (Gram); Q1 read + Q written (FP64)
+        phase_bytes = {"leaf": (12.0 if mode == "rq" else 8.0) * m * n, "q1": 8.0 * m * n,
+                       "reorth": 4.0 * m * n, "form_q": 12.0 * m * n}
+    else:
+        phase_bytes = {"leaf": (16.0 if mode == "rq" else 8.0) * m * n, "form_q": 16.0 * m * n}
     dom = max(phase_bytes, key=lambda k: ph[k][0] / max(1, ph[k][1]) if ph[k][1] else 0.0)
     dom_ms = ph[dom][0] / max(1, ph[dom][1])
     achieved = phase_bytes[dom] / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(m, n, dom) if mode == "rq" else None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(m, n, dom) if mode == "rq" and not mixed else None,
                 "kernel": dom,
                 "kernel_ms": dom_ms, "bytes_per_launch": phase_bytes[dom]}
     path_bytes = (32.0 if mode == "rq" else 8.0) * m * n + (8.0 * m * n + 16.0 * m * k_rhs if k_rhs else 0.0)
+    if mixed and mode == "rq":
+        path_bytes = 36.0 * m * n  # the byte model of the mixed path with its Gram pass unfused
     t_roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), path_bytes / (HBM_PEAK_GBS * 1e9))
 
     result = {
         "metric": "TSQR R+Q GFLOP/s & % roofline; mixed/batched vs FP64 at stated backward error",
         "value": value, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f32+f64" if mixed else "f64", "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "mode": mode,
                    "sigma": None if sig is None else f"logspace(0,-{w['decades']:g},{n})",
                    "seed": args.seed, "tree": {1: "binary", 2: "flat", 3: "hybrid"}.get(info["tree"], "auto"),

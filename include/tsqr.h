@@ -40,6 +40,20 @@ extern "C" {
 
 typedef int tsqr_status;
 
+/* Arithmetic of a plan.
+ * FP64: every step in FP64.
+ * MIXED: a first pass with the tile updates, the compact-WY factors T and the
+ *   explicit Q1 in FP32 (the reflector scalars -- norm, beta, tau -- the running
+ *   triangle R, the tree and the signs stay FP64), then a second pass in FP64
+ *   that re-orthogonalises Q1: G = Q1^T Q1 with FP64 accumulation of the exact
+ *   products of FP32 entries, ||G - I||_F (= ||R2^T R2 - I||_F) as the check,
+ *   G = R2^T R2 by Cholesky, and when the check exceeds 1e-13,
+ *   Q = Q1 R2^{-1} and R = R2 R1.  A is only read; the FP32 reflectors, Q1 and
+ *   the second-pass factors live in the plan.  tsqr_factor runs both passes
+ *   and returns the final R; tsqr_form_q writes the corrected Q; tsqr_apply_qt
+ *   is not available (status 3).  With want_q = 0 only the first pass runs and
+ *   R carries the FP32 pass's accuracy.  The paper fixes no precision beyond
+ *   FP64; this variant is the library's own. */
 typedef enum { TSQR_FP64 = 0, TSQR_MIXED = 1 } tsqr_precision;
 
 /* Reduction-tree shape (Sec. 2 and the list of tree shapes in Sec. 7):
@@ -104,14 +118,15 @@ tsqr_status tsqr_plan_create(tsqr_plan* p, int64_t m, int64_t n, tsqr_precision 
 /* Factor A (m x n, lda >= m).  Writes R (n x n upper triangular, diag >= 0,
  * strictly lower part set to 0) at R[i + j*ldr], ldr >= n.  With want_q the
  * leaf reflectors overwrite A in place (below the diagonal of each tile, LAPACK
- * style, Sec. 4.2) and the tree is kept in the plan (Sec. 4.1); otherwise A is
- * only read.  Errors: -1 p, -2 A NULL, -3 lda < m, -4 R NULL, -5 ldr < n. */
+ * style, Sec. 4.2) and the tree is kept in the plan (Sec. 4.1); otherwise, and
+ * on a MIXED plan, A is only read.  Errors: -1 p, -2 A NULL, -3 lda < m, -4 R NULL, -5 ldr < n. */
 tsqr_status tsqr_factor(tsqr_plan p, double* A, int64_t lda, double* R, int64_t ldr);
 
 /* As tsqr_factor, but A is only read and the reflectors go to V (m x n,
  * ldv >= m); later tsqr_form_q / tsqr_apply_qt calls take V in place of the
  * factored A.  V may equal A with ldv == lda (that is tsqr_factor).  With
- * want_q = 0, V is not written and may be NULL.
+ * want_q = 0, or on a MIXED plan (whose reflectors stay in the plan), V is not
+ * used and may be NULL.
  * Errors: -1 p, -2 A NULL, -3 lda < m, -4 V NULL (want_q), -5 ldv < m or V == A
  * with ldv != lda, -6 R NULL, -7 ldr < n. */
 tsqr_status tsqr_factor_into(tsqr_plan p, const double* A, int64_t lda, double* V, int64_t ldv, double* R,
@@ -119,7 +134,9 @@ tsqr_status tsqr_factor_into(tsqr_plan p, const double* A, int64_t lda, double* 
 
 /* Explicit thin Q (m x n, ldq >= m) from the reflectors tsqr_factor left in A
  * and the plan's tree (the broadcast of Sec. 4.1).  A = Q R with Q^T Q = I.
- * Q may alias A (same pointer and same leading dimension).
+ * Q may alias A (same pointer and same leading dimension).  On a MIXED plan
+ * A_factored and lda are not used (Q may be the original A) and Q is Q1 R2^{-1}
+ * from the second pass.
  * Errors: -1 p, -2 A NULL, -3 lda < m, -4 Q NULL, -5 ldq < m or aliasing with a
  * different leading dimension; 4 when the plan holds no factorisation with
  * reflectors. */
@@ -131,10 +148,17 @@ tsqr_status tsqr_form_q(tsqr_plan p, const double* A_factored, int64_t lda, doub
  * of B in the tree's basis of the orthogonal complement (they depend on the
  * tree).  k = 0 returns 0 at once (B may then be NULL).  Right-hand sides are
  * processed 32 at a time.  Errors: -1 p, -2 A NULL, -3 lda < m, -4 k < 0,
- * -5 B NULL, -6 ldb < m; 4 when the plan holds no factorisation with
- * reflectors. */
+ * -5 B NULL, -6 ldb < m; 3 on a MIXED plan; 4 when the plan holds no
+ * factorisation with reflectors. */
 tsqr_status tsqr_apply_qt(tsqr_plan p, const double* A_factored, int64_t lda, int64_t k, double* B,
                           int64_t ldb);
+
+/* MIXED plans: copy the first-pass Q1 (m x n FP32, ldq1 >= m, device memory)
+ * as it was before the second pass corrected it, e.g. to check the plan's
+ * orth_estimate against ||Q1^T Q1 - I||_F.  Asynchronous on the plan's stream.
+ * Errors: -1 p, -2 Q1 NULL, -3 ldq1 < m; 3 for an FP64 plan; 4 when the plan
+ * holds no factorisation with Q. */
+tsqr_status tsqr_mixed_q1(tsqr_plan p, float* Q1, int64_t ldq1);
 
 /* What tsqr_plan_create would choose for these arguments, without allocating
  * anything or touching a device (workspace_bytes tells the device memory a
@@ -155,6 +179,8 @@ typedef enum {
     TSQR_PHASE_SEEDS = 3,   /* top-down seed descent of tsqr_form_q */
     TSQR_PHASE_FORM_Q = 4,  /* per-tile Q expansion of tsqr_form_q */
     TSQR_PHASE_APPLY = 5,   /* tsqr_apply_qt */
+    TSQR_PHASE_Q1 = 6,      /* MIXED: the FP32 first-pass Q1 (inside tsqr_factor) */
+    TSQR_PHASE_REORTH = 7,  /* MIXED: second pass -- Gram, check, Cholesky, R = R2 R1 */
     TSQR_NUM_PHASES = 8
 } tsqr_phase;
 

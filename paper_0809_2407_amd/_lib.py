@@ -33,12 +33,12 @@ class TsqrTimings(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("calls", i64 * 8)]
 
 
-PHASES = ["leaf", "tree", "root", "seeds", "form_q", "apply_qt"]
+PHASES = ["leaf", "tree", "root", "seeds", "form_q", "apply_qt", "q1", "reorth"]
 
 EXPORTED = [
     "tsqr_plan_create", "tsqr_plan_query", "tsqr_factor", "tsqr_factor_into", "tsqr_form_q", "tsqr_apply_qt",
     "tsqr_plan_info", "tsqr_plan_profile", "tsqr_plan_timings", "tsqr_plan_destroy", "tsqr_status_string",
-    "tsqr_version",
+    "tsqr_version", "tsqr_mixed_q1",
 ]
 
 _lib = None
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
     lib.tsqr_status_string.restype = ctypes.c_char_p
     lib.tsqr_version.argtypes = []
     lib.tsqr_version.restype = ctypes.c_int
+    lib.tsqr_mixed_q1.argtypes = [P, ctypes.c_void_p, i64]
+    lib.tsqr_mixed_q1.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -13,15 +13,17 @@
 
 namespace tsqr {
 
-bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves)
+bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves,
+                 bool mixed)
 {
     if (n < 1 || n > kMaxN || m < n) return false;
     L = Layout();
     L.m = m;
     L.n = n;
+    L.mixed = mixed;
     L.np = (int)((n + 3) / 4 * 4);
     L.npb = (int)((n + 15) / 16 * 16);
-    L.mt = tile_rows_for(L.np);
+    L.mt = mixed ? tile_rows_f32(L.np) : tile_rows_for(L.np);
     L.waves = waves > 0 ? waves : (L.np <= 32 ? 4 : 2);
     const int64_t tiles_total = (m + L.mt - 1) / L.mt;
     int64_t f;
@@ -63,7 +65,7 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
         off += (doubles + 31) / 32 * 32;  // 256-byte alignment
         return o;
     };
-    L.off_T = take(L.ntiles * L.nt);
+    L.off_T = take(mixed ? 0 : L.ntiles * L.nt);
     for (int l = 0; l <= L.levels; ++l) {
         L.off_R[l] = take(L.count[l] * np2);
         L.off_S[l] = take(L.count[l] * np2);
@@ -73,6 +75,23 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
         }
     }
     L.off_D = take(L.np);
+    if (mixed) {
+        const int64_t npb2 = (int64_t)L.npb * L.npb;
+        const int64_t m_tiles = (m + L.mt - 1) / L.mt * L.mt;  // tiles start at multiples of mt
+        L.ld32 = (m_tiles + 63) / 64 * 64;
+        L.off_T32 = take((L.ntiles * L.nt + 1) / 2);
+        L.off_V32 = take((L.ld32 * L.npb + 1) / 2);
+        L.off_Q1 = take((L.ld32 * L.npb + 1) / 2);
+        const int64_t groups = L.ld32 / 64;
+        L.gram_waves = std::min<int64_t>(4096, groups);
+        L.gram_rows = (groups + L.gram_waves - 1) / L.gram_waves * 64;
+        L.off_Gp = take(L.gram_waves * npb2);
+        L.off_Gq = take((L.gram_waves + 63) / 64 * npb2);
+        L.off_G = take(npb2);
+        L.off_R1 = take((int64_t)L.np * L.np);
+        L.off_R2inv = take(npb2);
+        L.off_info = take(2);
+    }
     L.total = off;
     return true;
 }
@@ -147,6 +166,32 @@ hipError_t drain_events(tsqr_plan_s* p)
     return first;
 }
 
+// Mixed precision: FP32 leaf chains, the FP64 tree and root (R1 kept in the
+// workspace when Q is wanted), then Q1 in FP32 and the FP64 second pass, which
+// writes R = R2 R1 to the caller.  R-only plans stop after the first pass.
+tsqr_status factor_mixed(tsqr_plan_s* p, const double* A, int64_t lda, double* R, int64_t ldr)
+{
+    const bool want_q = p->want_q != 0;
+    const tsqr::Layout& L = p->L;
+    hipError_t e = run_phase(p, TSQR_PHASE_LEAF, [&] { return tsqr::launch_mixed_leaf(L, A, lda, p->ws, want_q, p->stream); });
+    if (e == hipSuccess && L.levels > 0)
+        e = run_phase(p, TSQR_PHASE_TREE, [&] { return tsqr::launch_tree(L, p->ws, want_q, p->stream); });
+    if (e == hipSuccess)
+        e = run_phase(p, TSQR_PHASE_ROOT, [&] {
+            return want_q ? tsqr::launch_root(L, p->ws, p->ws + L.off_R1, L.np, p->stream)
+                          : tsqr::launch_root(L, p->ws, R, ldr, p->stream);
+        });
+    if (e == hipSuccess && want_q) {
+        if (L.levels > 0) e = run_phase(p, TSQR_PHASE_SEEDS, [&] { return tsqr::launch_seeds(L, p->ws, p->stream); });
+        if (e == hipSuccess) e = run_phase(p, TSQR_PHASE_Q1, [&] { return tsqr::launch_form_q1(L, p->ws, p->stream); });
+        if (e == hipSuccess)
+            e = run_phase(p, TSQR_PHASE_REORTH, [&] { return tsqr::launch_reorth(L, p->ws, R, ldr, p->stream); });
+    }
+    if (e != hipSuccess) return hip_status(e);
+    p->state = want_q ? 1 : 2;
+    return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -175,7 +220,6 @@ static tsqr_status check_plan_args(int64_t m, int64_t n, tsqr_precision prec, co
     if (n < 1) return -3;
     if (n > tsqr::kMaxN) return 3;
     if (prec != TSQR_FP64 && prec != TSQR_MIXED) return -4;
-    if (prec == TSQR_MIXED) return 3;
     std::memset(&o, 0, sizeof(o));
     o.want_q = 1;
     if (opts) {
@@ -185,7 +229,7 @@ static tsqr_status check_plan_args(int64_t m, int64_t n, tsqr_precision prec, co
         if (o.waves != 0 && o.waves != 1 && o.waves != 2 && o.waves != 4) return -5;
         if (o.want_q != 0 && o.want_q != 1) return -5;
     }
-    if (!tsqr::make_layout(L, m, n, o.leaf_rows, o.flat_len, o.tree, o.waves)) return 3;
+    if (!tsqr::make_layout(L, m, n, o.leaf_rows, o.flat_len, o.tree, o.waves, prec == TSQR_MIXED)) return 3;
     if (o.tile_rows != 0 && o.tile_rows != L.mt) return -5;
     return 0;
 }
@@ -240,6 +284,18 @@ tsqr_status tsqr_plan_create(tsqr_plan* p, int64_t m, int64_t n, tsqr_precision 
         delete P;
         return hip_status(e);
     }
+    if (P->L.mixed) {
+        // the FP32 workspaces are read in whole tiles and 16-column blocks: what
+        // the kernels never write (rows past the last tile, columns past np) stays zero
+        const size_t bytes = (size_t)P->L.ld32 * P->L.npb * sizeof(float);
+        e = hipMemsetAsync(P->ws + P->L.off_V32, 0, bytes, P->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(P->ws + P->L.off_Q1, 0, bytes, P->stream);
+        if (e != hipSuccess) {
+            hipFree(P->ws);
+            delete P;
+            return hip_status(e);
+        }
+    }
     *p = P;
     return 0;
 }
@@ -251,7 +307,7 @@ tsqr_status tsqr_factor_into(tsqr_plan p, const double* A, int64_t lda, double* 
     if (!A) return -2;
     if (lda < p->L.m) return -3;
     const bool want_q = p->want_q != 0;
-    if (want_q) {
+    if (want_q && !p->L.mixed) {
         if (!V) return -4;
         if (ldv < p->L.m) return -5;
         if ((const double*)V == A && ldv != lda) return -5;
@@ -259,6 +315,7 @@ tsqr_status tsqr_factor_into(tsqr_plan p, const double* A, int64_t lda, double* 
     if (!R) return -6;
     if (ldr < p->L.n) return -7;
     p->state = 0;
+    if (p->L.mixed) return factor_mixed(p, A, lda, R, ldr);
     hipError_t e = run_phase(p, TSQR_PHASE_LEAF, [&] {
         return tsqr::launch_leaf_factor(p->L, A, lda, V, want_q ? ldv : lda, p->ws, want_q, p->stream);
     });
@@ -282,6 +339,15 @@ tsqr_status tsqr_factor(tsqr_plan p, double* A, int64_t lda, double* R, int64_t 
 tsqr_status tsqr_form_q(tsqr_plan p, const double* A_factored, int64_t lda, double* Q, int64_t ldq)
 {
     if (!p) return -1;
+    if (p->L.mixed) {
+        // the reflectors live in the plan: A_factored and lda are not used
+        if (!Q) return -4;
+        if (ldq < p->L.m) return -5;
+        if (p->state != 1) return 4;
+        return hip_status(run_phase(p, TSQR_PHASE_FORM_Q, [&] {
+            return tsqr::launch_reorth_q(p->L, p->ws, Q, ldq, p->stream);
+        }));
+    }
     if (!A_factored) return -2;
     if (lda < p->L.m) return -3;
     if (!Q) return -4;
@@ -301,6 +367,7 @@ tsqr_status tsqr_form_q(tsqr_plan p, const double* A_factored, int64_t lda, doub
 tsqr_status tsqr_apply_qt(tsqr_plan p, const double* A_factored, int64_t lda, int64_t k, double* B, int64_t ldb)
 {
     if (!p) return -1;
+    if (p->L.mixed) return 3;  // Q^T B is an FP64 path only
     if (!A_factored) return -2;
     if (lda < p->L.m) return -3;
     if (k < 0) return -4;
@@ -319,7 +386,29 @@ tsqr_status tsqr_plan_info(tsqr_plan p, tsqr_info* out)
     if (!p) return -1;
     if (!out) return -2;
     fill_info(p->L, p->prec, out);
+    if (p->L.mixed && p->state == 1) {
+        // what the second pass measured: waits for the plan's stream
+        double h[2] = {0.0, 0.0};
+        hipError_t e = hipStreamSynchronize(p->stream);
+        if (e == hipSuccess) e = hipMemcpy(h, p->ws + p->L.off_info, sizeof(h), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_status(e);
+        out->orth_estimate = h[0];
+        out->reorth_applied = h[1] != 0.0 ? 1 : 0;
+    }
     return 0;
+}
+
+tsqr_status tsqr_mixed_q1(tsqr_plan p, float* Q1, int64_t ldq1)
+{
+    if (!p) return -1;
+    if (!Q1) return -2;
+    if (ldq1 < p->L.m) return -3;
+    if (!p->L.mixed) return 3;
+    if (p->state != 1) return 4;
+    hipError_t e = hipMemcpy2DAsync(Q1, (size_t)ldq1 * sizeof(float), p->ws + p->L.off_Q1,
+                                    (size_t)p->L.ld32 * sizeof(float), (size_t)p->L.m * sizeof(float),
+                                    (size_t)p->L.n, hipMemcpyDeviceToDevice, p->stream);
+    return hip_status(e);
 }
 
 tsqr_status tsqr_plan_profile(tsqr_plan p, int enable)

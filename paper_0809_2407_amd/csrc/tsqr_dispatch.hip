@@ -6,22 +6,6 @@
 
 namespace tsqr {
 
-template <int NP>
-hipError_t leaf_factor_np(const Layout& L, const double* A, int64_t lda, double* V, int64_t ldv, double* ws,
-                          bool want_q, hipStream_t s);
-template <int NP>
-hipError_t tree_np(const Layout& L, double* ws, bool want_q, hipStream_t s);
-template <int NP>
-hipError_t root_np(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s);
-template <int NP>
-hipError_t seeds_np(const Layout& L, double* ws, hipStream_t s);
-template <int NP>
-hipError_t form_q_np(const Layout& L, const double* A, int64_t lda, double* ws, double* Q, int64_t ldq,
-                     hipStream_t s);
-template <int NP>
-hipError_t apply_qt_np(const Layout& L, const double* A, int64_t lda, int64_t k, double* B, int64_t ldb,
-                       double* ws, hipStream_t s);
-
 #ifdef TSQR_ONLY_NP
 // experiment builds: a single column count
 #define TSQR_NP_SWITCH(np, CALL)                                                                      \
@@ -93,6 +77,34 @@ hipError_t launch_apply_qt(const Layout& L, const double* A, int64_t lda, int64_
                            double* ws, hipStream_t s)
 {
 #define CALL(NP) apply_qt_np<NP>(L, A, lda, k, B, ldb, ws, s)
+    TSQR_NP_SWITCH(L.np, CALL)
+#undef CALL
+}
+
+hipError_t launch_mixed_leaf(const Layout& L, const double* A, int64_t lda, double* ws, bool want_q, hipStream_t s)
+{
+#define CALL(NP) mixed_leaf_np<NP>(L, A, lda, ws, want_q, s)
+    TSQR_NP_SWITCH(L.np, CALL)
+#undef CALL
+}
+
+hipError_t launch_form_q1(const Layout& L, double* ws, hipStream_t s)
+{
+#define CALL(NP) form_q1_np<NP>(L, ws, s)
+    TSQR_NP_SWITCH(L.np, CALL)
+#undef CALL
+}
+
+hipError_t launch_reorth(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s)
+{
+#define CALL(NP) reorth_np<NP>(L, ws, R, ldr, s)
+    TSQR_NP_SWITCH(L.np, CALL)
+#undef CALL
+}
+
+hipError_t launch_reorth_q(const Layout& L, double* ws, double* Q, int64_t ldq, hipStream_t s)
+{
+#define CALL(NP) reorth_q_np<NP>(L, ws, Q, ldq, s)
     TSQR_NP_SWITCH(L.np, CALL)
 #undef CALL
 }

@@ -9,6 +9,9 @@ namespace tsqr {
 
 constexpr int kMaxLevels = 48;
 constexpr int kMaxN = 64;
+// Mixed precision: the second pass corrects Q and R when ||Q1^T Q1 - I||_F
+// exceeds this bound.
+constexpr double kReorthBound = 1e-13;
 
 // Rows per tile for a padded column count np: about 4096 tile elements per
 // wavefront (64 doubles per lane, the register budget of the leaf kernel), a
@@ -19,6 +22,11 @@ __host__ __device__ constexpr int tile_rows_for(int np)
 {
     return (4096 / np / 16 * 16) > 512 ? 512 : (4096 / np / 16 * 16);
 }
+
+// Rows per tile of the mixed-precision leaf kernel, whose tile is held in FP32:
+// twice the FP64 tile in the same registers, at most 1024.
+#define TSQR_F32_TILE_SCALE 1
+__host__ __device__ constexpr int tile_rows_f32(int np) { return TSQR_F32_TILE_SCALE * tile_rows_for(np); }
 
 // Geometry of one TSQR problem: tiles, leaves (flat chains of tiles) and the
 // binary tree over the leaves, plus the offsets of every workspace buffer.
@@ -44,11 +52,23 @@ struct Layout {
     int64_t off_Y[kMaxLevels + 1] = {0};    // node reflectors Y1 (np x np), level >= 1
     int64_t off_TN[kMaxLevels + 1] = {0};   // node T (packed), level >= 1
     int64_t off_D = 0;                      // signs, np
+
+    // mixed precision (FP32 first pass, FP64 second pass)
+    bool mixed = false;
+    int64_t ld32 = 0;                       // rows of V32 and Q1: whole tiles, rounded up to 64
+    int64_t off_T32 = 0;                    // per-tile T in FP32 (packed), ntiles * nt floats
+    int64_t off_V32 = 0, off_Q1 = 0;        // FP32, ld32 x npb, zero past m and past n
+    int64_t gram_waves = 0, gram_rows = 0;  // partial Gram matrices: wavefronts, rows each
+    int64_t off_Gp = 0, off_Gq = 0, off_G = 0;  // partial, group and summed Gram matrices, npb x npb
+    int64_t off_R1 = 0;                     // first-pass R (np x np)
+    int64_t off_R2inv = 0;                  // R2^{-1} (npb x npb)
+    int64_t off_info = 0;                   // ||Q1^T Q1 - I||_F, correction flag
     int64_t total = 0;                      // doubles
 };
 
 // Fills the geometry.  Returns false for an unsupported shape.
-bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves);
+bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves,
+                 bool mixed);
 
 // Kernel launchers (tsqr_kernels.hip).  All enqueue on `s` and return the
 // launch status.
@@ -61,5 +81,36 @@ hipError_t launch_form_q(const Layout& L, const double* A, int64_t lda, double* 
                          hipStream_t s);
 hipError_t launch_apply_qt(const Layout& L, const double* A, int64_t lda, int64_t k, double* B, int64_t ldb,
                            double* ws, hipStream_t s);
+// mixed precision: FP32 leaf chains, FP32 Q1, FP64 second pass (Gram,
+// Cholesky, check, R = R2 R1 to the caller's R) and the corrected Q
+hipError_t launch_mixed_leaf(const Layout& L, const double* A, int64_t lda, double* ws, bool want_q, hipStream_t s);
+hipError_t launch_form_q1(const Layout& L, double* ws, hipStream_t s);
+hipError_t launch_reorth(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s);
+hipError_t launch_reorth_q(const Layout& L, double* ws, double* Q, int64_t ldq, hipStream_t s);
+
+// Per-width launchers behind the dispatch (one instantiation per padded width).
+template <int NP>
+hipError_t leaf_factor_np(const Layout& L, const double* A, int64_t lda, double* V, int64_t ldv, double* ws,
+                          bool want_q, hipStream_t s);
+template <int NP>
+hipError_t tree_np(const Layout& L, double* ws, bool want_q, hipStream_t s);
+template <int NP>
+hipError_t root_np(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s);
+template <int NP>
+hipError_t seeds_np(const Layout& L, double* ws, hipStream_t s);
+template <int NP>
+hipError_t form_q_np(const Layout& L, const double* A, int64_t lda, double* ws, double* Q, int64_t ldq,
+                     hipStream_t s);
+template <int NP>
+hipError_t apply_qt_np(const Layout& L, const double* A, int64_t lda, int64_t k, double* B, int64_t ldb,
+                       double* ws, hipStream_t s);
+template <int NP>
+hipError_t mixed_leaf_np(const Layout& L, const double* A, int64_t lda, double* ws, bool want_q, hipStream_t s);
+template <int NP>
+hipError_t form_q1_np(const Layout& L, double* ws, hipStream_t s);
+template <int NP>
+hipError_t reorth_np(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s);
+template <int NP>
+hipError_t reorth_q_np(const Layout& L, double* ws, double* Q, int64_t ldq, hipStream_t s);
 
 }  // namespace tsqr

@@ -62,6 +62,27 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int LR>
+__device__ __forceinline__ float group_sum(float v)
+{
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0x141>(v);
+    if (LR == 16) v += dpp_move<0x140>(v);
+    return v;
+}
+
+__device__ __forceinline__ float readlane_d(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 __device__ __forceinline__ double readlane_d(double v, int lane)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -84,21 +105,15 @@ __device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstl
 
 // Loads and stores at a wave-uniform base plus a 32-bit per-lane byte offset,
 // the form that addresses through a scalar base register.
-__device__ __forceinline__ double ld_at(const double* base, uint32_t byte_off)
+template <typename E, typename O>
+__device__ __forceinline__ E ld_at(const E* base, O byte_off)
 {
-    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+    return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + byte_off);
 }
-__device__ __forceinline__ void st_at(double* base, uint32_t byte_off, double v)
+template <typename E, typename O>
+__device__ __forceinline__ void st_at(E* base, O byte_off, E v)
 {
-    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
-}
-__device__ __forceinline__ double ld_at(const double* base, uint64_t byte_off)
-{
-    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
-}
-__device__ __forceinline__ void st_at(double* base, uint64_t byte_off, double v)
-{
-    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
+    *reinterpret_cast<E*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
 // True when the byte offset of element (15, 3) of a 16 x 4 block with leading
@@ -130,24 +145,44 @@ __device__ __forceinline__ double sqrt_pos(double x)
 }
 
 __host__ __device__ constexpr int round16(int np) { return (np + 15) / 16 * 16; }
-// Leading dimension of the triangle R in LDS: odd, so that the columns a
-// wavefront touches at once fall into different banks.
-__host__ __device__ constexpr int rs_ld(int np) { return np + 1; }
+// The running triangle R lives in LDS packed by rows: R(r, c), r <= c, at
+// r np - r(r+1)/2 + c (np(np+1)/2 doubles, rounded up to an even count).  The
+// row index is the wave-uniform one in the factorisation, so the per-lane part
+// of an address is the column alone.
+template <int NP>
+__host__ __device__ constexpr int rpk(int r, int c) { return r * NP - r * (r + 1) / 2 + c; }
+__host__ __device__ constexpr int r_area(int np) { return (np * (np + 1) / 2 + 1) / 2 * 2; }
+// The strictly upper Gram entries G(k, j), k < j, packed by columns at
+// j(j-1)/2 + k.
+__host__ __device__ constexpr int gpk(int k, int j) { return j * (j - 1) / 2 + k; }
 // Stride (doubles) between the per-lane segments of the reflector broadcast
 // buffer: s = 2 mod 4, so that 8 or 16 segments read 16 bytes at a time hit
 // disjoint banks, and 16-byte aligned.
 __host__ __device__ constexpr int vb_stride(int rl) { return (rl % 4 == 2) ? rl : (rl % 4 == 3) ? rl + 3 : (rl % 4 == 1) ? rl + 1 : rl + 2; }
+// The same byte stride rule (16 mod 32 bytes) for a broadcast buffer of floats.
+__host__ __device__ constexpr int vb_stride_f(int rl) { return rl % 8 == 4 ? rl : rl + ((12 - rl % 8) % 8); }
+template <typename E>
+__host__ __device__ constexpr int vb_stride_e(int rl) { return sizeof(E) == 8 ? vb_stride(rl) : vb_stride_f(rl); }
 __host__ __device__ constexpr int packed_size(int np) { return np * (np + 1) / 2; }
 // Column groups of the factor layout: 8 when NP is a multiple of 8, else 4.
 __host__ __device__ constexpr int col_groups(int np) { return np % 8 == 0 ? 8 : 4; }
-// The Gram area of the factor kernels also serves as the 16-row chunk buffer of
-// gram_mfma (16 x (np+1) doubles).
-__host__ __device__ constexpr int gram_area(int np) { return np * np > 16 * (np + 1) ? np * np : 16 * (np + 1); }
-// per-wave LDS of the factor kernels: R, Gram entries, reflector broadcast, tau
-__host__ __device__ constexpr int factor_lds_doubles(int np, int tile_rows)
+// The Gram area of the factor kernels (packed strictly upper G) also serves as
+// the 16-row chunk buffer of gram_mfma (16 x (np+1) doubles); R-only kernels
+// have none.
+__host__ __device__ constexpr int gram_area(int np)
 {
-    return np * rs_ld(np) + gram_area(np) + (64 / (np % 8 == 0 ? 8 : 4)) * vb_stride(tile_rows / (64 / (np % 8 == 0 ? 8 : 4))) + np;
+    return ((np * (np - 1) / 2 > 16 * (np + 1) ? np * (np - 1) / 2 : 16 * (np + 1)) + 1) / 2 * 2;
 }
+// per-wave LDS of the factor kernels: R, Gram entries (with Q), reflector broadcast, tau
+template <typename E = double>
+__host__ __device__ constexpr int factor_lds_doubles(int np, int tile_rows, bool want_q)
+{
+    return r_area(np) + (want_q ? gram_area(np) : 0) +
+           ((64 / (np % 8 == 0 ? 8 : 4)) * vb_stride_e<E>(tile_rows / (64 / (np % 8 == 0 ? 8 : 4))) * (int)sizeof(E) + 7) / 8 +
+           np;
+}
+template <typename E>
+__host__ __device__ constexpr int tile_rows_e(int np) { return sizeof(E) == 8 ? tile_rows_for(np) : tile_rows_f32(np); }
 
 // --------------------------------------------------------------------------
 // Householder QR of one tile held in registers.
@@ -171,15 +206,15 @@ __host__ __device__ constexpr int factor_lds_doubles(int np, int tile_rows)
 // The magnitudes are assumed to keep (alpha - beta) * beta within the normal
 // FP64 range (no scaling of the column norm).
 // --------------------------------------------------------------------------
-template <int NP, int RL, int LC, bool FIRST>
-__device__ __forceinline__ void factor_tile(double (&a)[RL][NP / LC], double (&sc)[NP / LC], double* Rs,
-                                            double* vb, double* taus, int lane)
+template <int NP, int RL, int LC, bool FIRST, typename E = double>
+__device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC], double* Rs, E* vb,
+                                            double* taus, int lane)
 {
-    constexpr int KC = NP / LC, LR = 64 / LC, RLD = rs_ld(NP);
+    constexpr int KC = NP / LC, LR = 64 / LC;
     const int cg = lane / LR, rg = lane % LR;
-    double* my_vb = vb + rg * vb_stride(RL);  // this lane's rows of the broadcast reflector
+    E* my_vb = vb + rg * vb_stride_e<E>(RL);  // this lane's rows of the broadcast reflector
 #pragma unroll
-    for (int k = 0; k < KC; ++k) sc[k] = 1.0;
+    for (int k = 0; k < KC; ++k) sc[k] = E(1);
 #pragma unroll
     for (int kb = 0; kb < KC; ++kb) {
         const int ij = (LC * kb) / LR;   // register slot of the pivot rows of this block
@@ -191,15 +226,15 @@ __device__ __forceinline__ void factor_tile(double (&a)[RL][NP / LC], double (&s
             double sp0 = 0.0, sp1 = 0.0;
 #pragma unroll
             for (int i = 0; i < RL; ++i) {
-                double x = a[i][kb];
+                double x = (double)a[i][kb];
                 if (FIRST && LR * i + rg <= j) x = 0.0;
                 if (i & 1) sp1 = fma(x, x, sp1);
                 else sp0 = fma(x, x, sp0);
             }
             const double s = readlane_d(group_sum<LR>(sp0 + sp1), cgj * LR);
             double alpha;
-            if (FIRST) alpha = readlane_d(a[ij][kb], cgj * LR + rg0 + cgj);
-            else alpha = Rs[j + j * RLD];
+            if (FIRST) alpha = (double)readlane_d(a[ij][kb], cgj * LR + rg0 + cgj);
+            else alpha = Rs[rpk<NP>(j, j)];
             // beta = -sgn(alpha) ||x||, tau = (beta - alpha)/beta = -d/beta, scale = 1/d
             // with d = alpha - beta; tau = 0 (H_j = I) when the part below the
             // pivot is zero.  Branch-free: the selects discard the inf/NaN of s == 0.
@@ -217,25 +252,25 @@ __device__ __forceinline__ void factor_tile(double (&a)[RL][NP / LC], double (&s
 #pragma unroll
                 for (int i = 0; i < RL; ++i) {
                     const int row = LR * i + rg;
-                    double v = a[i][kb] * scale;
-                    if (FIRST) v = row > j ? v : (row == j ? 1.0 : 0.0);
+                    E v = a[i][kb] * (E)scale;
+                    if (FIRST) v = row > j ? v : (row == j ? E(1) : E(0));
                     my_vb[i] = v;
                 }
-                sc[kb] = scale;
+                sc[kb] = (E)scale;
             }
             // the other lanes read what the owners wrote: the compiler reasons per
             // lane, so this barrier keeps their loads after the owners' stores
             __builtin_amdgcn_wave_barrier();
-            double vr[RL];
+            E vr[RL];
 #pragma unroll
             for (int i = 0; i < RL; ++i) vr[i] = my_vb[i];
             // dot products of v_j with the trailing columns this lane holds (two chains)
-            double d[KC];
+            E d[KC];
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
-                d[k] = 0.0;
+                d[k] = E(0);
                 if (k < kb) continue;
-                double acc0 = 0.0, acc1 = 0.0;
+                E acc0 = E(0), acc1 = E(0);
 #pragma unroll
                 for (int i = 0; i < RL; ++i) {
                     if (i & 1) acc1 = fma(vr[i], a[i][k], acc1);
@@ -249,21 +284,21 @@ __device__ __forceinline__ void factor_tile(double (&a)[RL][NP / LC], double (&s
                 if (k < kb) continue;
                 // k == kb: only the columns right of the pivot are trailing
                 const bool trailing = (k > kb) || (cg > cgj);
-                double w = d[k];
+                double w = (double)d[k];
                 double rjc = 0.0;
                 if (!FIRST) {
-                    rjc = Rs[j + c * RLD];
+                    rjc = Rs[rpk<NP>(j, c)];
                     w += rjc;
                 }
                 const double tw = trailing ? tau * w : 0.0;
 #pragma unroll
-                for (int i = 0; i < RL; ++i) a[i][k] = fma(-tw, vr[i], a[i][k]);
-                if (!FIRST && rg == 0 && trailing) Rs[j + c * RLD] = rjc - tw;
+                for (int i = 0; i < RL; ++i) a[i][k] = fma(-(E)tw, vr[i], a[i][k]);
+                if (!FIRST && rg == 0 && trailing) Rs[rpk<NP>(j, c)] = rjc - tw;
             }
             if (FIRST) {
-                if (owner && rg == rg0 + cgj) a[ij][kb] = beta;
+                if (owner && rg == rg0 + cgj) a[ij][kb] = (E)beta;
             } else {
-                if (lane == 0) Rs[j + j * RLD] = beta;
+                if (lane == 0) Rs[rpk<NP>(j, j)] = beta;
             }
             if (lane == 0) taus[j] = tau;
         }
@@ -274,8 +309,8 @@ __device__ __forceinline__ void factor_tile(double (&a)[RL][NP / LC], double (&s
 
 // Applies the deferred reflector scales: y = x * sc below the diagonal (FIRST)
 // or in every row (chained tiles).
-template <int NP, int RL, int LC, bool FIRST>
-__device__ __forceinline__ void scale_tile(double (&a)[RL][NP / LC], const double (&sc)[NP / LC], int lane)
+template <int NP, int RL, int LC, bool FIRST, typename E = double>
+__device__ __forceinline__ void scale_tile(E (&a)[RL][NP / LC], const E (&sc)[NP / LC], int lane)
 {
     constexpr int KC = NP / LC, LR = 64 / LC;
     const int cg = lane / LR, rg = lane % LR;
@@ -296,8 +331,8 @@ __device__ __forceinline__ void scale_tile(double (&a)[RL][NP / LC], const doubl
 // V^T (A) and V (B).  Reflectors: FIRST tiles have v_c(r) = 0 above the
 // diagonal and 1 on it; chained tiles [e_c; y_c] contribute y_c^T y_d
 // (c != d).  Writes the strictly upper part G(c, d), c < d, to Gs.
-template <int NP, int RL, int LC, bool FIRST>
-__device__ __forceinline__ void gram_mfma(const double (&a)[RL][NP / LC], double* cb, double* Gs, int lane)
+template <int NP, int RL, int LC, bool FIRST, typename E = double>
+__device__ __forceinline__ void gram_mfma(const E (&a)[RL][NP / LC], double* cb, double* Gs, int lane)
 {
     constexpr int KC = NP / LC, LR = 64 / LC, MT = LR * RL, LDP = NP + 1;
     constexpr int NPB = round16(NP), JB = NPB / 16;
@@ -320,7 +355,7 @@ __device__ __forceinline__ void gram_mfma(const double (&a)[RL][NP / LC], double
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
                 const int col = LC * k + cg;
-                double v = a[i][k];
+                double v = (double)a[i][k];  // products of FP32 entries are exact in FP64
                 if (FIRST) v = row > col ? v : (row == col ? 1.0 : 0.0);
                 cb[(row - c0) * LDP + col] = v;
             }
@@ -348,7 +383,7 @@ __device__ __forceinline__ void gram_mfma(const double (&a)[RL][NP / LC], double
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * ib + q + 4 * r, col = 16 * jb + p;
-                if (row < col && col < NP) Gs[row + col * NP] = acc[ib][jb][r];
+                if (row < col && col < NP) Gs[gpk(row, col)] = acc[ib][jb][r];
             }
     __builtin_amdgcn_wave_barrier();
 }
@@ -356,8 +391,8 @@ __device__ __forceinline__ void gram_mfma(const double (&a)[RL][NP / LC], double
 // T of H_0 ... H_{NP-1} = I - V T V^T from the Gram entries G(c, j) = v_c^T v_j
 // (c < j) and tau: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).
 // Lane t < NP builds row t; T is written packed (column j at j(j+1)/2).
-template <int NP>
-__device__ __forceinline__ void build_T(const double* Gs, const double* taus, double* __restrict__ Tout, int lane)
+template <int NP, typename E = double>
+__device__ __forceinline__ void build_T(const double* Gs, const double* taus, E* __restrict__ Tout, int lane)
 {
     double tr[NP];
 #pragma unroll
@@ -365,12 +400,18 @@ __device__ __forceinline__ void build_T(const double* Gs, const double* taus, do
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         const double tj = taus[j];
-        double acc = 0.0;
+        double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
-        for (int k = 0; k < j; ++k) acc = fma(tr[k], Gs[k + j * NP], acc);
+        for (int k = 0; k < j; ++k) {
+            if (k & 1) acc1 = fma(tr[k], Gs[gpk(k, j)], acc1);
+            else acc0 = fma(tr[k], Gs[gpk(k, j)], acc0);
+            // at most 16 loads of G in flight
+            if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+        }
+        const double acc = acc0 + acc1;
         const double v = (lane < j) ? -tj * acc : (lane == j ? tj : 0.0);
         tr[j] = v;
-        if (lane <= j) Tout[j * (j + 1) / 2 + lane] = v;
+        if (lane <= j) Tout[j * (j + 1) / 2 + lane] = (E)v;
         // keep the loads of later columns from being hoisted all at once
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -379,8 +420,8 @@ __device__ __forceinline__ void build_T(const double* Gs, const double* taus, do
 // Tile load/store in the factor layout.  The per-lane part of the address
 // (row rg, column cg) is one loop-invariant offset; the rest is uniform, so the
 // compiler does not keep one address per element alive across the chain.
-template <int NP, int RL, int LC>
-__device__ __forceinline__ void load_tile(double (&a)[RL][NP / LC], const double* tb, int64_t lda,
+template <int NP, int RL, int LC, typename E = double>
+__device__ __forceinline__ void load_tile(E (&a)[RL][NP / LC], const double* tb, int64_t lda,
                                           int64_t lane_off, int64_t valid, int n, int rg, int cg)
 {
     constexpr int KC = NP / LC, LR = 64 / LC, MT = LR * RL;
@@ -389,7 +430,7 @@ __device__ __forceinline__ void load_tile(double (&a)[RL][NP / LC], const double
         for (int k = 0; k < KC; ++k) {
             const double* cb = tb + (int64_t)(LC * k) * lda + lane_off;
 #pragma unroll
-            for (int i = 0; i < RL; ++i) a[i][k] = cb[LR * i];
+            for (int i = 0; i < RL; ++i) a[i][k] = (E)cb[LR * i];
         }
     } else {
 #pragma unroll
@@ -397,27 +438,27 @@ __device__ __forceinline__ void load_tile(double (&a)[RL][NP / LC], const double
             const double* cb = tb + (int64_t)(LC * k) * lda + lane_off;
             const bool cv = LC * k + cg < n;
 #pragma unroll
-            for (int i = 0; i < RL; ++i) a[i][k] = (cv && LR * i + rg < valid) ? cb[LR * i] : 0.0;
+            for (int i = 0; i < RL; ++i) a[i][k] = (cv && LR * i + rg < valid) ? (E)cb[LR * i] : E(0);
         }
     }
 }
 
-template <int NP, int RL, int LC>
-__device__ __forceinline__ void store_tile(const double (&a)[RL][NP / LC], double* tb, int64_t lda,
+template <int NP, int RL, int LC, typename E = double>
+__device__ __forceinline__ void store_tile(const E (&a)[RL][NP / LC], E* tb, int64_t lda,
                                            int64_t lane_off, int64_t valid, int n, int rg, int cg)
 {
     constexpr int KC = NP / LC, LR = 64 / LC, MT = LR * RL;
     if (valid == MT && n == NP) {
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
-            double* cb = tb + (int64_t)(LC * k) * lda + lane_off;
+            E* cb = tb + (int64_t)(LC * k) * lda + lane_off;
 #pragma unroll
             for (int i = 0; i < RL; ++i) cb[LR * i] = a[i][k];
         }
     } else {
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
-            double* cb = tb + (int64_t)(LC * k) * lda + lane_off;
+            E* cb = tb + (int64_t)(LC * k) * lda + lane_off;
             const bool cv = LC * k + cg < n;
 #pragma unroll
             for (int i = 0; i < RL; ++i)
@@ -429,36 +470,44 @@ __device__ __forceinline__ void store_tile(const double (&a)[RL][NP / LC], doubl
 // --------------------------------------------------------------------------
 // Leaf kernel: one wavefront per leaf, the flat chain over its tiles.
 // --------------------------------------------------------------------------
-template <int NP, bool WANT_Q>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_leaf_factor(const double* A, int64_t lda, double* V, int64_t ldv,
+// E = float is the first pass of the mixed-precision path: the tile is held
+// and updated in FP32 (FP32 dot products over at most 1024 rows, combined
+// pairwise across lanes), while the reflector scalars (norm, beta, tau), the
+// running triangle R and the Gram entries of T stay FP64.  V goes to a
+// workspace of whole tiles (rows past m and columns past n are zeros) and T is
+// rounded to FP32.
+template <int NP, bool WANT_Q, typename E = double>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_leaf_factor(const double* A, int64_t lda, E* V, int64_t ldv,
                                                      int64_t m, int n, int64_t P, int64_t leaf_rows, int64_t f,
-                                                     double* __restrict__ Ttile, double* __restrict__ Rleaf)
+                                                     E* __restrict__ Ttile, double* __restrict__ Rleaf)
 {
-    constexpr int LC = col_groups(NP), LR = 64 / LC, MT = tile_rows_for(NP), RL = MT / LR, KC = NP / LC;
+    constexpr bool MIXED = sizeof(E) == 4;
+    constexpr int LC = col_groups(NP), LR = 64 / LC, MT = tile_rows_e<E>(NP), RL = MT / LR, KC = NP / LC;
     constexpr int NT = packed_size(NP);
-    constexpr int WS = factor_lds_doubles(NP, MT);
+    constexpr int WS = factor_lds_doubles<E>(NP, MT, WANT_Q);
+    constexpr int GA = WANT_Q ? gram_area(NP) : 0;
     extern __shared__ double smem[];
     const int wave = wave_index(), lane = threadIdx.x & 63;
     const int cg = lane / LR, rg = lane % LR;
     const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (leaf >= P) return;
     double* Rs = smem + wave * WS;
-    double* Gs = Rs + NP * rs_ld(NP);
-    double* vb = Gs + gram_area(NP);
-    double* taus = vb + LR * vb_stride(RL);
+    double* Gs = Rs + r_area(NP);
+    E* vb = reinterpret_cast<E*>(Gs + GA);
+    double* taus = Gs + GA + (LR * vb_stride_e<E>(RL) * (int)sizeof(E) + 7) / 8;
 
     const int64_t row0 = leaf * leaf_rows;
     const int64_t rows = (leaf == P - 1) ? (m - row0) : leaf_rows;
     const int64_t ntl = (rows + MT - 1) / MT;
     const int64_t lane_off = rg + (int64_t)cg * lda;
     const int64_t lane_off_v = rg + (int64_t)cg * ldv;
-    double a[RL][KC], sc[KC];
+    E a[RL][KC], sc[KC];
     // tile 0 (peeled: a branch between the two factor variants inside the
     // loop would make the register allocator keep two copies of the tile)
     {
         const int64_t valid = rows < MT ? rows : MT;
-        load_tile<NP, RL, LC>(a, A + row0, lda, lane_off, valid, n, rg, cg);
-        factor_tile<NP, RL, LC, true>(a, sc, Rs, vb, taus, lane);
+        load_tile<NP, RL, LC, E>(a, A + row0, lda, lane_off, valid, n, rg, cg);
+        factor_tile<NP, RL, LC, true, E>(a, sc, Rs, vb, taus, lane);
         // the tile's top NP rows hold R on and above the diagonal
 #pragma unroll
         for (int i = 0; i < (NP + LR - 1) / LR; ++i) {
@@ -467,33 +516,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 #pragma unroll
                 for (int k = 0; k < KC; ++k) {
                     const int c = LC * k + cg;
-                    Rs[r + c * rs_ld(NP)] = (r <= c) ? a[i][k] : 0.0;
+                    if (r <= c) Rs[rpk<NP>(r, c)] = (double)a[i][k];
                 }
             }
         }
         __builtin_amdgcn_wave_barrier();
         if (WANT_Q) {
-            scale_tile<NP, RL, LC, true>(a, sc, lane);
-            store_tile<NP, RL, LC>(a, V + row0, ldv, lane_off_v, valid, n, rg, cg);
-            gram_mfma<NP, RL, LC, true>(a, Gs, Gs, lane);
-            build_T<NP>(Gs, taus, Ttile + (leaf * f) * NT, lane);
+            scale_tile<NP, RL, LC, true, E>(a, sc, lane);
+            // the mixed workspace takes whole tiles (zero rows and columns included)
+            store_tile<NP, RL, LC, E>(a, V + row0, ldv, lane_off_v, MIXED ? MT : valid, MIXED ? NP : n, rg, cg);
+            gram_mfma<NP, RL, LC, true, E>(a, Gs, Gs, lane);
+            build_T<NP, E>(Gs, taus, Ttile + (leaf * f) * NT, lane);
         }
     }
     for (int64_t t = 1; t < ntl; ++t) {
         const int64_t t0 = row0 + t * MT;
         const int64_t valid = (rows - t * MT) < MT ? (rows - t * MT) : MT;
-        load_tile<NP, RL, LC>(a, A + t0, lda, lane_off, valid, n, rg, cg);
-        factor_tile<NP, RL, LC, false>(a, sc, Rs, vb, taus, lane);
+        load_tile<NP, RL, LC, E>(a, A + t0, lda, lane_off, valid, n, rg, cg);
+        factor_tile<NP, RL, LC, false, E>(a, sc, Rs, vb, taus, lane);
         if (WANT_Q) {
-            scale_tile<NP, RL, LC, false>(a, sc, lane);
-            store_tile<NP, RL, LC>(a, V + t0, ldv, lane_off_v, valid, n, rg, cg);
-            gram_mfma<NP, RL, LC, false>(a, Gs, Gs, lane);
-            build_T<NP>(Gs, taus, Ttile + (leaf * f + t) * NT, lane);
+            scale_tile<NP, RL, LC, false, E>(a, sc, lane);
+            store_tile<NP, RL, LC, E>(a, V + t0, ldv, lane_off_v, MIXED ? MT : valid, MIXED ? NP : n, rg, cg);
+            gram_mfma<NP, RL, LC, false, E>(a, Gs, Gs, lane);
+            build_T<NP, E>(Gs, taus, Ttile + (leaf * f + t) * NT, lane);
         }
     }
     __builtin_amdgcn_wave_barrier();
     double* Ro = Rleaf + leaf * NP * NP;
-    for (int idx = lane; idx < NP * NP; idx += 64) Ro[idx] = Rs[(idx % NP) + (idx / NP) * rs_ld(NP)];
+    for (int idx = lane; idx < NP * NP; idx += 64) {
+        const int r = idx % NP, c = idx / NP;
+        Ro[idx] = r <= c ? Rs[rpk<NP>(r, c)] : 0.0;
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -511,7 +564,8 @@ __global__ void __launch_bounds__(256) k_tree_level(const double* __restrict__ R
     // the node tile holds R_b (NP rows), padded with zero rows to whole 16-row
     // chunks of gram_mfma
     constexpr int RLN = round16(NP) / LR, MTN = LR * RLN, NT = packed_size(NP);
-    constexpr int WS = factor_lds_doubles(NP, MTN);
+    constexpr int WS = factor_lds_doubles<double>(NP, MTN, WANT_Q);
+    constexpr int GA = WANT_Q ? gram_area(NP) : 0;
     extern __shared__ double smem[];
     const int wave = wave_index(), lane = threadIdx.x & 63;
     const int cg = lane / LR, rg = lane % LR;
@@ -525,10 +579,13 @@ __global__ void __launch_bounds__(256) k_tree_level(const double* __restrict__ R
         return;
     }
     double* Rs = smem + wave * WS;
-    double* Gs = Rs + NP * rs_ld(NP);
-    double* vb = Gs + gram_area(NP);
+    double* Gs = Rs + r_area(NP);
+    double* vb = Gs + GA;
     double* taus = vb + LR * vb_stride(RLN);
-    for (int idx = lane; idx < NP * NP; idx += 64) Rs[(idx % NP) + (idx / NP) * rs_ld(NP)] = Ra[idx];
+    for (int idx = lane; idx < NP * NP; idx += 64) {
+        const int r = idx % NP, c = idx / NP;
+        if (r <= c) Rs[rpk<NP>(r, c)] = Ra[idx];
+    }
     const double* Rb = Rin + ib * NP * NP;
     double a[RLN][KC], sc[KC];
 #pragma unroll
@@ -557,7 +614,10 @@ __global__ void __launch_bounds__(256) k_tree_level(const double* __restrict__ R
         }
     }
     __builtin_amdgcn_wave_barrier();
-    for (int idx = lane; idx < NP * NP; idx += 64) Ro[idx] = Rs[(idx % NP) + (idx / NP) * rs_ld(NP)];
+    for (int idx = lane; idx < NP * NP; idx += 64) {
+        const int r = idx % NP, c = idx / NP;
+        Ro[idx] = r <= c ? Rs[rpk<NP>(r, c)] : 0.0;
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -578,43 +638,66 @@ __global__ void __launch_bounds__(64) k_root(const double* __restrict__ Rroot, i
     if (lane < NP) Dsig[lane] = Rroot[lane + lane * NP] < 0.0 ? -1.0 : 1.0;
 }
 
-// Matrix-core product Z = T S for NP x NP operands: T packed upper triangular in
-// global memory, S in registers with Sr[s][jb] = S(4s + cg, 16jb + rg).  The
-// result comes back in the same register layout.
-template <int NP, int JW = round16(NP) / 16>
-__device__ __forceinline__ void tri_times_regs(const double* __restrict__ T, const double (&Sr)[round16(NP) / 4][JW],
-                                               double (&Zr)[round16(NP) / 4][JW], int lane)
+// The 16x16x4 matrix-core op in FP64 or FP32.  Both take A(i, k) from lane
+// 16k + i and B(k, j) from lane 16k + j; the output rows differ: lane
+// 16q + p, register r holds D(q + 4r, p) in FP64 and D(4q + r, p) in FP32.
+// A block computed by one product and fed to the next as the B operand keeps
+// the rows it came out with, so slot s of such a register block holds row
+// krow(s, q) = 16 (s / 4) + out_row(q, s % 4), and the A operand of the next
+// product is loaded with the same permutation of its k index.
+template <typename E> struct Mfma;
+template <> struct Mfma<double> {
+    typedef dbl4 acc_t;
+    __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+    __device__ static acc_t mma(double a, double b, acc_t c) { return mfma16x16x4(a, b, c); }
+    __host__ __device__ static constexpr int out_row(int q, int r) { return q + 4 * r; }
+};
+template <> struct Mfma<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    __device__ static acc_t zero() { return acc_t{0.0f, 0.0f, 0.0f, 0.0f}; }
+    __device__ static acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __host__ __device__ static constexpr int out_row(int q, int r) { return 4 * q + r; }
+};
+template <typename E>
+__host__ __device__ constexpr int krow(int s, int q) { return 16 * (s / 4) + Mfma<E>::out_row(q, s % 4); }
+
+// Z = T S with T upper triangular (packed by columns, column j at j(j+1)/2) in
+// global memory, S in registers with Sr[s][jb] = S(krow(s, q), 16 jb + p).
+// The result comes back in the same register layout.
+template <int NP, int JW = round16(NP) / 16, typename E = double>
+__device__ __forceinline__ void tri_times_regs(const E* __restrict__ T, const E (&Sr)[round16(NP) / 4][JW],
+                                               E (&Zr)[round16(NP) / 4][JW], int lane)
 {
     constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
     const int ln = opaque(lane);
     const int cg = ln >> 4, rg = ln & 15;
 #pragma unroll
     for (int ib = 0; ib < JB; ++ib) {
-        // T(16 ib + p, 4 s + q) vanishes for 4 s + 3 < 16 ib: those k-steps are skipped
-        double tv[KS];
+        // T(16 ib + p, c) vanishes for c < 16 ib: those k-steps are skipped
+        E tv[KS];
 #pragma unroll
         for (int s = 4 * ib; s < KS; ++s) {
-            const int r = 16 * ib + rg, c = 4 * s + cg;
+            const int r = 16 * ib + rg, c = krow<E>(s, cg);
             const bool ok = r <= c && c < NP;
             // unconditional load, in bounds
-            const double v = ld_at(T, (uint32_t)(ok ? c * (c + 1) / 2 + r : 0) * 8u);
-            tv[s] = ok ? v : 0.0;
+            const E v = ld_at(T, (uint32_t)(ok ? c * (c + 1) / 2 + r : 0) * (uint32_t)sizeof(E));
+            tv[s] = ok ? v : E(0);
         }
 #pragma unroll
         for (int jb = 0; jb < JW; ++jb) {
-            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+            typename Mfma<E>::acc_t acc = Mfma<E>::zero();
 #pragma unroll
-            for (int s = 4 * ib; s < KS; ++s) acc = mfma16x16x4(tv[s], Sr[s][jb], acc);
+            for (int s = 4 * ib; s < KS; ++s) acc = Mfma<E>::mma(tv[s], Sr[s][jb], acc);
 #pragma unroll
             for (int r = 0; r < 4; ++r) Zr[4 * ib + r][jb] = acc[r];
         }
     }
 }
 
-// Columns 16 j0 .. 16 (j0 + JW) - 1 of an NP x NP seed (column-major, leading
-// dimension NP) into / out of the register layout above.
-template <int NP, int JW = round16(NP) / 16>
-__device__ __forceinline__ void load_seed(const double* __restrict__ S, double (&Sr)[round16(NP) / 4][JW], int lane,
+// Columns 16 j0 .. 16 (j0 + JW) - 1 of an NP x NP FP64 seed (column-major,
+// leading dimension NP) into / out of the register layout above.
+template <int NP, int JW = round16(NP) / 16, typename E = double>
+__device__ __forceinline__ void load_seed(const double* __restrict__ S, E (&Sr)[round16(NP) / 4][JW], int lane,
                                           int j0 = 0)
 {
     constexpr int NPB = round16(NP), KS = NPB / 4;
@@ -623,10 +706,10 @@ __device__ __forceinline__ void load_seed(const double* __restrict__ S, double (
     for (int s = 0; s < KS; ++s)
 #pragma unroll
         for (int jb = 0; jb < JW; ++jb) {
-            const int r = 4 * s + cg, c = 16 * (j0 + jb) + rg;
+            const int r = krow<E>(s, cg), c = 16 * (j0 + jb) + rg;
             const bool ok = r < NP && c < NP;
             const double v = S[ok ? r + c * NP : 0];
-            Sr[s][jb] = ok ? v : 0.0;
+            Sr[s][jb] = ok ? (E)v : E(0);
         }
 }
 
@@ -640,7 +723,7 @@ __device__ __forceinline__ void store_seed(double* __restrict__ S, const double 
     for (int s = 0; s < KS; ++s)
 #pragma unroll
         for (int jb = 0; jb < JW; ++jb) {
-            const int r = 4 * s + cg, c = 16 * (j0 + jb) + rg;
+            const int r = krow<double>(s, cg), c = 16 * (j0 + jb) + rg;
             if (r < NP && c < NP) S[r + c * NP] = Sr[s][jb];
         }
 }
@@ -710,17 +793,29 @@ __global__ void __launch_bounds__(256) k_seed_level(const double* __restrict__ S
 // --------------------------------------------------------------------------
 constexpr int fq_col_blocks(int np) { return round16(np) / 16 <= 3 ? round16(np) / 16 : 1; }
 
-template <int NP, bool WIDE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_form_q(const double* V, int64_t lda, int64_t m, int n, int64_t P,
-                                                int64_t leaf_rows, int64_t f, const double* __restrict__ Ttile,
-                                                const double* __restrict__ Sleaf, double* Q, int64_t ldq)
+// E = float is the first pass of the mixed-precision path: V and T in FP32
+// from the mixed leaf kernel, the FP64 seeds rounded to FP32, products on the
+// FP32 matrix cores, and Q1 written to a workspace of whole tiles and
+// round16(NP) columns (rows past m hold values of zero rows of V; columns past
+// n are zero).  Rows past m and columns past n of V are zeros there too, so
+// no load or store needs a mask.
+template <int NP, bool WIDE, typename E = double>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_form_q(const E* V, int64_t lda, int64_t m, int n, int64_t P,
+                                                int64_t leaf_rows, int64_t f, const E* __restrict__ Ttile,
+                                                const double* __restrict__ Sleaf, E* Q, int64_t ldq)
 {
-    constexpr int MT = tile_rows_for(NP), RL = MT / 16, KC = NP / 4;
+    constexpr bool MIXED = sizeof(E) == 4;
+    constexpr int MT = tile_rows_e<E>(NP), RL = MT / 16, KC = NP / 4;
     constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, NT = packed_size(NP);
+    // k-steps of the expansion: the FP32 permutation of k mixes the columns of
+    // a 16-block, so whole blocks are contracted (their padding is zero)
+    constexpr int KX = MIXED ? KS : KC;
     constexpr int JW = fq_col_blocks(NP), SPLIT = JB / JW;
     constexpr int FQU = NP > 48 ? 1 : 2;  // row blocks in flight; more spills at the widest tiles
     static_assert(JB % JW == 0, "column window must divide the padded width");
-    extern __shared__ double smem[];
+    typedef Mfma<E> MM;
+    extern __shared__ double smem_d[];
+    E* smem = reinterpret_cast<E*>(smem_d);
     const int wave = wave_index(), lane = threadIdx.x & 63;
     const int cg = lane >> 4, rg = lane & 15;
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
@@ -729,70 +824,71 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     if (leaf >= P) return;
     // the seed window lives in LDS between tile steps (each lane owns the
     // elements of its register layout); at tile 0 it is S_0 for the [S_0; 0] term
-    double* Ss = smem + wave * NPB * 16 * JW;
+    E* Ss = smem + wave * NPB * 16 * JW;
 
     const int64_t row0 = leaf * leaf_rows;
     const int64_t rows = (leaf == P - 1) ? (m - row0) : leaf_rows;
     const int64_t ntl = (rows + MT - 1) / MT;
     {
-        double Sr[KS][JW];
-        load_seed<NP, JW>(Sleaf + leaf * NP * NP, Sr, lane, j0);
+        E Sr[KS][JW];
+        load_seed<NP, JW, E>(Sleaf + leaf * NP * NP, Sr, lane, j0);
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
-            for (int jb = 0; jb < JW; ++jb) Ss[4 * s + cg + (16 * jb + rg) * NPB] = Sr[s][jb];
+            for (int jb = 0; jb < JW; ++jb) Ss[krow<E>(s, cg) + (16 * jb + rg) * NPB] = Sr[s][jb];
     }
     for (int64_t t = ntl - 1; t >= 0; --t) {
         const int ln = opaque(lane);
         const int lcg = ln >> 4, lrg = ln & 15;
-        // per-lane byte offsets within a 16 x 4 block of V and of Q (64-bit
-        // only for leading dimensions past 32-bit reach)
+        // per-lane byte offsets within a 16 x 4 (FP64) or 16 x 16 (FP32) block
+        // of V and of Q (64-bit only for leading dimensions past 32-bit reach)
         using off_t = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
-        const off_t lane_v = (off_t)(lrg + lcg * lda) * 8u;
-        const off_t lane_q = (off_t)(lrg + lcg * ldq) * 8u;
-        // last column group: columns past n read column n - 1 instead (then zeroed)
+        const int cstep = MIXED ? 4 : 1;  // column distance of the lane groups
+        const off_t lane_v = (off_t)(lrg + cstep * lcg * lda) * (off_t)sizeof(E);
+        const off_t lane_q = (off_t)(lrg + cstep * lcg * ldq) * (off_t)sizeof(E);
+        // FP64, last column group: columns past n read column n - 1 instead (then zeroed)
         const int cl_last = 4 * (KC - 1) + lcg < n ? lcg : n - 1 - 4 * (KC - 1);
-        const off_t lane_vl = (off_t)(lrg + cl_last * lda) * 8u;
-        const double* T = Ttile + (leaf * f + t) * NT;
+        const off_t lane_vl = (off_t)(lrg + cl_last * lda) * (off_t)sizeof(E);
+        const E* T = Ttile + (leaf * f + t) * NT;
         const int64_t t0 = row0 + t * MT;
-        const int64_t valid = (rows - t * MT) < MT ? (rows - t * MT) : MT;
-        double Zr[KS][JW];
+        const int64_t valid = MIXED ? MT : ((rows - t * MT) < MT ? (rows - t * MT) : MT);
+        E Zr[KS][JW];
         {
-            double Sr[KS][JW];
+            E Sr[KS][JW];
 #pragma unroll
             for (int s = 0; s < KS; ++s)
 #pragma unroll
-                for (int jb = 0; jb < JW; ++jb) Sr[s][jb] = Ss[4 * s + cg + (16 * jb + rg) * NPB];
+                for (int jb = 0; jb < JW; ++jb) Sr[s][jb] = Ss[krow<E>(s, cg) + (16 * jb + rg) * NPB];
             if (t > 0) {
-                tri_times_regs<NP, JW>(T, Sr, Zr, lane);
+                tri_times_regs<NP, JW, E>(T, Sr, Zr, lane);
 #pragma unroll
                 for (int s = 0; s < KS; ++s)
 #pragma unroll
-                    for (int jb = 0; jb < JW; ++jb) Ss[4 * s + cg + (16 * jb + rg) * NPB] = Sr[s][jb] - Zr[s][jb];
+                    for (int jb = 0; jb < JW; ++jb) Ss[krow<E>(s, cg) + (16 * jb + rg) * NPB] = Sr[s][jb] - Zr[s][jb];
             } else {
                 // W = V_top^T S_0 with V_top the unit lower triangle of the tile's top rows
-                double Wr[KS][JW];
+                E Wr[KS][JW];
 #pragma unroll
                 for (int ib = 0; ib < JB; ++ib) {
-                    // V_top(4 s + q, 16 ib + p) vanishes for 4 s + 3 < 16 ib
-                    double vt[KS];
+                    // V_top(r, 16 ib + p) vanishes for r < 16 ib
+                    E vt[KS];
 #pragma unroll
                     for (int s = 4 * ib; s < KS; ++s) {
-                        const int r = 4 * s + cg, c = 16 * ib + rg;  // V_top(r, c)
+                        const int r = krow<E>(s, cg), c = 16 * ib + rg;  // V_top(r, c)
                         const bool ok = r > c && r < valid && c < n;
-                        const double v = V[t0 + (ok ? r + (int64_t)c * lda : 0)];
-                        vt[s] = ok ? v : (r == c && r < NP ? 1.0 : 0.0);
+                        const E v = V[t0 + (ok ? r + (int64_t)c * lda : 0)];
+                        vt[s] = ok ? v : (r == c && r < NP ? E(1) : E(0));
                     }
 #pragma unroll
                     for (int jb = 0; jb < JW; ++jb) {
-                        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+                        typename MM::acc_t acc = MM::zero();
 #pragma unroll
-                        for (int s = 4 * ib; s < KS; ++s) acc = mfma16x16x4(vt[s], Sr[s][jb], acc);
+                        for (int s = 4 * ib; s < KS; ++s) acc = MM::mma(vt[s], Sr[s][jb], acc);
 #pragma unroll
                         for (int r = 0; r < 4; ++r) Wr[4 * ib + r][jb] = acc[r];
                     }
                 }
-                tri_times_regs<NP, JW>(T, Wr, Zr, lane);
+                tri_times_regs<NP, JW, E>(T, Wr, Zr, lane);
                 __builtin_amdgcn_wave_barrier();  // S_0 is read across lanes below
             }
         }
@@ -802,47 +898,276 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         for (int i = 0; i < RL; ++i) {
             const int rl = 16 * i + lrg;
             const bool rv = rl < valid;
-            const double* vb = V + t0 + 16 * i;
-            double y[KC];
-            if (full) {
+            const E* vb = V + t0 + 16 * i;
+            E y[KX];
+            if (MIXED) {
+                // whole padded tiles: column krow(k, q) of V
+#pragma unroll
+                for (int k = 0; k < KX; ++k) y[k] = ld_at(vb + (int64_t)(16 * (k / 4) + k % 4) * lda, lane_v);
+            } else if (full) {
                 // only the last group of four columns can reach past n (NP = n rounded up to 4)
 #pragma unroll
-                for (int k = 0; k < KC - 1; ++k) y[k] = ld_at(vb + (int64_t)(4 * k) * lda, lane_v);
-                const double yl = ld_at(vb + (int64_t)(4 * (KC - 1)) * lda, lane_vl);
-                y[KC - 1] = 4 * (KC - 1) + lcg < n ? yl : 0.0;
+                for (int k = 0; k < KX - 1; ++k) y[k] = ld_at(vb + (int64_t)(4 * k) * lda, lane_v);
+                const E yl = ld_at(vb + (int64_t)(4 * (KX - 1)) * lda, lane_vl);
+                y[KX - 1] = 4 * (KX - 1) + lcg < n ? yl : E(0);
             } else {
                 // ragged tile or padded columns: clamp to an element that exists, then zero
                 const int rc = rv ? rl : (int)valid - 1;
 #pragma unroll
-                for (int k = 0; k < KC; ++k) {
+                for (int k = 0; k < KX; ++k) {
                     const int c = 4 * k + lcg, cc = c < n ? c : n - 1;
-                    const double v = V[t0 + rc + (int64_t)cc * lda];
-                    y[k] = (rv && c < n) ? v : 0.0;
+                    const E v = V[t0 + rc + (int64_t)cc * lda];
+                    y[k] = (rv && c < n) ? v : E(0);
                 }
             }
             if (t == 0) {
 #pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    const int c = 4 * k + lcg;
-                    if (rl < NP) y[k] = (rl > c) ? y[k] : (rl == c ? 1.0 : 0.0);
+                for (int k = 0; k < KX; ++k) {
+                    const int c = krow<E>(k, lcg);
+                    if (rl < NP) y[k] = (rl > c) ? y[k] : (rl == c ? E(1) : E(0));
                 }
             }
-            double* qb = Q + t0 + 16 * i + (int64_t)(16 * j0) * ldq;
+            E* qb = Q + t0 + 16 * i + (int64_t)(16 * j0) * ldq;
 #pragma unroll
             for (int jb = 0; jb < JW; ++jb) {
-                dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+                typename MM::acc_t acc = MM::zero();
 #pragma unroll
-                for (int k = 0; k < KC; ++k) acc = mfma16x16x4(Zr[k][jb], y[k], acc);
+                for (int k = 0; k < KX; ++k) acc = MM::mma(Zr[k][jb], y[k], acc);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int cl = 16 * jb + lcg + 4 * r, c = 16 * j0 + cl;
-                    // the window spans round16(NP) columns: those at or past n are never stored
-                    if (c < n && (full || rv)) {
-                        double v = -acc[r];
-                        if (t == 0 && rl < NP) v += Ss[rl + cl * NPB];
+                    const int cl = 16 * jb + MM::out_row(lcg, r), c = 16 * j0 + cl;
+                    E v = -acc[r];
+                    if (t == 0 && rl < NP) v += Ss[rl + cl * NPB];
+                    if (MIXED) {
+                        // every row and column of the workspace is written; zero past n
+                        st_at(qb + (int64_t)(16 * jb + r) * ldq, lane_q, c < n ? v : E(0));
+                    } else if (c < n && (full || rv)) {
+                        // the window spans round16(NP) columns: those at or past n are never stored
                         st_at(qb + (int64_t)(16 * jb + 4 * r) * ldq, lane_q, v);
                     }
                 }
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Second pass of the mixed-precision path.  Q1 (FP32, whole tiles, NPB =
+// round16(NP) columns, zero past n) is re-orthogonalised in FP64:
+//   G = Q1^T Q1 (products of FP32 values are exact in FP64), ||G - I||_F as
+//   the check of ||Q1^T Q1 - I||_F, G = R2^T R2 (Cholesky; Q1 is orthonormal
+//   to FP32 accuracy, so G is within about 1e-6 of I and the factorisation
+//   cannot break down), and when the check exceeds its bound
+//   Q = Q1 R2^{-1}, R = R2 R1.
+// --------------------------------------------------------------------------
+
+// Partial Gram matrices: wavefront w sums rows [w rw, (w + 1) rw) (rw a
+// multiple of 64) into the upper blocks of its NPB x NPB slot of Gp.  In k-step
+// s of a 64-row group, lane (q, p) supplies row 16 q + s of columns 16 b + p:
+// the 16 rows a lane needs are consecutive, four 16-byte loads per block.
+template <int NP>
+__global__ void __launch_bounds__(256) k_gram_q1(const float* __restrict__ Q1, int64_t ldq1, int64_t rows_total,
+                                                 int64_t rw, int64_t nw, double* __restrict__ Gp)
+{
+    constexpr int NPB = round16(NP), JB = NPB / 16;
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int q = lane >> 4, p = lane & 15;
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (w >= nw) return;
+    dbl4 acc[JB][JB];
+#pragma unroll
+    for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) acc[ib][jb] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int64_t r0 = w * rw, r1 = (r0 + rw) < rows_total ? (r0 + rw) : rows_total;
+    for (int64_t g = r0; g < r1; g += 64) {
+        float x[JB][16];
+#pragma unroll
+        for (int b = 0; b < JB; ++b) {
+            const float* src = Q1 + g + 16 * q + (int64_t)(16 * b + p) * ldq1;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float4 t = *reinterpret_cast<const float4*>(src + 4 * v);
+                x[b][4 * v] = t.x;
+                x[b][4 * v + 1] = t.y;
+                x[b][4 * v + 2] = t.z;
+                x[b][4 * v + 3] = t.w;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+#pragma unroll
+            for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+                for (int jb = ib; jb < JB; ++jb)
+                    acc[ib][jb] = mfma16x16x4((double)x[ib][s], (double)x[jb][s], acc[ib][jb]);
+    }
+    double* G = Gp + w * NPB * NPB;
+#pragma unroll
+    for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+        for (int jb = ib; jb < JB; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) G[(16 * ib + q + 4 * r) + (16 * jb + p) * NPB] = acc[ib][jb][r];
+}
+
+// Sum of the partial Gram matrices in two stages, both pairwise, so that every
+// entry carries O(log nw) rounding steps (the check it feeds is 1e-13).
+// Stage 1: block (x, g) adds partials [64 g, 64 g + 64) of 256 entries (eight
+// interleaved accumulators, combined as a tree) into Gq[g].
+template <int NP>
+__global__ void __launch_bounds__(256) k_gram_sum64(const double* __restrict__ Gp, int64_t nw, double* __restrict__ Gq)
+{
+    constexpr int NPB = round16(NP);
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = blockIdx.y;
+    if (e >= NPB * NPB) return;
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int64_t w0 = 64 * g, wn = (nw - w0) < 64 ? (nw - w0) : 64;
+    if (wn == 64) {
+#pragma unroll
+        for (int u = 0; u < 64; ++u) a[u % 8] += Gp[(w0 + u) * NPB * NPB + e];
+    } else {
+        for (int64_t u = 0; u < wn; ++u) a[u % 8] += Gp[(w0 + u) * NPB * NPB + e];
+    }
+    Gq[g * NPB * NPB + e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// Stage 2: one thread per entry merges the ng group sums as a binary counter.
+template <int NP>
+__global__ void __launch_bounds__(256) k_gram_sum(const double* __restrict__ Gq, int64_t ng, double* __restrict__ G)
+{
+    constexpr int NPB = round16(NP);
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= NPB * NPB) return;
+    double stack[32];
+    int64_t cnt = 0;
+    for (int64_t g = 0; g < ng; ++g) {
+        double cs = Gq[g * NPB * NPB + e];
+        int lvl = 0;
+        for (int64_t c = cnt; c & 1; c >>= 1) cs = stack[lvl++] + cs;
+        stack[lvl] = cs;
+        ++cnt;
+    }
+    double sum = 0.0;
+    for (int lvl = 0; cnt >> lvl; ++lvl)
+        if ((cnt >> lvl) & 1) sum = stack[lvl] + sum;
+    G[e] = sum;
+}
+
+// One wavefront: the check ||G - I||_F, the flag, the Cholesky factor R2 of
+// G, R2^{-1}, and R = R2 R1 for the caller (R1 the sign-normalised first-pass
+// R; diag(R2) > 0 keeps diag(R) >= 0).  Below the bound: R2^{-1} = I, R = R1.
+// G and then R2 sit in LDS (column j owned by lane j); column j of R2^{-1} is
+// written by lane j straight to R2inv (NPB x NPB, zero past n).
+template <int NP>
+__global__ void __launch_bounds__(64) k_reorth_factor(const double* __restrict__ G, const double* __restrict__ R1,
+                                                      int n, double bound, double* __restrict__ Xs,
+                                                      double* __restrict__ info, double* __restrict__ R, int64_t ldr)
+{
+    constexpr int NPB = round16(NP), LD = NPB + 1, XLD = NPB;
+    __shared__ double Gs[NPB * LD];
+    const int lane = threadIdx.x;
+    // symmetric G from its upper triangle; lane j owns column j
+    double dev = 0.0;
+    for (int j = lane; j < NPB; j += 64)
+        for (int i = 0; i < NPB; ++i) {
+            const double g = (i <= j) ? G[i + j * NPB] : G[j + i * NPB];
+            Gs[i + j * LD] = g;
+            if (i < n && j < n) {
+                const double d = g - (i == j ? 1.0 : 0.0);
+                dev = fma(d, d, dev);
+            }
+        }
+    // ||G - I||_F over the n x n block: wave sum
+    for (int off = 32; off >= 1; off >>= 1) dev += __shfl_xor(dev, off);
+    const double orth = sqrt(dev);
+    const bool apply = orth > bound;
+    __syncthreads();
+    if (apply) {
+        // right-looking Cholesky G = R2^T R2, R2 upper, overwriting the upper triangle of Gs
+        for (int k = 0; k < n; ++k) {
+            const double d = sqrt(Gs[k + k * LD]);
+            __syncthreads();
+            for (int j = lane; j < n; j += 64) {
+                if (j > k) Gs[k + j * LD] /= d;
+                if (j == k) Gs[k + k * LD] = d;
+            }
+            __syncthreads();
+            for (int j = lane; j < n; j += 64)
+                if (j > k) {
+                    const double rkj = Gs[k + j * LD];
+                    for (int i = k + 1; i <= j; ++i) Gs[i + j * LD] = fma(-Gs[k + i * LD], rkj, Gs[i + j * LD]);
+                }
+            __syncthreads();
+        }
+        // column j of R2^{-1} by back substitution (the lane reads back only its own writes)
+        for (int j = lane; j < NPB; j += 64) {
+            for (int i = 0; i < NPB; ++i) Xs[i + j * XLD] = 0.0;
+            if (j < n) {
+                Xs[j + j * XLD] = 1.0 / Gs[j + j * LD];
+                for (int i = j - 1; i >= 0; --i) {
+                    double acc = 0.0;
+                    for (int k = i + 1; k <= j; ++k) acc = fma(Gs[i + k * LD], Xs[k + j * XLD], acc);
+                    Xs[i + j * XLD] = -acc / Gs[i + i * LD];
+                }
+            }
+        }
+    } else {
+        for (int j = lane; j < NPB; j += 64)
+            for (int i = 0; i < NPB; ++i) {
+                Xs[i + j * XLD] = (i == j && j < n) ? 1.0 : 0.0;
+                Gs[i + j * LD] = (i == j) ? 1.0 : 0.0;
+            }
+    }
+    __syncthreads();
+    // R = R2 R1 (upper times upper), column j by lane j
+    for (int j = lane; j < n; j += 64)
+        for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            if (i <= j)
+                for (int k = i; k <= j; ++k) acc = fma(Gs[i + k * LD], R1[k + j * NP], acc);
+            R[i + j * ldr] = acc;
+        }
+    if (lane == 0) {
+        info[0] = orth;
+        info[1] = apply ? 1.0 : 0.0;
+    }
+}
+
+// Q = Q1 R2^{-1} in FP64 (R2^{-1} = I when the check passed), 16 rows at a
+// time: D = R2^{-T} Q1^T on the matrix cores, so that a lane's outputs are 16
+// consecutive rows of one column of Q.  R2^{-1} is upper triangular: output
+// block ob needs k < 16 (ob + 1) only.
+template <int NP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_reorth_q(const float* __restrict__ Q1, int64_t ldq1, int64_t m, int n,
+                                                  const double* __restrict__ R2inv, double* __restrict__ Q,
+                                                  int64_t ldq, int64_t nblocks)
+{
+    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int q = lane >> 4, p = lane & 15;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    // A operands R2^{-T}(16 ob + p, 4 s + q) = R2^{-1}(4 s + q, 16 ob + p), kept for the whole run
+    double ra[JB][KS];
+#pragma unroll
+    for (int ob = 0; ob < JB; ++ob)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) ra[ob][s] = (s < 4 * (ob + 1)) ? R2inv[(4 * s + q) + (16 * ob + p) * NPB] : 0.0;
+    for (int64_t rb = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; rb < nblocks; rb += nwaves) {
+        const int64_t row = 16 * rb + p;
+        double x[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) x[s] = (double)Q1[row + (int64_t)(4 * s + q) * ldq1];
+#pragma unroll
+        for (int ob = 0; ob < JB; ++ob) {
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < 4 * (ob + 1) && s < KS; ++s) acc = mfma16x16x4(ra[ob][s], x[s], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = 16 * ob + q + 4 * r;
+                if (row < m && c < n) Q[row + (int64_t)c * ldq] = acc[r];
             }
         }
     }
@@ -1115,7 +1440,7 @@ hipError_t leaf_factor_np(const Layout& L, const double* A, int64_t lda, double*
                           bool want_q, hipStream_t s)
 {
     constexpr int MT = tile_rows_for(NP);
-    const size_t lds = (size_t)L.waves * factor_lds_doubles(NP, MT) * sizeof(double);
+    const size_t lds = (size_t)L.waves * factor_lds_doubles(NP, MT, want_q) * sizeof(double);
     const dim3 grid(grid_for(L.P, L.waves)), block(64 * L.waves);
     if (want_q) {
         allow_lds(k_leaf_factor<NP, true>, lds);
@@ -1134,7 +1459,7 @@ hipError_t tree_np(const Layout& L, double* ws, bool want_q, hipStream_t s)
 {
     constexpr int MTN = round16(NP);
     const int waves = NP <= 32 ? 4 : 2;  // per-wave LDS grows as NP^2
-    const size_t lds = (size_t)waves * factor_lds_doubles(NP, MTN) * sizeof(double);
+    const size_t lds = (size_t)waves * factor_lds_doubles(NP, MTN, want_q) * sizeof(double);
     for (int l = 1; l <= L.levels; ++l) {
         const dim3 grid(grid_for(L.count[l], waves)), block(64 * waves);
         if (want_q) {
@@ -1182,13 +1507,13 @@ hipError_t form_q_np(const Layout& L, const double* A, int64_t lda, double* ws, 
     const size_t lds = (size_t)L.waves * NPB * 16 * JW * sizeof(double);
     const dim3 grid(grid_for(L.P * SPLIT, L.waves)), block(64 * L.waves);
     if (lane_offsets_fit_32(lda) && lane_offsets_fit_32(ldq)) {
-        allow_lds(k_form_q<NP, false>, lds);
-        hipLaunchKernelGGL((k_form_q<NP, false>), grid, block, lds, s, A, lda, L.m, (int)L.n, L.P, L.leaf_rows,
-                           L.f, ws + L.off_T, ws + L.off_S[0], Q, ldq);
+        allow_lds(k_form_q<NP, false, double>, lds);
+        hipLaunchKernelGGL((k_form_q<NP, false, double>), grid, block, lds, s, A, lda, L.m, (int)L.n, L.P,
+                           L.leaf_rows, L.f, ws + L.off_T, ws + L.off_S[0], Q, ldq);
     } else {
-        allow_lds(k_form_q<NP, true>, lds);
-        hipLaunchKernelGGL((k_form_q<NP, true>), grid, block, lds, s, A, lda, L.m, (int)L.n, L.P, L.leaf_rows,
-                           L.f, ws + L.off_T, ws + L.off_S[0], Q, ldq);
+        allow_lds(k_form_q<NP, true, double>, lds);
+        hipLaunchKernelGGL((k_form_q<NP, true, double>), grid, block, lds, s, A, lda, L.m, (int)L.n, L.P,
+                           L.leaf_rows, L.f, ws + L.off_T, ws + L.off_S[0], Q, ldq);
     }
     return hipGetLastError();
 }
@@ -1221,6 +1546,87 @@ hipError_t apply_qt_np(const Layout& L, const double* A, int64_t lda, int64_t k,
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// ---- mixed precision -------------------------------------------------------
+
+// True when the byte offset of element (15, 12) of a 16 x 16 FP32 block with
+// leading dimension ld fits in 32 bits.
+inline bool lane_offsets_fit_32_f32(int64_t ld) { return (uint64_t)(15 + 12 * ld) * 4u < (1ull << 32); }
+
+template <int NP>
+hipError_t mixed_leaf_np(const Layout& L, const double* A, int64_t lda, double* ws, bool want_q, hipStream_t s)
+{
+    constexpr int MT = tile_rows_f32(NP);
+    const size_t lds = (size_t)L.waves * factor_lds_doubles<float>(NP, MT, want_q) * sizeof(double);
+    const dim3 grid(grid_for(L.P, L.waves)), block(64 * L.waves);
+    float* V32 = reinterpret_cast<float*>(ws + L.off_V32);
+    float* T32 = reinterpret_cast<float*>(ws + L.off_T32);
+    if (want_q) {
+        allow_lds(k_leaf_factor<NP, true, float>, lds);
+        hipLaunchKernelGGL((k_leaf_factor<NP, true, float>), grid, block, lds, s, A, lda, V32, L.ld32, L.m,
+                           (int)L.n, L.P, L.leaf_rows, L.f, T32, ws + L.off_R[0]);
+    } else {
+        allow_lds(k_leaf_factor<NP, false, float>, lds);
+        hipLaunchKernelGGL((k_leaf_factor<NP, false, float>), grid, block, lds, s, A, lda, V32, L.ld32, L.m,
+                           (int)L.n, L.P, L.leaf_rows, L.f, T32, ws + L.off_R[0]);
+    }
+    return hipGetLastError();
+}
+
+template <int NP>
+hipError_t form_q1_np(const Layout& L, double* ws, hipStream_t s)
+{
+    constexpr int NPB = round16(NP), JW = fq_col_blocks(NP), SPLIT = NPB / 16 / JW;
+    const size_t lds = (size_t)L.waves * NPB * 16 * JW * sizeof(float);
+    const dim3 grid(grid_for(L.P * SPLIT, L.waves)), block(64 * L.waves);
+    const float* V32 = reinterpret_cast<const float*>(ws + L.off_V32);
+    const float* T32 = reinterpret_cast<const float*>(ws + L.off_T32);
+    float* Q1 = reinterpret_cast<float*>(ws + L.off_Q1);
+    if (lane_offsets_fit_32_f32(L.ld32)) {
+        allow_lds(k_form_q<NP, false, float>, lds);
+        hipLaunchKernelGGL((k_form_q<NP, false, float>), grid, block, lds, s, V32, L.ld32, L.m, (int)L.n, L.P,
+                           L.leaf_rows, L.f, T32, ws + L.off_S[0], Q1, L.ld32);
+    } else {
+        allow_lds(k_form_q<NP, true, float>, lds);
+        hipLaunchKernelGGL((k_form_q<NP, true, float>), grid, block, lds, s, V32, L.ld32, L.m, (int)L.n, L.P,
+                           L.leaf_rows, L.f, T32, ws + L.off_S[0], Q1, L.ld32);
+    }
+    return hipGetLastError();
+}
+
+template <int NP>
+hipError_t reorth_np(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s)
+{
+    constexpr int NPB = round16(NP);
+    const float* Q1 = reinterpret_cast<const float*>(ws + L.off_Q1);
+    hipLaunchKernelGGL((k_gram_q1<NP>), dim3(grid_for(L.gram_waves, 4)), dim3(256), 0, s, Q1, L.ld32, L.ld32,
+                       L.gram_rows, L.gram_waves, ws + L.off_Gp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t ng = (L.gram_waves + 63) / 64;
+    hipLaunchKernelGGL((k_gram_sum64<NP>), dim3((NPB * NPB + 255) / 256, (unsigned)ng), dim3(256), 0, s,
+                       ws + L.off_Gp, L.gram_waves, ws + L.off_Gq);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_gram_sum<NP>), dim3((NPB * NPB + 255) / 256), dim3(256), 0, s, ws + L.off_Gq, ng,
+                       ws + L.off_G);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_reorth_factor<NP>), dim3(1), dim3(64), 0, s, ws + L.off_G, ws + L.off_R1, (int)L.n,
+                       kReorthBound, ws + L.off_R2inv, ws + L.off_info, R, ldr);
+    return hipGetLastError();
+}
+
+template <int NP>
+hipError_t reorth_q_np(const Layout& L, double* ws, double* Q, int64_t ldq, hipStream_t s)
+{
+    const float* Q1 = reinterpret_cast<const float*>(ws + L.off_Q1);
+    const int64_t nblocks = (L.m + 15) / 16;
+    const int64_t waves = nblocks < 8192 ? nblocks : 8192;
+    hipLaunchKernelGGL((k_reorth_q<NP>), dim3(grid_for(waves, 4)), dim3(256), 0, s, Q1, L.ld32, L.m, (int)L.n,
+                       ws + L.off_R2inv, Q, ldq, nblocks);
+    return hipGetLastError();
 }
 
 }  // namespace detail
@@ -1258,5 +1664,42 @@ hipError_t apply_qt_np(const Layout& L, const double* A, int64_t lda, int64_t k,
 {
     return detail::apply_qt_np<NP>(L, A, lda, k, B, ldb, ws, s);
 }
+
+template <int NP>
+hipError_t mixed_leaf_np(const Layout& L, const double* A, int64_t lda, double* ws, bool want_q, hipStream_t s)
+{
+    return detail::mixed_leaf_np<NP>(L, A, lda, ws, want_q, s);
+}
+template <int NP>
+hipError_t form_q1_np(const Layout& L, double* ws, hipStream_t s)
+{
+    return detail::form_q1_np<NP>(L, ws, s);
+}
+template <int NP>
+hipError_t reorth_np(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s)
+{
+    return detail::reorth_np<NP>(L, ws, R, ldr, s);
+}
+template <int NP>
+hipError_t reorth_q_np(const Layout& L, double* ws, double* Q, int64_t ldq, hipStream_t s)
+{
+    return detail::reorth_q_np<NP>(L, ws, Q, ldq, s);
+}
+
+// Every per-width launcher of one padded width (used by the tsqr_np_*.hip units).
+#define TSQR_INSTANTIATE(NP)                                                                                   \
+    template hipError_t leaf_factor_np<NP>(const Layout&, const double*, int64_t, double*, int64_t, double*, bool, \
+                                           hipStream_t);                                                     \
+    template hipError_t tree_np<NP>(const Layout&, double*, bool, hipStream_t);                                \
+    template hipError_t root_np<NP>(const Layout&, double*, double*, int64_t, hipStream_t);                    \
+    template hipError_t seeds_np<NP>(const Layout&, double*, hipStream_t);                                     \
+    template hipError_t form_q_np<NP>(const Layout&, const double*, int64_t, double*, double*, int64_t,        \
+                                      hipStream_t);                                                          \
+    template hipError_t apply_qt_np<NP>(const Layout&, const double*, int64_t, int64_t, double*, int64_t,      \
+                                        double*, hipStream_t);                                               \
+    template hipError_t mixed_leaf_np<NP>(const Layout&, const double*, int64_t, double*, bool, hipStream_t);  \
+    template hipError_t form_q1_np<NP>(const Layout&, double*, hipStream_t);                                   \
+    template hipError_t reorth_np<NP>(const Layout&, double*, double*, int64_t, hipStream_t);                  \
+    template hipError_t reorth_q_np<NP>(const Layout&, double*, double*, int64_t, hipStream_t);
 
 }  // namespace tsqr

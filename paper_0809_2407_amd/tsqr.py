@@ -34,9 +34,9 @@ def to_colmajor(X: torch.Tensor, device="cuda") -> torch.Tensor:
     return Y
 
 
-def _ld(X: torch.Tensor, rows: int, name: str) -> int:
-    if X.dim() != 2 or X.dtype != torch.float64:
-        raise ValueError(f"{name}: a 2-D float64 tensor is required")
+def _ld(X: torch.Tensor, rows: int, name: str, dtype=torch.float64) -> int:
+    if X.dim() != 2 or X.dtype != dtype:
+        raise ValueError(f"{name}: a 2-D {dtype} tensor is required")
     if not X.is_cuda:
         raise ValueError(f"{name}: a device tensor is required")
     if X.shape[0] != rows:
@@ -130,13 +130,21 @@ class Plan:
         check("tsqr_plan_timings", self._lib.tsqr_plan_timings(self._h, ctypes.byref(out)))
         return {name: (out.ms[i], out.calls[i]) for i, name in enumerate(PHASES)}
 
-    def form_q(self, A: torch.Tensor, Q: Optional[torch.Tensor] = None) -> torch.Tensor:
-        lda = _ld(A, self.m, "A")
+    def form_q(self, A: Optional[torch.Tensor], Q: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """tsqr_form_q.  A is the factored matrix (FP64 plans); a MIXED plan keeps
+        its reflectors itself and takes A = None."""
+        aptr, lda = (A.data_ptr(), _ld(A, self.m, "A")) if A is not None else (0, self.m)
         if Q is None:
-            Q = colmajor(self.m, self.n, device=A.device)
+            Q = colmajor(self.m, self.n, device=A.device if A is not None else "cuda")
         ldq = _ld(Q, self.m, "Q")
-        check("tsqr_form_q", self._lib.tsqr_form_q(self._h, A.data_ptr(), lda, Q.data_ptr(), ldq))
+        check("tsqr_form_q", self._lib.tsqr_form_q(self._h, aptr, lda, Q.data_ptr(), ldq))
         return Q
+
+    def mixed_q1(self) -> torch.Tensor:
+        """tsqr_mixed_q1: the FP32 first-pass Q1 of a MIXED plan (m x n, column-major)."""
+        Q1 = colmajor(self.m, self.n, dtype=torch.float32)
+        check("tsqr_mixed_q1", self._lib.tsqr_mixed_q1(self._h, Q1.data_ptr(), _ld(Q1, self.m, "Q1", torch.float32)))
+        return Q1
 
     def apply_qt(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
         lda = _ld(A, self.m, "A")

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared_functions():
     text = open(os.path.join(ROOT, "include", "tsqr.h")).read()
-    return sorted(set(re.findall(r"\b(tsqr_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(tsqr_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():

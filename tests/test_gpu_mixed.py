@@ -1,0 +1,138 @@
+"""The mixed-precision path (FP32 first pass, FP64 re-orthogonalising second
+pass) through the C ABI.  FP32 rounding values are parity unpinned: the checks
+are the bounds of the method against the FP64 oracle -- backward error
+<= 1e-6, orthogonality <= 1e-13 after the second pass, R close to the oracle's
+-- and the second pass's own check, ||R2^T R2 - I||_F, against ||Q1^T Q1 - I||_F
+computed on the host from the first-pass Q1."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import announce, need_gpu
+from metrics import backward_error, is_upper, orthogonality, rel_diff
+
+pytestmark = pytest.mark.gpu
+
+BWD_MIXED = 1e-6
+ORTH_MIXED = 1e-13
+
+
+def run_mixed(A, want_q=True, **plan_kw):
+    torch = need_gpu()
+    from paper_0809_2407_amd import tsqr as T
+
+    m, n = A.shape
+    Ad = T.to_colmajor(torch.from_numpy(A))
+    A_before = Ad.clone()
+    with T.Plan(m, n, precision="mixed", want_q=want_q, **plan_kw) as p:
+        R = p.factor(Ad)
+        Q = Q1 = None
+        if want_q:
+            Q = p.form_q(None)
+            Q1 = p.mixed_q1()
+        torch.cuda.synchronize()
+        info = p.info()
+    assert torch.equal(Ad, A_before)  # A is only read on a MIXED plan
+    return (R.cpu().numpy(), None if Q is None else Q.cpu().numpy(),
+            None if Q1 is None else Q1.cpu().numpy().astype(np.float64), info)
+
+
+CASES = [(50000, 64), (40000, 32), (30000, 17), (20000, 8), (9000, 48), (5000, 3), (777, 20)]
+
+
+@pytest.mark.parametrize("m,n", CASES)
+def test_mixed_bounds_on_prescribed_sigma(m, n):
+    """sigma log-spaced from 1 to 1e-6 (the matrix of the mixed comparison)."""
+    need_gpu()
+    A, _ = synth.prescribed_sigma(m, n, seed=700 + n, decades=6)
+    announce(f"mixed {m}x{n} kappa=1e6")
+    R, Q, Q1, info = run_mixed(A)
+    assert info["precision"] == 1 and info["reorth_applied"] == 1
+    assert is_upper(R) and np.all(np.diag(R) >= 0)
+    bwd = backward_error(A, Q, R)
+    orth = orthogonality(Q)
+    Rref = oracle.qr_reference(A, want_q=False)
+    dr = rel_diff(R, Rref)
+    print(f"mixed {m}x{n}: backward {bwd:.2e} orthogonality {orth:.2e} |R-R_fp64|/|R| {dr:.2e} "
+          f"orth_estimate {info['orth_estimate']:.3e}")
+    assert bwd <= BWD_MIXED
+    assert orth <= ORTH_MIXED
+    assert dr <= 1e-5
+
+
+@pytest.mark.parametrize("m,n", [(50000, 64), (30000, 17), (4000, 5)])
+def test_second_pass_check_matches_first_pass_orthogonality(m, n):
+    """The device-side check ||G - I||_F (= ||R2^T R2 - I||_F) agrees with
+    ||Q1^T Q1 - I||_F computed on the host from the copied first-pass Q1."""
+    need_gpu()
+    A = synth.gaussian(m, n, seed=800 + n)
+    announce(f"mixed check {m}x{n}")
+    R, Q, Q1, info = run_mixed(A)
+    host = orthogonality(Q1)
+    est = info["orth_estimate"]
+    print(f"orth estimate {est:.6e} host {host:.6e}")
+    assert host > ORTH_MIXED  # an FP32 Q1 is never orthogonal to 1e-13
+    assert abs(est - host) <= 1e-3 * host
+    # Q1 itself is a QR factor to FP32 accuracy, and Q = Q1 R2^{-1}
+    assert orthogonality(Q1) <= 1e-4
+    assert orthogonality(Q) <= ORTH_MIXED
+
+
+def test_mixed_ill_conditioned_and_ragged():
+    need_gpu()
+    A, _ = synth.prescribed_sigma(5 * 4096 + 321, 32, seed=901, decades=12)
+    announce("mixed kappa=1e12 ragged")
+    R, Q, _, info = run_mixed(A, tree="hybrid", flat_len=3)
+    assert backward_error(A, Q, R) <= BWD_MIXED
+    assert orthogonality(Q) <= ORTH_MIXED
+
+
+@pytest.mark.parametrize("tree", [dict(tree="binary"), dict(tree="flat"), dict(tree="hybrid", flat_len=2)],
+                         ids=["binary", "flat", "hybrid2"])
+def test_mixed_trees(tree):
+    need_gpu()
+    A, _ = synth.prescribed_sigma(12000, 24, seed=902, decades=6)
+    announce(f"mixed trees {tree}")
+    R, Q, _, info = run_mixed(A, **tree)
+    assert backward_error(A, Q, R) <= BWD_MIXED
+    assert orthogonality(Q) <= ORTH_MIXED
+    assert rel_diff(R, oracle.qr_reference(A, want_q=False)) <= 1e-5
+
+
+def test_mixed_r_only_and_tiny():
+    need_gpu()
+    A, _ = synth.prescribed_sigma(30000, 40, seed=903, decades=6)
+    announce("mixed R only")
+    R, Q, _, info = run_mixed(A, want_q=False)
+    assert Q is None
+    assert is_upper(R) and np.all(np.diag(R) >= 0)
+    # one FP32 pass: R to FP32-level accuracy
+    assert rel_diff(R, oracle.qr_reference(A, want_q=False)) <= 1e-5
+    for m, n in [(64, 64), (16, 16), (70, 9)]:
+        A = synth.gaussian(m, n, seed=904 + n)
+        announce(f"mixed tiny {m}x{n}")
+        R, Q, _, _ = run_mixed(A)
+        assert backward_error(A, Q, R) <= BWD_MIXED
+        assert orthogonality(Q) <= ORTH_MIXED
+
+
+def test_mixed_rejects_apply_qt_and_matches_fp64_plan():
+    torch = need_gpu()
+    from paper_0809_2407_amd import tsqr as T
+    from paper_0809_2407_amd._lib import TsqrError
+
+    A = synth.gaussian(8000, 16, seed=905)
+    Ad = T.to_colmajor(torch.from_numpy(A))
+    B = T.colmajor(8000, 2)
+    announce("mixed apply_qt unsupported")
+    with T.Plan(8000, 16, precision="mixed") as p:
+        p.factor(Ad)
+        with pytest.raises(TsqrError) as e:
+            p.apply_qt(Ad, B)
+        assert e.value.status == 3
+    with T.Plan(8000, 16) as p:
+        with pytest.raises(TsqrError) as e:
+            p.mixed_q1()
+        assert e.value.status == 3
+    torch.cuda.synchronize()
