@@ -200,6 +200,48 @@ tsqr_status tsqr_plan_timings(tsqr_plan p, tsqr_timings* out);
 /* Free the plan and its workspace (synchronises its stream first). */
 tsqr_status tsqr_plan_destroy(tsqr_plan p);
 
+/* ---- Batched plans --------------------------------------------------------
+ * Many independent problems (A_i m_i x n_i, n_i <= 64) factored together: the
+ * library's own batched launch, not a construct of the paper, which treats one
+ * matrix.  Each problem gets the single-problem method (leaf chains, binary
+ * tree over the leaves, sign normalisation; the explicit Q by the seed
+ * broadcast) and the same results.  Problems of one padded width share every
+ * launch: persistent kernels walk device work lists of (problem, leaf) and
+ * (problem, tree node) items, one launch per phase and tree level, and the
+ * whole sequence is captured once into a HIP graph that each call replays
+ * (one small pointer upload and one graph launch on the plan's stream, no
+ * host synchronisation).  Batched plans are FP64 only (MIXED returns 3); opts
+ * apply to every problem (tile_rows must be 0). */
+typedef struct tsqr_batched_plan_s* tsqr_batched_plan;
+
+/* count problems with sizes m[i] x n[i] (host arrays).  Errors: -1 p NULL,
+ * -2 count < 1, -3 m NULL or some m[i] < n[i] or m[i] < 1 or n[i] < 1, -4 n
+ * NULL, -5 bad precision, -6 bad option field; 3 MIXED, n[i] > 64 or a tree too
+ * deep; 2 out of memory. */
+tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* p, int count, const int64_t* m, const int64_t* n,
+                                     tsqr_precision prec, const tsqr_opts* opts, void* hip_stream);
+
+/* Factor every A[i] (device pointer, lda[i] >= m[i]; host arrays of pointers
+ * and leading dimensions) and write R[i] (n[i] x n[i], ldr[i] >= n[i]).  With
+ * want_q the reflectors overwrite A[i] as in tsqr_factor.  Errors: -1 p, -2 A
+ * or some A[i] NULL, -3 lda or some lda[i] < m[i], -4 R or some R[i] NULL,
+ * -5 ldr or some ldr[i] < n[i]. */
+tsqr_status tsqr_batched_factor(tsqr_batched_plan p, double* const* A, const int64_t* lda, double* const* R,
+                                const int64_t* ldr);
+
+/* Explicit thin Q[i] (m[i] x n[i], ldq[i] >= m[i]) of every problem from its
+ * factored A[i]; Q[i] may alias A[i] with the same leading dimension.
+ * Errors as tsqr_batched_factor (-4 Q, -5 ldq or aliasing with another
+ * leading dimension); 4 when no factorisation with reflectors was done. */
+tsqr_status tsqr_batched_form_q(tsqr_batched_plan p, double* const* A, const int64_t* lda, double* const* Q,
+                                const int64_t* ldq);
+
+/* What the plan chose for problem `index`.  Errors: -1 p, -2 index, -3 out. */
+tsqr_status tsqr_batched_problem_info(tsqr_batched_plan p, int index, tsqr_info* out);
+
+/* Free the batched plan (synchronises its stream first). */
+tsqr_status tsqr_batched_plan_destroy(tsqr_batched_plan p);
+
 /* Static, human-readable text for a status code. */
 const char* tsqr_status_string(tsqr_status s);
 

@@ -39,6 +39,8 @@ EXPORTED = [
     "tsqr_plan_create", "tsqr_plan_query", "tsqr_factor", "tsqr_factor_into", "tsqr_form_q", "tsqr_apply_qt",
     "tsqr_plan_info", "tsqr_plan_profile", "tsqr_plan_timings", "tsqr_plan_destroy", "tsqr_status_string",
     "tsqr_version", "tsqr_mixed_q1",
+    "tsqr_batched_plan_create", "tsqr_batched_factor", "tsqr_batched_form_q", "tsqr_batched_problem_info",
+    "tsqr_batched_plan_destroy",
 ]
 
 _lib = None
@@ -87,6 +89,19 @@ def load(path: str = LIB_PATH):
     lib.tsqr_version.restype = ctypes.c_int
     lib.tsqr_mixed_q1.argtypes = [P, ctypes.c_void_p, i64]
     lib.tsqr_mixed_q1.restype = ctypes.c_int
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    vpp = ctypes.POINTER(ctypes.c_void_p)
+    lib.tsqr_batched_plan_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, i64p, i64p, ctypes.c_int,
+                                             ctypes.POINTER(TsqrOpts), P]
+    lib.tsqr_batched_plan_create.restype = ctypes.c_int
+    lib.tsqr_batched_factor.argtypes = [P, vpp, i64p, vpp, i64p]
+    lib.tsqr_batched_factor.restype = ctypes.c_int
+    lib.tsqr_batched_form_q.argtypes = [P, vpp, i64p, vpp, i64p]
+    lib.tsqr_batched_form_q.restype = ctypes.c_int
+    lib.tsqr_batched_problem_info.argtypes = [P, ctypes.c_int, ctypes.POINTER(TsqrInfo)]
+    lib.tsqr_batched_problem_info.restype = ctypes.c_int
+    lib.tsqr_batched_plan_destroy.argtypes = [P]
+    lib.tsqr_batched_plan_destroy.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -1,0 +1,337 @@
+// tsqr_batched.cpp -- batched TSQR plans: many independent tall-skinny
+// problems factored by one replay of a captured HIP graph.
+//
+// Problems are grouped by padded width (one kernel instantiation per width).
+// For each width class the plan holds device work lists -- the (problem,
+// leaf) items of the leaf chains and of the explicit-Q pass, the (problem,
+// node) items of every tree level, one root item per problem -- and the
+// persistent batched kernels walk them.  The per-problem geometry and
+// workspace offsets are uploaded once; the matrix pointers of a call go
+// through a pinned staging buffer to a small device table, so the captured
+// graphs never change and a call costs one small copy and one graph launch,
+// with no host synchronisation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/tsqr.h"
+#include "tsqr_internal.h"
+
+struct tsqr_batched_plan_s {
+    int count = 0;
+    tsqr_precision prec = TSQR_FP64;
+    int want_q = 1;
+    int waves = 0;  // leaf and Q kernels: wavefronts per workgroup
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;  // internal, only for capturing the graphs
+    std::vector<tsqr::Layout> L;
+    std::vector<tsqr::BatchClass> classes;
+    double* ws = nullptr;
+    int64_t ws_doubles = 0;
+    tsqr::BatchProblem* d_probs = nullptr;
+    int64_t* d_items = nullptr;
+    tsqr::BatchArgs* d_args_f = nullptr;
+    tsqr::BatchArgs* d_args_q = nullptr;
+    tsqr::BatchArgs* h_args_f = nullptr;  // pinned staging
+    tsqr::BatchArgs* h_args_q = nullptr;
+    hipEvent_t ev_f = nullptr, ev_q = nullptr;  // the staging copies have been consumed
+    hipGraphExec_t g_factor = nullptr, g_form_q = nullptr;
+    int state = 0;  // 0: nothing factored, 1: factored with reflectors, 2: R only
+};
+
+namespace {
+
+tsqr_status hstatus(hipError_t e)
+{
+    if (e == hipSuccess) return 0;
+    if (e == hipErrorOutOfMemory) return 2;
+    return 1;
+}
+
+void release(tsqr_batched_plan_s* p)
+{
+    if (p->g_factor) hipGraphExecDestroy(p->g_factor);
+    if (p->g_form_q) hipGraphExecDestroy(p->g_form_q);
+    if (p->ev_f) hipEventDestroy(p->ev_f);
+    if (p->ev_q) hipEventDestroy(p->ev_q);
+    if (p->h_args_f) hipHostFree(p->h_args_f);
+    if (p->h_args_q) hipHostFree(p->h_args_q);
+    if (p->d_args_f) hipFree(p->d_args_f);
+    if (p->d_args_q) hipFree(p->d_args_q);
+    if (p->d_items) hipFree(p->d_items);
+    if (p->d_probs) hipFree(p->d_probs);
+    if (p->ws) hipFree(p->ws);
+    if (p->capture) hipStreamDestroy(p->capture);
+    delete p;
+}
+
+// Captures `enqueue(stream)` into an executable graph.
+template <typename F>
+hipError_t capture_graph(hipStream_t cap, hipGraphExec_t* exec, F&& enqueue)
+{
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return e;
+    hipError_t el = enqueue(cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cap, &g);
+    if (el != hipSuccess) e = el;
+    if (e == hipSuccess) e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    return e;
+}
+
+// Uploads the pointers of one call through the pinned staging buffer; waits
+// (host side) only for the previous upload from the same buffer.
+hipError_t stage_args(tsqr_batched_plan_s* p, tsqr::BatchArgs* h, tsqr::BatchArgs* d, hipEvent_t ev,
+                      double* const* A, const int64_t* lda, double* const* X, const int64_t* ldx)
+{
+    hipError_t e = hipEventSynchronize(ev);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < p->count; ++i) h[i] = tsqr::BatchArgs{A[i], lda[i], X[i], ldx[i]};
+    e = hipMemcpyAsync(d, h, sizeof(tsqr::BatchArgs) * p->count, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev, p->stream);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const int64_t* m, const int64_t* n,
+                                     tsqr_precision prec, const tsqr_opts* opts, void* hip_stream)
+{
+    if (!out) return -1;
+    *out = nullptr;
+    if (count < 1) return -2;
+    if (!m) return -3;
+    if (!n) return -4;
+    if (prec != TSQR_FP64 && prec != TSQR_MIXED) return -5;
+    tsqr_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.want_q = 1;
+    if (opts) {
+        o = *opts;
+        if (o.tree < TSQR_TREE_AUTO || o.tree > TSQR_TREE_HYBRID) return -6;
+        if (o.leaf_rows < 0 || o.tile_rows != 0 || o.flat_len < 0) return -6;
+        if (o.waves != 0 && o.waves != 1 && o.waves != 2 && o.waves != 4) return -6;
+        if (o.want_q != 0 && o.want_q != 1) return -6;
+    }
+    for (int i = 0; i < count; ++i) {
+        if (n[i] < 1 || m[i] < 1 || m[i] < n[i]) return -3;
+        if (n[i] > tsqr::kMaxN) return 3;
+    }
+    if (prec == TSQR_MIXED) return 3;  // batched plans are FP64
+
+    tsqr_batched_plan_s* p = new (std::nothrow) tsqr_batched_plan_s();
+    if (!p) return 2;
+    p->count = count;
+    p->prec = prec;
+    p->want_q = o.want_q;
+    p->waves = o.waves;
+    p->stream = (hipStream_t)hip_stream;
+    p->L.resize(count);
+    std::vector<tsqr::BatchProblem> bp(count);
+    int64_t off = 0;
+    for (int i = 0; i < count; ++i) {
+        tsqr::Layout& L = p->L[i];
+        if (!tsqr::make_layout(L, m[i], n[i], o.leaf_rows, o.flat_len, o.tree, o.waves, false) ||
+            L.levels >= tsqr::kBatchLevels) {
+            delete p;
+            return 3;
+        }
+        tsqr::BatchProblem& b = bp[i];
+        b.m = L.m;
+        b.n = (int)L.n;
+        b.levels = L.levels;
+        b.P = L.P;
+        b.leaf_rows = L.leaf_rows;
+        b.f = L.f;
+        b.ws_off = off;
+        b.off_T = L.off_T;
+        b.off_D = L.off_D;
+        for (int l = 0; l <= L.levels; ++l) {
+            b.off_R[l] = L.off_R[l];
+            b.off_S[l] = L.off_S[l];
+            b.off_Y[l] = L.off_Y[l];
+            b.off_TN[l] = L.off_TN[l];
+            b.count[l] = L.count[l];
+        }
+        off += L.total;
+    }
+    p->ws_doubles = off;
+
+    // width classes, largest problems first inside each (the persistent grids
+    // take items in order)
+    std::vector<int> widths;
+    for (int i = 0; i < count; ++i)
+        if (std::find(widths.begin(), widths.end(), p->L[i].np) == widths.end()) widths.push_back(p->L[i].np);
+    std::sort(widths.begin(), widths.end());
+    std::vector<std::vector<int64_t>> lists;  // host copies, concatenated below
+    struct ClassLists {
+        size_t leaf, root, level[tsqr::kBatchLevels];
+    };
+    std::vector<ClassLists> where;
+    for (int np : widths) {
+        std::vector<int> probs;
+        for (int i = 0; i < count; ++i)
+            if (p->L[i].np == np) probs.push_back(i);
+        std::stable_sort(probs.begin(), probs.end(), [&](int a, int b) { return p->L[a].m > p->L[b].m; });
+        tsqr::BatchClass C;
+        C.np = np;
+        C.nprob = (int64_t)probs.size();
+        ClassLists w{};
+        std::vector<int64_t> leaf, root;
+        for (int i : probs) {
+            for (int64_t q = 0; q < p->L[i].P; ++q) leaf.push_back(tsqr::batch_item(i, q));
+            root.push_back(tsqr::batch_item(i, 0));
+            C.max_levels = std::max(C.max_levels, p->L[i].levels);
+        }
+        C.n_leaf = (int64_t)leaf.size();
+        w.leaf = lists.size();
+        lists.push_back(leaf);
+        w.root = lists.size();
+        lists.push_back(root);
+        for (int l = 1; l <= C.max_levels; ++l) {
+            std::vector<int64_t> lv;
+            for (int i : probs)
+                if (p->L[i].levels >= l)
+                    for (int64_t q = 0; q < p->L[i].count[l]; ++q) lv.push_back(tsqr::batch_item(i, q));
+            C.n_level[l] = (int64_t)lv.size();
+            w.level[l] = lists.size();
+            lists.push_back(lv);
+        }
+        p->classes.push_back(C);
+        where.push_back(w);
+    }
+    std::vector<int64_t> all;
+    std::vector<size_t> start(lists.size());
+    for (size_t k = 0; k < lists.size(); ++k) {
+        start[k] = all.size();
+        all.insert(all.end(), lists[k].begin(), lists[k].end());
+    }
+
+    hipError_t e = hipMalloc((void**)&p->ws, (size_t)p->ws_doubles * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_probs, sizeof(tsqr::BatchProblem) * count);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, sizeof(int64_t) * std::max<size_t>(1, all.size()));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_args_f, sizeof(tsqr::BatchArgs) * count);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_args_q, sizeof(tsqr::BatchArgs) * count);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_args_f, sizeof(tsqr::BatchArgs) * count, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_args_q, sizeof(tsqr::BatchArgs) * count, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_f, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_q, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_probs, bp.data(), sizeof(tsqr::BatchProblem) * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !all.empty())
+        e = hipMemcpy(p->d_items, all.data(), sizeof(int64_t) * all.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        release(p);
+        return hstatus(e);
+    }
+    for (size_t c = 0; c < p->classes.size(); ++c) {
+        tsqr::BatchClass& C = p->classes[c];
+        C.leaf_items = p->d_items + start[where[c].leaf];
+        C.root_items = p->d_items + start[where[c].root];
+        for (int l = 1; l <= C.max_levels; ++l) C.level_items[l] = p->d_items + start[where[c].level[l]];
+    }
+    *out = p;
+    return 0;
+}
+
+tsqr_status tsqr_batched_factor(tsqr_batched_plan p, double* const* A, const int64_t* lda, double* const* R,
+                                const int64_t* ldr)
+{
+    if (!p) return -1;
+    if (!A) return -2;
+    if (!lda) return -3;
+    if (!R) return -4;
+    if (!ldr) return -5;
+    for (int i = 0; i < p->count; ++i) {
+        if (!A[i]) return -2;
+        if (lda[i] < p->L[i].m) return -3;
+        if (!R[i]) return -4;
+        if (ldr[i] < p->L[i].n) return -5;
+    }
+    p->state = 0;
+    hipError_t e = stage_args(p, p->h_args_f, p->d_args_f, p->ev_f, A, lda, R, ldr);
+    if (e == hipSuccess && !p->g_factor) {
+        e = capture_graph(p->capture, &p->g_factor, [&](hipStream_t s) {
+            for (const tsqr::BatchClass& C : p->classes) {
+                const int waves = p->waves > 0 ? p->waves : (C.np <= 32 ? 4 : 2);
+                hipError_t el = tsqr::launch_batch_factor(C, p->d_probs, p->d_args_f, p->ws, p->want_q != 0, waves, s);
+                if (el != hipSuccess) return el;
+            }
+            return hipSuccess;
+        });
+    }
+    if (e == hipSuccess) e = hipGraphLaunch(p->g_factor, p->stream);
+    if (e != hipSuccess) return hstatus(e);
+    p->state = p->want_q ? 1 : 2;
+    return 0;
+}
+
+tsqr_status tsqr_batched_form_q(tsqr_batched_plan p, double* const* A, const int64_t* lda, double* const* Q,
+                                const int64_t* ldq)
+{
+    if (!p) return -1;
+    if (!A) return -2;
+    if (!lda) return -3;
+    if (!Q) return -4;
+    if (!ldq) return -5;
+    for (int i = 0; i < p->count; ++i) {
+        if (!A[i]) return -2;
+        if (lda[i] < p->L[i].m) return -3;
+        if (!Q[i]) return -4;
+        if (ldq[i] < p->L[i].m) return -5;
+        if (Q[i] == A[i] && ldq[i] != lda[i]) return -5;
+    }
+    if (p->state != 1) return 4;
+    hipError_t e = stage_args(p, p->h_args_q, p->d_args_q, p->ev_q, A, lda, Q, ldq);
+    if (e == hipSuccess && !p->g_form_q) {
+        e = capture_graph(p->capture, &p->g_form_q, [&](hipStream_t s) {
+            for (const tsqr::BatchClass& C : p->classes) {
+                const int waves = p->waves > 0 ? p->waves : (C.np <= 32 ? 4 : 2);
+                hipError_t el = tsqr::launch_batch_form_q(C, p->d_probs, p->d_args_q, p->ws, waves, s);
+                if (el != hipSuccess) return el;
+            }
+            return hipSuccess;
+        });
+    }
+    if (e == hipSuccess) e = hipGraphLaunch(p->g_form_q, p->stream);
+    return hstatus(e);
+}
+
+tsqr_status tsqr_batched_problem_info(tsqr_batched_plan p, int index, tsqr_info* out)
+{
+    if (!p) return -1;
+    if (index < 0 || index >= p->count) return -2;
+    if (!out) return -3;
+    const tsqr::Layout& L = p->L[index];
+    std::memset(out, 0, sizeof(*out));
+    out->m = L.m;
+    out->n = L.n;
+    out->n_padded = L.np;
+    out->tile_rows = L.mt;
+    out->leaf_rows = L.leaf_rows;
+    out->num_leaves = L.P;
+    out->num_tiles = L.ntiles;
+    out->tree_levels = L.levels;
+    out->tree = L.P == 1 ? TSQR_TREE_FLAT : (L.f == 1 ? TSQR_TREE_BINARY : TSQR_TREE_HYBRID);
+    out->waves = p->waves > 0 ? p->waves : (L.np <= 32 ? 4 : 2);
+    out->precision = p->prec;
+    out->workspace_bytes = L.total * (int64_t)sizeof(double);
+    return 0;
+}
+
+tsqr_status tsqr_batched_plan_destroy(tsqr_batched_plan p)
+{
+    if (!p) return -1;
+    hipError_t e = hipStreamSynchronize(p->stream);
+    release(p);
+    return hstatus(e);
+}
+
+}  // extern "C"

@@ -109,4 +109,20 @@ hipError_t launch_reorth_q(const Layout& L, double* ws, double* Q, int64_t ldq, 
 #undef CALL
 }
 
+hipError_t launch_batch_factor(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                               bool want_q, int waves, hipStream_t s)
+{
+#define CALL(NP) batch_factor_np<NP>(C, probs, args, ws, want_q, waves, s)
+    TSQR_NP_SWITCH(C.np, CALL)
+#undef CALL
+}
+
+hipError_t launch_batch_form_q(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                               int waves, hipStream_t s)
+{
+#define CALL(NP) batch_form_q_np<NP>(C, probs, args, ws, waves, s)
+    TSQR_NP_SWITCH(C.np, CALL)
+#undef CALL
+}
+
 }  // namespace tsqr

@@ -66,6 +66,47 @@ struct Layout {
     int64_t total = 0;                      // doubles
 };
 
+// ---- batched problems -------------------------------------------------------
+constexpr int kBatchLevels = 32;
+
+// Static description of one problem of a batch (uploaded once per plan): its
+// geometry and the offsets of its workspace inside the plan's buffer.
+struct BatchProblem {
+    int64_t m = 0;
+    int n = 0, levels = 0;
+    int64_t P = 0, leaf_rows = 0, f = 0;
+    int64_t ws_off = 0;  // doubles
+    int64_t off_T = 0, off_D = 0;
+    int64_t off_R[kBatchLevels] = {0}, off_S[kBatchLevels] = {0};
+    int64_t off_Y[kBatchLevels] = {0}, off_TN[kBatchLevels] = {0};
+    int64_t count[kBatchLevels] = {0};
+};
+
+// Per-call matrices of one problem: A (factored in place) and the output
+// (R for the factorisation, Q for the explicit Q).
+struct BatchArgs {
+    double* A = nullptr;
+    int64_t lda = 0;
+    double* X = nullptr;
+    int64_t ldx = 0;
+};
+
+// Work items of the batched kernels: problem index in the high 32 bits,
+// leaf or node index in the low 32 bits.
+__host__ __device__ inline int64_t batch_item(int64_t p, int64_t i) { return (p << 32) | i; }
+
+// Device-side work lists of one width class (all problems with the same np).
+struct BatchClass {
+    int np = 0;
+    int64_t nprob = 0;
+    int max_levels = 0;
+    const int64_t* leaf_items = nullptr;  // (problem, leaf)
+    int64_t n_leaf = 0;
+    const int64_t* root_items = nullptr;  // (problem, 0)
+    const int64_t* level_items[kBatchLevels] = {nullptr};  // (problem, node) of level l >= 1
+    int64_t n_level[kBatchLevels] = {0};
+};
+
 // Fills the geometry.  Returns false for an unsupported shape.
 bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves,
                  bool mixed);
@@ -87,6 +128,12 @@ hipError_t launch_mixed_leaf(const Layout& L, const double* A, int64_t lda, doub
 hipError_t launch_form_q1(const Layout& L, double* ws, hipStream_t s);
 hipError_t launch_reorth(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s);
 hipError_t launch_reorth_q(const Layout& L, double* ws, double* Q, int64_t ldq, hipStream_t s);
+
+// batched FP64: every problem of a width class in one launch per phase
+hipError_t launch_batch_factor(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                               bool want_q, int waves, hipStream_t s);
+hipError_t launch_batch_form_q(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                               int waves, hipStream_t s);
 
 // Per-width launchers behind the dispatch (one instantiation per padded width).
 template <int NP>
@@ -112,5 +159,11 @@ template <int NP>
 hipError_t reorth_np(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s);
 template <int NP>
 hipError_t reorth_q_np(const Layout& L, double* ws, double* Q, int64_t ldq, hipStream_t s);
+template <int NP>
+hipError_t batch_factor_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                           bool want_q, int waves, hipStream_t s);
+template <int NP>
+hipError_t batch_form_q_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                           int waves, hipStream_t s);
 
 }  // namespace tsqr

@@ -476,22 +476,17 @@ __device__ __forceinline__ void store_tile(const E (&a)[RL][NP / LC], E* tb, int
 // running triangle R and the Gram entries of T stay FP64.  V goes to a
 // workspace of whole tiles (rows past m and columns past n are zeros) and T is
 // rounded to FP32.
-template <int NP, bool WANT_Q, typename E = double>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_leaf_factor(const double* A, int64_t lda, E* V, int64_t ldv,
-                                                     int64_t m, int n, int64_t P, int64_t leaf_rows, int64_t f,
-                                                     E* __restrict__ Ttile, double* __restrict__ Rleaf)
+template <int NP, bool WANT_Q, typename E>
+__device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, int64_t ldv, int64_t m, int n,
+                                           int64_t P, int64_t leaf_rows, int64_t f, E* __restrict__ Ttile,
+                                           double* __restrict__ Rleaf, int64_t leaf, double* wsm, int lane)
 {
     constexpr bool MIXED = sizeof(E) == 4;
     constexpr int LC = col_groups(NP), LR = 64 / LC, MT = tile_rows_e<E>(NP), RL = MT / LR, KC = NP / LC;
     constexpr int NT = packed_size(NP);
-    constexpr int WS = factor_lds_doubles<E>(NP, MT, WANT_Q);
     constexpr int GA = WANT_Q ? gram_area(NP) : 0;
-    extern __shared__ double smem[];
-    const int wave = wave_index(), lane = threadIdx.x & 63;
     const int cg = lane / LR, rg = lane % LR;
-    const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-    if (leaf >= P) return;
-    double* Rs = smem + wave * WS;
+    double* Rs = wsm;
     double* Gs = Rs + r_area(NP);
     E* vb = reinterpret_cast<E*>(Gs + GA);
     double* taus = Gs + GA + (LR * vb_stride_e<E>(RL) * (int)sizeof(E) + 7) / 8;
@@ -549,6 +544,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     }
 }
 
+template <int NP, bool WANT_Q, typename E = double>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_leaf_factor(const double* A, int64_t lda, E* V, int64_t ldv,
+                                                     int64_t m, int n, int64_t P, int64_t leaf_rows, int64_t f,
+                                                     E* __restrict__ Ttile, double* __restrict__ Rleaf)
+{
+    constexpr int WS = factor_lds_doubles<E>(NP, tile_rows_e<E>(NP), WANT_Q);
+    extern __shared__ double smem[];
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (leaf >= P) return;
+    leaf_chain<NP, WANT_Q, E>(A, lda, V, ldv, m, n, P, leaf_rows, f, Ttile, Rleaf, leaf, smem + wave * WS, lane);
+}
+
 // --------------------------------------------------------------------------
 // One level of the binary tree: node q stacks R_{2q} on R_{2q+1} (lower index
 // on top) and factors the pair; an odd last entry is passed up unchanged
@@ -556,21 +564,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 // broadcast of Q.
 // --------------------------------------------------------------------------
 template <int NP, bool WANT_Q>
-__global__ void __launch_bounds__(256) k_tree_level(const double* __restrict__ Rin, int64_t cin,
-                                                    double* __restrict__ Rout, double* __restrict__ Ynode,
-                                                    double* __restrict__ Tnode, int64_t cout)
+__device__ __forceinline__ void tree_node(const double* __restrict__ Rin, int64_t cin, double* __restrict__ Rout,
+                                          double* __restrict__ Ynode, double* __restrict__ Tnode, int64_t q,
+                                          double* wsm, int lane)
 {
     constexpr int LC = col_groups(NP), LR = 64 / LC, KC = NP / LC;
     // the node tile holds R_b (NP rows), padded with zero rows to whole 16-row
     // chunks of gram_mfma
-    constexpr int RLN = round16(NP) / LR, MTN = LR * RLN, NT = packed_size(NP);
-    constexpr int WS = factor_lds_doubles<double>(NP, MTN, WANT_Q);
+    constexpr int RLN = round16(NP) / LR, NT = packed_size(NP);
     constexpr int GA = WANT_Q ? gram_area(NP) : 0;
-    extern __shared__ double smem[];
-    const int wave = wave_index(), lane = threadIdx.x & 63;
     const int cg = lane / LR, rg = lane % LR;
-    const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-    if (q >= cout) return;
     const int64_t ia = 2 * q, ib = 2 * q + 1;
     const double* Ra = Rin + ia * NP * NP;
     double* Ro = Rout + q * NP * NP;
@@ -578,7 +581,7 @@ __global__ void __launch_bounds__(256) k_tree_level(const double* __restrict__ R
         for (int idx = lane; idx < NP * NP; idx += 64) Ro[idx] = Ra[idx];
         return;
     }
-    double* Rs = smem + wave * WS;
+    double* Rs = wsm;
     double* Gs = Rs + r_area(NP);
     double* vb = Gs + GA;
     double* taus = vb + LR * vb_stride(RLN);
@@ -620,15 +623,27 @@ __global__ void __launch_bounds__(256) k_tree_level(const double* __restrict__ R
     }
 }
 
+template <int NP, bool WANT_Q>
+__global__ void __launch_bounds__(256) k_tree_level(const double* __restrict__ Rin, int64_t cin,
+                                                    double* __restrict__ Rout, double* __restrict__ Ynode,
+                                                    double* __restrict__ Tnode, int64_t cout)
+{
+    constexpr int WS = factor_lds_doubles<double>(NP, round16(NP), WANT_Q);
+    extern __shared__ double smem[];
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (q >= cout) return;
+    tree_node<NP, WANT_Q>(Rin, cin, Rout, Ynode, Tnode, q, smem + wave * WS, lane);
+}
+
 // --------------------------------------------------------------------------
 // Root: signs D = diag(sgn(R_jj)) (sgn(0) = +1), the user's R = D R with its
 // strictly lower part zeroed, and the root seed diag(D) of the broadcast.
 // --------------------------------------------------------------------------
 template <int NP>
-__global__ void __launch_bounds__(64) k_root(const double* __restrict__ Rroot, int n, double* __restrict__ R,
-                                             int64_t ldr, double* __restrict__ Dsig, double* __restrict__ Sroot)
+__device__ __forceinline__ void root_body(const double* __restrict__ Rroot, int n, double* __restrict__ R,
+                                          int64_t ldr, double* __restrict__ Dsig, double* __restrict__ Sroot, int lane)
 {
-    const int lane = threadIdx.x;
     for (int idx = lane; idx < NP * NP; idx += 64) {
         const int i = idx % NP, j = idx / NP;
         const double di = Rroot[i + i * NP] < 0.0 ? -1.0 : 1.0;
@@ -636,6 +651,13 @@ __global__ void __launch_bounds__(64) k_root(const double* __restrict__ Rroot, i
         if (Sroot) Sroot[idx] = (i == j) ? di : 0.0;
     }
     if (lane < NP) Dsig[lane] = Rroot[lane + lane * NP] < 0.0 ? -1.0 : 1.0;
+}
+
+template <int NP>
+__global__ void __launch_bounds__(64) k_root(const double* __restrict__ Rroot, int n, double* __restrict__ R,
+                                             int64_t ldr, double* __restrict__ Dsig, double* __restrict__ Sroot)
+{
+    root_body<NP>(Rroot, n, R, ldr, Dsig, Sroot, threadIdx.x);
 }
 
 // The 16x16x4 matrix-core op in FP64 or FP32.  Both take A(i, k) from lane
@@ -734,15 +756,12 @@ __device__ __forceinline__ void store_seed(double* __restrict__ S, const double 
 // (from (I - [I; Y1] T [I; Y1]^T) [S; 0]).  A pass-through node hands S down.
 // --------------------------------------------------------------------------
 template <int NP>
-__global__ void __launch_bounds__(256) k_seed_level(const double* __restrict__ Sp, const double* __restrict__ Ynode,
-                                                    const double* __restrict__ Tnode, int64_t cin,
-                                                    double* __restrict__ Sc, int64_t cout)
+__device__ __forceinline__ void seed_node(const double* __restrict__ Sp, const double* __restrict__ Ynode,
+                                          const double* __restrict__ Tnode, int64_t cin, double* __restrict__ Sc,
+                                          int64_t q, int lane)
 {
     constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, NT = packed_size(NP);
-    const int wave = wave_index(), lane = threadIdx.x & 63;
     const int cg = lane >> 4, rg = lane & 15;
-    const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-    if (q >= cout) return;
     const int64_t ia = 2 * q, ib = 2 * q + 1;
     const double* S = Sp + q * NP * NP;
     if (ib >= cin) {
@@ -782,6 +801,17 @@ __global__ void __launch_bounds__(256) k_seed_level(const double* __restrict__ S
     }
 }
 
+template <int NP>
+__global__ void __launch_bounds__(256) k_seed_level(const double* __restrict__ Sp, const double* __restrict__ Ynode,
+                                                    const double* __restrict__ Tnode, int64_t cin,
+                                                    double* __restrict__ Sc, int64_t cout)
+{
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (q >= cout) return;
+    seed_node<NP>(Sp, Ynode, Tnode, cin, Sc, q, lane);
+}
+
 // --------------------------------------------------------------------------
 // Q kernel: a leaf's chain replayed from the last tile to the first.
 // Tile k > 0: Z = T_k S_k, Q_k = -Y_k Z, S_{k-1} = S_k - Z.
@@ -799,10 +829,10 @@ constexpr int fq_col_blocks(int np) { return round16(np) / 16 <= 3 ? round16(np)
 // round16(NP) columns (rows past m hold values of zero rows of V; columns past
 // n are zero).  Rows past m and columns past n of V are zeros there too, so
 // no load or store needs a mask.
-template <int NP, bool WIDE, typename E = double>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_form_q(const E* V, int64_t lda, int64_t m, int n, int64_t P,
-                                                int64_t leaf_rows, int64_t f, const E* __restrict__ Ttile,
-                                                const double* __restrict__ Sleaf, E* Q, int64_t ldq)
+template <int NP, bool WIDE, typename E>
+__device__ __forceinline__ void form_q_leaf(const E* V, int64_t lda, int64_t m, int n, int64_t P, int64_t leaf_rows,
+                                            int64_t f, const E* __restrict__ Ttile, const double* __restrict__ Sleaf,
+                                            E* Q, int64_t ldq, int64_t leaf, int j0, E* Ss, int lane)
 {
     constexpr bool MIXED = sizeof(E) == 4;
     constexpr int MT = tile_rows_e<E>(NP), RL = MT / 16, KC = NP / 4;
@@ -814,17 +844,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     constexpr int FQU = NP > 48 ? 1 : 2;  // row blocks in flight; more spills at the widest tiles
     static_assert(JB % JW == 0, "column window must divide the padded width");
     typedef Mfma<E> MM;
-    extern __shared__ double smem_d[];
-    E* smem = reinterpret_cast<E*>(smem_d);
-    const int wave = wave_index(), lane = threadIdx.x & 63;
     const int cg = lane >> 4, rg = lane & 15;
-    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-    const int64_t leaf = gw / SPLIT;
-    const int j0 = (int)(gw % SPLIT) * JW;
-    if (leaf >= P) return;
     // the seed window lives in LDS between tile steps (each lane owns the
     // elements of its register layout); at tile 0 it is S_0 for the [S_0; 0] term
-    E* Ss = smem + wave * NPB * 16 * JW;
 
     const int64_t row0 = leaf * leaf_rows;
     const int64_t rows = (leaf == P - 1) ? (m - row0) : leaf_rows;
@@ -949,6 +971,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             }
         }
     }
+}
+
+template <int NP, bool WIDE, typename E = double>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_form_q(const E* V, int64_t lda, int64_t m, int n, int64_t P,
+                                                int64_t leaf_rows, int64_t f, const E* __restrict__ Ttile,
+                                                const double* __restrict__ Sleaf, E* Q, int64_t ldq)
+{
+    constexpr int NPB = round16(NP), JW = fq_col_blocks(NP), SPLIT = NPB / 16 / JW;
+    extern __shared__ double smem_d[];
+    E* smem = reinterpret_cast<E*>(smem_d);
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    const int64_t leaf = gw / SPLIT;
+    const int j0 = (int)(gw % SPLIT) * JW;
+    if (leaf >= P) return;
+    form_q_leaf<NP, WIDE, E>(V, lda, m, n, P, leaf_rows, f, Ttile, Sleaf, Q, ldq, leaf, j0,
+                             smem + wave * NPB * 16 * JW, lane);
 }
 
 // --------------------------------------------------------------------------
@@ -1548,6 +1587,169 @@ hipError_t apply_qt_np(const Layout& L, const double* A, int64_t lda, int64_t k,
     return hipSuccess;
 }
 
+// ---- batched problems ------------------------------------------------------
+// Persistent grids: every wavefront walks a device work list (grid stride), so
+// one launch covers the leaves (or the nodes of one tree level) of every
+// problem of a width class.  The per-item work is that of the single-problem
+// kernels.
+
+template <int NP, bool WANT_Q>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_leaf_batch(const BatchProblem* __restrict__ probs,
+                                                    const BatchArgs* __restrict__ args, double* ws,
+                                                    const int64_t* __restrict__ items, int64_t nitems)
+{
+    constexpr int WS = factor_lds_doubles<double>(NP, tile_rows_for(NP), WANT_Q);
+    extern __shared__ double smem[];
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < nitems; it += nw) {
+        const int64_t item = items[it];
+        const int64_t p = item >> 32, leaf = item & 0xffffffff;
+        const BatchProblem& B = probs[p];
+        const BatchArgs X = args[p];
+        double* w = ws + B.ws_off;
+        leaf_chain<NP, WANT_Q, double>(X.A, X.lda, X.A, X.lda, B.m, B.n, B.P, B.leaf_rows, B.f, w + B.off_T,
+                                       w + B.off_R[0], leaf, smem + wave * WS, lane);
+        __builtin_amdgcn_wave_barrier();  // the next item rewrites this wave's LDS
+    }
+}
+
+template <int NP, bool WANT_Q>
+__global__ void __launch_bounds__(256) k_tree_batch(const BatchProblem* __restrict__ probs, double* ws,
+                                                    const int64_t* __restrict__ items, int64_t nitems, int l)
+{
+    constexpr int WS = factor_lds_doubles<double>(NP, round16(NP), WANT_Q);
+    extern __shared__ double smem[];
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < nitems; it += nw) {
+        const int64_t item = items[it];
+        const int64_t p = item >> 32, q = item & 0xffffffff;
+        const BatchProblem& B = probs[p];
+        double* w = ws + B.ws_off;
+        tree_node<NP, WANT_Q>(w + B.off_R[l - 1], B.count[l - 1], w + B.off_R[l], w + B.off_Y[l], w + B.off_TN[l],
+                              q, smem + wave * WS, lane);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+template <int NP>
+__global__ void __launch_bounds__(256) k_root_batch(const BatchProblem* __restrict__ probs,
+                                                    const BatchArgs* __restrict__ args, double* ws,
+                                                    const int64_t* __restrict__ items, int64_t nitems, int want_q)
+{
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < nitems; it += nw) {
+        const int64_t p = items[it] >> 32;
+        const BatchProblem& B = probs[p];
+        const BatchArgs X = args[p];
+        double* w = ws + B.ws_off;
+        root_body<NP>(w + B.off_R[B.levels], B.n, X.X, X.ldx, w + B.off_D, want_q ? w + B.off_S[B.levels] : nullptr,
+                      lane);
+    }
+}
+
+template <int NP>
+__global__ void __launch_bounds__(256) k_seed_batch(const BatchProblem* __restrict__ probs, double* ws,
+                                                    const int64_t* __restrict__ items, int64_t nitems, int l)
+{
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < nitems; it += nw) {
+        const int64_t item = items[it];
+        const int64_t p = item >> 32, q = item & 0xffffffff;
+        const BatchProblem& B = probs[p];
+        double* w = ws + B.ws_off;
+        seed_node<NP>(w + B.off_S[l], w + B.off_Y[l], w + B.off_TN[l], B.count[l - 1], w + B.off_S[l - 1], q, lane);
+    }
+}
+
+template <int NP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_form_q_batch(const BatchProblem* __restrict__ probs,
+                                                    const BatchArgs* __restrict__ args, double* ws,
+                                                    const int64_t* __restrict__ items, int64_t nitems)
+{
+    constexpr int NPB = round16(NP), JW = fq_col_blocks(NP), SPLIT = NPB / 16 / JW;
+    extern __shared__ double smem[];
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < nitems * SPLIT; it += nw) {
+        const int64_t item = items[it / SPLIT];
+        const int j0 = (int)(it % SPLIT) * JW;
+        const int64_t p = item >> 32, leaf = item & 0xffffffff;
+        const BatchProblem& B = probs[p];
+        const BatchArgs X = args[p];
+        double* w = ws + B.ws_off;
+        form_q_leaf<NP, true, double>(X.A, X.lda, B.m, B.n, B.P, B.leaf_rows, B.f, w + B.off_T, w + B.off_S[0],
+                                      X.X, X.ldx, leaf, j0, smem + wave * NPB * 16 * JW, lane);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Grid of a persistent batched launch: enough waves to fill the device at two
+// per SIMD, never more than there are items.
+inline unsigned batch_grid(int64_t items, int waves)
+{
+    const int64_t cap = 256 * 8 / waves;  // 256 CUs, 8 waves each
+    const int64_t need = (items + waves - 1) / waves;
+    return (unsigned)(need < cap ? (need > 0 ? need : 1) : cap);
+}
+
+template <int NP>
+hipError_t batch_factor_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                           bool want_q, int waves, hipStream_t s)
+{
+    {
+        const size_t lds = (size_t)waves * factor_lds_doubles(NP, tile_rows_for(NP), want_q) * sizeof(double);
+        const dim3 grid(batch_grid(C.n_leaf, waves)), block(64 * waves);
+        if (want_q) {
+            allow_lds(k_leaf_batch<NP, true>, lds);
+            hipLaunchKernelGGL((k_leaf_batch<NP, true>), grid, block, lds, s, probs, args, ws, C.leaf_items, C.n_leaf);
+        } else {
+            allow_lds(k_leaf_batch<NP, false>, lds);
+            hipLaunchKernelGGL((k_leaf_batch<NP, false>), grid, block, lds, s, probs, args, ws, C.leaf_items, C.n_leaf);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int tw = NP <= 32 ? 4 : 2;
+    const size_t tlds = (size_t)tw * factor_lds_doubles(NP, round16(NP), want_q) * sizeof(double);
+    for (int l = 1; l <= C.max_levels; ++l) {
+        const dim3 grid(batch_grid(C.n_level[l], tw)), block(64 * tw);
+        if (want_q) {
+            allow_lds(k_tree_batch<NP, true>, tlds);
+            hipLaunchKernelGGL((k_tree_batch<NP, true>), grid, block, tlds, s, probs, ws, C.level_items[l], C.n_level[l], l);
+        } else {
+            allow_lds(k_tree_batch<NP, false>, tlds);
+            hipLaunchKernelGGL((k_tree_batch<NP, false>), grid, block, tlds, s, probs, ws, C.level_items[l], C.n_level[l], l);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_root_batch<NP>), dim3(batch_grid(C.nprob, 4)), dim3(256), 0, s, probs, args, ws,
+                       C.root_items, C.nprob, want_q ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <int NP>
+hipError_t batch_form_q_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                           int waves, hipStream_t s)
+{
+    for (int l = C.max_levels; l >= 1; --l) {
+        hipLaunchKernelGGL((k_seed_batch<NP>), dim3(batch_grid(C.n_level[l], 4)), dim3(256), 0, s, probs, ws,
+                           C.level_items[l], C.n_level[l], l);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    constexpr int NPB = round16(NP), JW = fq_col_blocks(NP), SPLIT = NPB / 16 / JW;
+    const size_t lds = (size_t)waves * NPB * 16 * JW * sizeof(double);
+    allow_lds(k_form_q_batch<NP>, lds);
+    hipLaunchKernelGGL((k_form_q_batch<NP>), dim3(batch_grid(C.n_leaf * SPLIT, waves)), dim3(64 * waves), lds, s,
+                       probs, args, ws, C.leaf_items, C.n_leaf);
+    return hipGetLastError();
+}
+
 // ---- mixed precision -------------------------------------------------------
 
 // True when the byte offset of element (15, 12) of a 16 x 16 FP32 block with
@@ -1686,6 +1888,19 @@ hipError_t reorth_q_np(const Layout& L, double* ws, double* Q, int64_t ldq, hipS
     return detail::reorth_q_np<NP>(L, ws, Q, ldq, s);
 }
 
+template <int NP>
+hipError_t batch_factor_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                           bool want_q, int waves, hipStream_t s)
+{
+    return detail::batch_factor_np<NP>(C, probs, args, ws, want_q, waves, s);
+}
+template <int NP>
+hipError_t batch_form_q_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                           int waves, hipStream_t s)
+{
+    return detail::batch_form_q_np<NP>(C, probs, args, ws, waves, s);
+}
+
 // Every per-width launcher of one padded width (used by the tsqr_np_*.hip units).
 #define TSQR_INSTANTIATE(NP)                                                                                   \
     template hipError_t leaf_factor_np<NP>(const Layout&, const double*, int64_t, double*, int64_t, double*, bool, \
@@ -1700,6 +1915,10 @@ hipError_t reorth_q_np(const Layout& L, double* ws, double* Q, int64_t ldq, hipS
     template hipError_t mixed_leaf_np<NP>(const Layout&, const double*, int64_t, double*, bool, hipStream_t);  \
     template hipError_t form_q1_np<NP>(const Layout&, double*, hipStream_t);                                   \
     template hipError_t reorth_np<NP>(const Layout&, double*, double*, int64_t, hipStream_t);                  \
-    template hipError_t reorth_q_np<NP>(const Layout&, double*, double*, int64_t, hipStream_t);
+    template hipError_t reorth_q_np<NP>(const Layout&, double*, double*, int64_t, hipStream_t);                \
+    template hipError_t batch_factor_np<NP>(const BatchClass&, const BatchProblem*, const BatchArgs*, double*,  \
+                                            bool, int, hipStream_t);                                          \
+    template hipError_t batch_form_q_np<NP>(const BatchClass&, const BatchProblem*, const BatchArgs*, double*,  \
+                                            int, hipStream_t);
 
 }  // namespace tsqr

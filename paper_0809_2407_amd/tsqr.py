@@ -153,6 +153,76 @@ class Plan:
         return B
 
 
+class BatchedPlan:
+    """tsqr_batched_plan_create / tsqr_batched_factor / tsqr_batched_form_q /
+    tsqr_batched_problem_info / tsqr_batched_plan_destroy for a list of
+    problem sizes."""
+
+    def __init__(self, ms, ns, precision: str = "fp64", tree: str = "auto", leaf_rows: int = 0,
+                 flat_len: int = 0, waves: int = 0, want_q: bool = True, stream=None):
+        self._lib = _lib.load()
+        self.ms = [int(x) for x in ms]
+        self.ns = [int(x) for x in ns]
+        if len(self.ms) != len(self.ns):
+            raise ValueError("ms and ns differ in length")
+        self.count = len(self.ms)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        opts = TsqrOpts(_TREES[tree], int(leaf_rows), 0, int(flat_len), int(waves), 1 if want_q else 0)
+        I64 = ctypes.c_int64 * self.count
+        h = ctypes.c_void_p()
+        check("tsqr_batched_plan_create",
+              self._lib.tsqr_batched_plan_create(ctypes.byref(h), self.count, I64(*self.ms), I64(*self.ns),
+                                                 _PREC[precision], ctypes.byref(opts), _stream_handle(self.stream)))
+        self._h = h
+
+    def _arrays(self, mats, rows, name):
+        if len(mats) != self.count:
+            raise ValueError(f"{name}: {self.count} matrices expected")
+        ptrs = (ctypes.c_void_p * self.count)(*[X.data_ptr() for X in mats])
+        lds = (ctypes.c_int64 * self.count)(*[_ld(X, r, name) for X, r in zip(mats, rows)])
+        return ptrs, lds
+
+    def factor(self, As, Rs=None):
+        """Factor every A (column-major, overwritten by the reflectors); returns the R's."""
+        if Rs is None:
+            Rs = [colmajor(n, n, device=A.device) for A, n in zip(As, self.ns)]
+        ap, al = self._arrays(As, self.ms, "A")
+        rp, rl = self._arrays(Rs, self.ns, "R")
+        check("tsqr_batched_factor", self._lib.tsqr_batched_factor(self._h, ap, al, rp, rl))
+        return Rs
+
+    def form_q(self, As, Qs=None):
+        if Qs is None:
+            Qs = [colmajor(m, n, device=A.device) for A, m, n in zip(As, self.ms, self.ns)]
+        ap, al = self._arrays(As, self.ms, "A")
+        qp, ql = self._arrays(Qs, self.ms, "Q")
+        check("tsqr_batched_form_q", self._lib.tsqr_batched_form_q(self._h, ap, al, qp, ql))
+        return Qs
+
+    def problem_info(self, i: int) -> dict:
+        out = TsqrInfo()
+        check("tsqr_batched_problem_info", self._lib.tsqr_batched_problem_info(self._h, int(i), ctypes.byref(out)))
+        return {f: getattr(out, f) for f, _ in TsqrInfo._fields_}
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            check("tsqr_batched_plan_destroy", self._lib.tsqr_batched_plan_destroy(h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 def qr(A: torch.Tensor, **plan_kw):
     """Thin QR of a column-major device matrix: returns (Q, R); A is overwritten
     by the reflectors."""

@@ -107,3 +107,21 @@ def test_levels_match_binary_pairing():
             c = (c + 1) // 2
             L += 1
         assert q["tree_levels"] == L
+
+
+def test_batched_argument_errors_without_device():
+    from paper_0809_2407_amd import _lib
+    lib = _lib.load()
+    P = ctypes.c_void_p()
+    I64 = ctypes.c_int64 * 2
+    ms, ns = I64(100, 200), I64(8, 16)
+    assert lib.tsqr_batched_plan_create(None, 2, ms, ns, 0, None, None) == -1
+    assert lib.tsqr_batched_plan_create(ctypes.byref(P), 0, ms, ns, 0, None, None) == -2
+    assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, None, ns, 0, None, None) == -3
+    assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, ms, None, 0, None, None) == -4
+    assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, ms, ns, 7, None, None) == -5
+    assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, I64(100, 10), ns, 0, None, None) == -3
+    assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, ms, I64(8, 65), 0, None, None) == 3
+    assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, ms, ns, 1, None, None) == 3
+    assert lib.tsqr_batched_factor(None, None, None, None, None) == -1
+    assert lib.tsqr_batched_plan_destroy(None) == -1
