@@ -43,6 +43,14 @@ WORKLOADS = {
 }
 DEFAULT = "tsqr_fp64_rq_m16777216_n32_kappa1e12"
 
+# Many independent problems: m_i uniform on 1000..200000, n_i uniform on
+# {8, 16, 32, 64}, entries iid N(0,1); one batched plan (captured graph) against
+# a loop of single-problem calls on the same stream.
+BATCHED = {
+    "tsqr_batched_fp64_rq_p2048_m1000_200000_n8_64": dict(count=2048, m_lo=1000, m_hi=200000, ns=(8, 16, 32, 64)),
+    "tsqr_batched_fp64_rq_p256_m1000_200000_n8_64": dict(count=256, m_lo=1000, m_hi=200000, ns=(8, 16, 32, 64)),
+}
+
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -143,7 +151,7 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(BATCHED))
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 24)
@@ -164,6 +172,8 @@ def main(argv=None) -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU"}))
         return 1
+    if args.workload in BATCHED:
+        return run_batched(args)
     w = dict(WORKLOADS[args.workload])
     m, n, mode = w["m"], w["n"], w["mode"]
     log(f"workload {args.workload}: generating input")
@@ -278,6 +288,127 @@ def main(argv=None) -> int:
         result["cpu_baseline"] = None
 
     plan.close()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def run_batched(args) -> int:
+    """One step = R and explicit Q of every problem of the batch: one replay of
+    the batched plan's factor graph and one of its Q graph.  The loop of single
+    calls does the same problems one plan at a time.  A is regenerated before
+    every step (outside the timed events: the factorisation overwrites it)."""
+    import numpy as np
+    import torch
+    from paper_0809_2407_amd import tsqr as T
+
+    w = BATCHED[args.workload]
+    rng = np.random.default_rng(args.seed)
+    ms = [int(x) for x in rng.integers(w["m_lo"], w["m_hi"] + 1, size=w["count"])]
+    ns = [int(x) for x in rng.choice(w["ns"], size=w["count"])]
+    fl = sum(flops_rq(m, n) for m, n in zip(ms, ns))
+    entries = sum(m * n for m, n in zip(ms, ns))
+    log(f"batched workload {args.workload}: {w['count']} problems, {entries * 8 / 1e9:.1f} GB per matrix set")
+    g = torch.Generator(device="cuda")
+    As = [T.colmajor(m, n) for m, n in zip(ms, ns)]
+    Qs = [T.colmajor(m, n) for m, n in zip(ms, ns)]
+
+    def fill(A, step, i):
+        g.manual_seed((args.seed * 1000 + step) * 8192 + i)
+        A.normal_(generator=g)
+
+    def regenerate(step):
+        for i, A in enumerate(As):
+            fill(A, step, i)
+
+    bp = T.BatchedPlan(ms, ns)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+
+    def batched_step():
+        bp.factor(As)
+        bp.form_q(As, Qs)
+
+    for i in range(args.warmup):
+        regenerate(i)
+        batched_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        regenerate(100 + i)
+        ev[i][0].record()
+        batched_step()
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    log(f"batched: {b_ms:.3f} ms/step (events), wall {wall * 1e3 / args.steps:.1f} ms/step with regeneration")
+
+    # accuracy on a sample of problems of the last step (against the regenerated input)
+    regen_check = {}
+    sample = list(range(0, w["count"], max(1, w["count"] // 16)))
+    worst_b = worst_o = 0.0
+    if not args.no_check:
+        # the sampled problems' inputs again, into fresh buffers, for the residuals
+        last = 100 + args.steps - 1
+        A0 = {}
+        for i in sample:
+            A0[i] = torch.empty_like(As[i])
+            fill(A0[i], last, i)
+        regenerate(last)
+        Rs = bp.factor(As)
+        bp.form_q(As, Qs)
+        torch.cuda.synchronize()
+        for i in sample:
+            A, Q, R = A0[i], Qs[i], Rs[i]
+            bwd = float(torch.linalg.norm(torch.addmm(A, Q, R, alpha=-1.0)) / torch.linalg.norm(A))
+            G = sum(Q[r:r + 4096].t() @ Q[r:r + 4096] for r in range(0, ms[i], 4096))  # blocked Gram
+            orth = float(torch.linalg.norm(G - torch.eye(ns[i], dtype=G.dtype, device=G.device)))
+            worst_b, worst_o = max(worst_b, bwd / (20 * ns[i] * 2.0 ** -53)), max(worst_o, orth / (20 * ns[i] * 2.0 ** -53))
+        regen_check = {"sampled_problems": len(sample), "max_backward_over_bound": worst_b,
+                       "max_orthogonality_over_bound": worst_o}
+        log(f"accuracy {regen_check}")
+        del A0
+
+    # the loop of single calls on the same problems
+    plans = [T.Plan(m, n) for m, n in zip(ms, ns)]
+
+    def loop_step():
+        for p, A, Q in zip(plans, As, Qs):
+            p.factor(A)
+            p.form_q(A, Q)
+
+    regenerate(0)
+    loop_step()
+    torch.cuda.synchronize()
+    lev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for i in range(args.steps):
+        regenerate(100 + i)
+        lev[i][0].record()
+        loop_step()
+        lev[i][1].record()
+    torch.cuda.synchronize()
+    l_ms = sum(a.elapsed_time(b) for a, b in lev) / args.steps
+    log(f"loop of single calls: {l_ms:.3f} ms/step")
+    for p in plans:
+        p.close()
+
+    result = {
+        "metric": "TSQR R+Q GFLOP/s & % roofline; mixed/batched vs FP64 at stated backward error",
+        "value": fl / (b_ms * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": b_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "problems": w["count"], "m_range": [w["m_lo"], w["m_hi"]],
+                   "n_choices": list(w["ns"]), "seed": args.seed, "sum_mn": entries, "flops": fl,
+                   "parallelism": "single GPU"},
+        "loop_of_single_calls": {"ms_per_step": l_ms, "value": fl / (l_ms * 1e-3) / 1e9,
+                                 "batched_speedup": l_ms / b_ms},
+        "path_roofline": {"t_roof_ms": max(fl / (FP64_PEAK_TFLOPS * 1e12), 32.0 * entries / (HBM_PEAK_GBS * 1e9)) * 1e3,
+                          "bytes": 32.0 * entries, "flops": fl},
+        "accuracy": regen_check or None,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    result["path_roofline"]["frac"] = result["path_roofline"]["t_roof_ms"] / b_ms
+    bp.close()
     print(json.dumps(result), flush=True)
     return 0
 

@@ -36,9 +36,13 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
     } else if (tree == TSQR_TREE_HYBRID && flat_len > 0) {
         f = flat_len;
     } else {
-        // automatic: about 4096 leaves, chains of 1..64 tiles
+        // automatic: about 4096 leaves, chains of 1..64 tiles, and chains long
+        // enough that the per-leaf factors (R, seed, node Y and T: about 4 np^2
+        // doubles) stay under a quarter of the leaf's f * mt * n doubles
         f = tiles_total / 4096;
-        f = std::max<int64_t>(1, std::min<int64_t>(64, f));
+        const int64_t f_mem = (16 * (int64_t)L.np * L.np + L.mt * n - 1) / (L.mt * n);
+        f = std::max<int64_t>(std::max<int64_t>(1, f_mem), std::min<int64_t>(64, f));
+        f = std::min<int64_t>(f, std::max<int64_t>(1, tiles_total));
     }
     if (f < 1) f = 1;
     L.f = f;
