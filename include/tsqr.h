@@ -21,7 +21,8 @@
  *   - Status codes: 0 = success; -i = argument i (1-based, in the order of the
  *     prototype) is invalid (LAPACK "info" style); 1 = HIP runtime error,
  *     2 = device memory exhausted, 3 = unsupported case, 4 = call out of order
- *     (e.g. tsqr_form_q before tsqr_factor).
+ *     (e.g. tsqr_form_q before tsqr_factor), 5 = class not in the autotune
+ *     cache.
  *   - NaN or Inf entries propagate; nothing checks for them.
  *   - A plan is not thread-safe.  Different plans are independent.
  *   - Householder conventions: H_j = I - tau_j v_j v_j^T with v_j(j) = 1,
@@ -199,6 +200,52 @@ tsqr_status tsqr_plan_timings(tsqr_plan p, tsqr_timings* out);
 
 /* Free the plan and its workspace (synchronises its stream first). */
 tsqr_status tsqr_plan_destroy(tsqr_plan p);
+
+/* ---- Autotuner --------------------------------------------------------------
+ * Per problem class -- n, the m bucket floor(log2 m), the precision, and R
+ * only or R + Q -- the tuner times candidate geometries on the device and keeps
+ * the fastest: the leaf length (tiles per flat chain: 1 = binary tree over the
+ * tiles, longer = hybrid, every tile = one flat chain) and the wavefronts per
+ * workgroup of the leaf and Q kernels (1, 2 or 4).  The tile height is fixed
+ * by n (it sizes the register-resident tile) and the leaf update is
+ * unblocked, so neither is searched.  Accuracy guard: chains (and the flat
+ * tree) are capped at 256 tiles, since rounding accumulates along a chain
+ * (the flat tree is the least accurate shape of Sec. 2).  The choice of the
+ * best tree is left open by the paper; this search is the library's own.
+ *
+ * Results are cached in a JSON file ({"entries": {class: {"tree", "leaf_rows",
+ * "flat_len", "waves", "want_q", "ms"}}}).  tsqr_plan_create and
+ * tsqr_batched_plan_create called with opts == NULL take the cached options of
+ * their class when the environment variable TSQR_TUNE_CACHE names such a
+ * file. */
+typedef struct {
+    tsqr_opts opts;  /* the fastest candidate (or the cached one) */
+    double ms;       /* its device time for one factorisation (+ explicit Q) */
+    int candidates;  /* candidates timed (0 when read from the cache) */
+    int from_cache;  /* 1 when the class was found in the cache */
+} tsqr_tune_result;
+
+/* Tune the class of (m, n, prec, want_q).  scratch (m x n, ld >= m, device) is
+ * only read; NULL makes the tuner allocate and fill its own.  Each candidate
+ * runs reps + 1 times (the first untimed) on hip_stream; the call
+ * synchronises.  With cache_path, a cached class is returned at once and a
+ * tuned one is stored.  Errors: -1 m, -2 n, -3 prec, -4 want_q, -6 ld < m,
+ * -9 reps < 1, -10 out NULL; 3 n > 64 or no candidate ran; 1 HIP error or an
+ * unwritable cache. */
+tsqr_status tsqr_autotune(int64_t m, int64_t n, tsqr_precision prec, int want_q, double* scratch, int64_t ld,
+                          void* hip_stream, const char* cache_path, int reps, tsqr_tune_result* out);
+
+/* Cached options of the class of (m, n, prec, want_q), and their time when ms
+ * is not NULL.  Host only.  Errors: -1 path NULL, -2 m, -3 n, -4 prec,
+ * -5 want_q, -6 out NULL; 5 when the class is not in the cache. */
+tsqr_status tsqr_tune_cache_lookup(const char* cache_path, int64_t m, int64_t n, tsqr_precision prec, int want_q,
+                                   tsqr_opts* out, double* ms);
+
+/* Store (or replace) the options of a class in the cache file.  Host only.
+ * Errors: -1 path NULL, -2 m, -3 n, -4 prec, -5 opts NULL or bad want_q;
+ * 1 when the file cannot be written. */
+tsqr_status tsqr_tune_cache_store(const char* cache_path, int64_t m, int64_t n, tsqr_precision prec,
+                                  const tsqr_opts* opts, double ms);
 
 /* ---- Batched plans --------------------------------------------------------
  * Many independent problems (A_i m_i x n_i, n_i <= 64) factored together: the

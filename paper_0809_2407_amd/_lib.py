@@ -33,6 +33,11 @@ class TsqrTimings(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("calls", i64 * 8)]
 
 
+class TsqrTuneResult(ctypes.Structure):
+    _fields_ = [("opts", TsqrOpts), ("ms", ctypes.c_double), ("candidates", ctypes.c_int),
+                ("from_cache", ctypes.c_int)]
+
+
 PHASES = ["leaf", "tree", "root", "seeds", "form_q", "apply_qt", "q1", "reorth"]
 
 EXPORTED = [
@@ -40,7 +45,7 @@ EXPORTED = [
     "tsqr_plan_info", "tsqr_plan_profile", "tsqr_plan_timings", "tsqr_plan_destroy", "tsqr_status_string",
     "tsqr_version", "tsqr_mixed_q1",
     "tsqr_batched_plan_create", "tsqr_batched_factor", "tsqr_batched_form_q", "tsqr_batched_problem_info",
-    "tsqr_batched_plan_destroy",
+    "tsqr_batched_plan_destroy", "tsqr_autotune", "tsqr_tune_cache_lookup", "tsqr_tune_cache_store",
 ]
 
 _lib = None
@@ -102,6 +107,15 @@ def load(path: str = LIB_PATH):
     lib.tsqr_batched_problem_info.restype = ctypes.c_int
     lib.tsqr_batched_plan_destroy.argtypes = [P]
     lib.tsqr_batched_plan_destroy.restype = ctypes.c_int
+    lib.tsqr_autotune.argtypes = [i64, i64, ctypes.c_int, ctypes.c_int, dp, i64, P, ctypes.c_char_p, ctypes.c_int,
+                                  ctypes.POINTER(TsqrTuneResult)]
+    lib.tsqr_autotune.restype = ctypes.c_int
+    lib.tsqr_tune_cache_lookup.argtypes = [ctypes.c_char_p, i64, i64, ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(TsqrOpts), ctypes.POINTER(ctypes.c_double)]
+    lib.tsqr_tune_cache_lookup.restype = ctypes.c_int
+    lib.tsqr_tune_cache_store.argtypes = [ctypes.c_char_p, i64, i64, ctypes.c_int, ctypes.POINTER(TsqrOpts),
+                                          ctypes.c_double]
+    lib.tsqr_tune_cache_store.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -12,6 +12,10 @@
 #include "tsqr_internal.h"
 
 namespace tsqr {
+bool tuned_opts(int64_t m, int64_t n, tsqr_precision prec, int want_q, tsqr_opts* out);  // tsqr_tune.cpp
+}
+
+namespace tsqr {
 
 bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves,
                  bool mixed)
@@ -211,6 +215,7 @@ const char* tsqr_status_string(tsqr_status s)
     case 2: return "device memory exhausted";
     case 3: return "unsupported case";
     case 4: return "call out of order (no factorisation with reflectors in the plan)";
+    case 5: return "class not in the autotune cache";
     default: return "unknown status";
     }
 }
@@ -226,6 +231,8 @@ static tsqr_status check_plan_args(int64_t m, int64_t n, tsqr_precision prec, co
     if (prec != TSQR_FP64 && prec != TSQR_MIXED) return -4;
     std::memset(&o, 0, sizeof(o));
     o.want_q = 1;
+    tsqr_opts tuned;
+    if (!opts && tsqr::tuned_opts(m, n, prec, 1, &tuned)) opts = &tuned;
     if (opts) {
         o = *opts;
         if (o.tree < TSQR_TREE_AUTO || o.tree > TSQR_TREE_HYBRID) return -5;

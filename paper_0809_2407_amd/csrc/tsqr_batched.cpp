@@ -20,6 +20,10 @@
 #include "../../include/tsqr.h"
 #include "tsqr_internal.h"
 
+namespace tsqr {
+bool tuned_opts(int64_t m, int64_t n, tsqr_precision prec, int want_q, tsqr_opts* out);  // tsqr_tune.cpp
+}
+
 struct tsqr_batched_plan_s {
     int count = 0;
     tsqr_precision prec = TSQR_FP64;
@@ -137,7 +141,15 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
     int64_t off = 0;
     for (int i = 0; i < count; ++i) {
         tsqr::Layout& L = p->L[i];
-        if (!tsqr::make_layout(L, m[i], n[i], o.leaf_rows, o.flat_len, o.tree, o.waves, false) ||
+        // without options, each problem takes the cached choice of its class (if any)
+        tsqr_opts oi = o;
+        tsqr_opts tuned;
+        if (!opts && tsqr::tuned_opts(m[i], n[i], prec, 1, &tuned) && tuned.tile_rows == 0) {
+            oi.tree = tuned.tree;
+            oi.leaf_rows = tuned.leaf_rows;
+            oi.flat_len = tuned.flat_len;
+        }
+        if (!tsqr::make_layout(L, m[i], n[i], oi.leaf_rows, oi.flat_len, oi.tree, oi.waves, false) ||
             L.levels >= tsqr::kBatchLevels) {
             delete p;
             return 3;

@@ -52,14 +52,22 @@ def _stream_handle(stream) -> int:
     return int(stream.cuda_stream)
 
 
+def _opts_or_null(tree, leaf_rows, tile_rows, flat_len, waves, want_q):
+    """Options for the C ABI; NULL when every field is at its default, so that
+    the library may take the autotuned choice of the problem's class."""
+    if tree == "auto" and not (leaf_rows or tile_rows or flat_len or waves) and want_q:
+        return None
+    return ctypes.byref(TsqrOpts(_TREES[tree], int(leaf_rows), int(tile_rows), int(flat_len), int(waves),
+                                 1 if want_q else 0))
+
+
 def plan_query(m: int, n: int, precision: str = "fp64", tree: str = "auto", leaf_rows: int = 0,
                tile_rows: int = 0, flat_len: int = 0, waves: int = 0, want_q: bool = True) -> dict:
     """tsqr_plan_query: what a plan would choose (no device needed)."""
     lib = _lib.load()
-    opts = TsqrOpts(_TREES[tree], int(leaf_rows), int(tile_rows), int(flat_len), int(waves), 1 if want_q else 0)
+    opts = _opts_or_null(tree, leaf_rows, tile_rows, flat_len, waves, want_q)
     out = TsqrInfo()
-    check("tsqr_plan_query", lib.tsqr_plan_query(int(m), int(n), _PREC[precision], ctypes.byref(opts),
-                                                 ctypes.byref(out)))
+    check("tsqr_plan_query", lib.tsqr_plan_query(int(m), int(n), _PREC[precision], opts, ctypes.byref(out)))
     return {f: getattr(out, f) for f, _ in TsqrInfo._fields_}
 
 
@@ -72,11 +80,10 @@ class Plan:
         self._lib = _lib.load()
         self.m, self.n = int(m), int(n)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        opts = TsqrOpts(_TREES[tree], int(leaf_rows), int(tile_rows), int(flat_len), int(waves),
-                        1 if want_q else 0)
+        opts = _opts_or_null(tree, leaf_rows, tile_rows, flat_len, waves, want_q)
         h = ctypes.c_void_p()
         check("tsqr_plan_create", self._lib.tsqr_plan_create(ctypes.byref(h), self.m, self.n, _PREC[precision],
-                                                              ctypes.byref(opts), _stream_handle(self.stream)))
+                                                              opts, _stream_handle(self.stream)))
         self._h = h
 
     def close(self) -> None:
@@ -167,12 +174,12 @@ class BatchedPlan:
             raise ValueError("ms and ns differ in length")
         self.count = len(self.ms)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        opts = TsqrOpts(_TREES[tree], int(leaf_rows), 0, int(flat_len), int(waves), 1 if want_q else 0)
+        opts = _opts_or_null(tree, leaf_rows, 0, flat_len, waves, want_q)
         I64 = ctypes.c_int64 * self.count
         h = ctypes.c_void_p()
         check("tsqr_batched_plan_create",
               self._lib.tsqr_batched_plan_create(ctypes.byref(h), self.count, I64(*self.ms), I64(*self.ns),
-                                                 _PREC[precision], ctypes.byref(opts), _stream_handle(self.stream)))
+                                                 _PREC[precision], opts, _stream_handle(self.stream)))
         self._h = h
 
     def _arrays(self, mats, rows, name):
@@ -221,6 +228,52 @@ class BatchedPlan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+_TREE_NAMES = {0: "auto", 1: "binary", 2: "flat", 3: "hybrid"}
+
+
+def _opts_dict(o: TsqrOpts) -> dict:
+    return {"tree": _TREE_NAMES[o.tree], "leaf_rows": o.leaf_rows, "tile_rows": o.tile_rows,
+            "flat_len": o.flat_len, "waves": o.waves, "want_q": bool(o.want_q)}
+
+
+def autotune(m: int, n: int, precision: str = "fp64", want_q: bool = True, A: Optional[torch.Tensor] = None,
+             cache: Optional[str] = None, reps: int = 3, stream=None) -> dict:
+    """tsqr_autotune: the fastest geometry for the class of (m, n); A (if given)
+    is a representative column-major device matrix, only read.  The returned
+    'opts' are Plan keyword arguments."""
+    lib = _lib.load()
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    aptr, lda = (A.data_ptr(), _ld(A, m, "A")) if A is not None else (None, int(m))
+    out = _lib.TsqrTuneResult()
+    check("tsqr_autotune", lib.tsqr_autotune(int(m), int(n), _PREC[precision], 1 if want_q else 0, aptr, lda,
+                                             _stream_handle(stream), cache.encode() if cache else None, int(reps),
+                                             ctypes.byref(out)))
+    return {"opts": _opts_dict(out.opts), "ms": out.ms, "candidates": out.candidates,
+            "from_cache": bool(out.from_cache)}
+
+
+def tune_cache_lookup(path: str, m: int, n: int, precision: str = "fp64", want_q: bool = True) -> Optional[dict]:
+    """tsqr_tune_cache_lookup: the cached options of a class, or None."""
+    lib = _lib.load()
+    o = TsqrOpts()
+    ms = ctypes.c_double()
+    st = lib.tsqr_tune_cache_lookup(path.encode(), int(m), int(n), _PREC[precision], 1 if want_q else 0,
+                                    ctypes.byref(o), ctypes.byref(ms))
+    if st == 5:
+        return None
+    check("tsqr_tune_cache_lookup", st)
+    return {"opts": _opts_dict(o), "ms": ms.value}
+
+
+def tune_cache_store(path: str, m: int, n: int, opts: dict, ms: float, precision: str = "fp64") -> None:
+    """tsqr_tune_cache_store."""
+    lib = _lib.load()
+    o = TsqrOpts(_TREES[opts.get("tree", "auto")], int(opts.get("leaf_rows", 0)), int(opts.get("tile_rows", 0)),
+                 int(opts.get("flat_len", 0)), int(opts.get("waves", 0)), 1 if opts.get("want_q", True) else 0)
+    check("tsqr_tune_cache_store", lib.tsqr_tune_cache_store(path.encode(), int(m), int(n), _PREC[precision],
+                                                             ctypes.byref(o), float(ms)))
 
 
 def qr(A: torch.Tensor, **plan_kw):

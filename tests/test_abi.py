@@ -125,3 +125,39 @@ def test_batched_argument_errors_without_device():
     assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, ms, ns, 1, None, None) == 3
     assert lib.tsqr_batched_factor(None, None, None, None, None) == -1
     assert lib.tsqr_batched_plan_destroy(None) == -1
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    import json
+
+    from paper_0809_2407_amd import tsqr as T
+    path = str(tmp_path / "tune.json")
+    assert T.tune_cache_lookup(path, 100000, 16) is None  # no file: empty cache
+    T.tune_cache_store(path, 100000, 16, {"tree": "hybrid", "flat_len": 4, "waves": 2}, 1.25)
+    T.tune_cache_store(path, 1 << 24, 32, {"tree": "binary", "waves": 4}, 6.5)
+    T.tune_cache_store(path, 1 << 24, 32, {"tree": "flat", "waves": 1, "want_q": False}, 2.5)
+    doc = json.load(open(path))  # the cache is plain JSON
+    assert len(doc["entries"]) == 3
+    hit = T.tune_cache_lookup(path, 120000, 16)  # same bucket: floor(log2 m) = 16
+    assert hit["opts"]["tree"] == "hybrid" and hit["opts"]["flat_len"] == 4 and hit["ms"] == 1.25
+    assert T.tune_cache_lookup(path, 200000, 16) is None  # bucket 17
+    assert T.tune_cache_lookup(path, 100000, 16, precision="mixed") is None
+    assert T.tune_cache_lookup(path, 1 << 24, 32)["opts"]["tree"] == "binary"
+    assert T.tune_cache_lookup(path, 1 << 24, 32, want_q=False)["opts"]["tree"] == "flat"
+    T.tune_cache_store(path, 100000, 16, {"tree": "binary", "waves": 4}, 0.5)  # replaces
+    assert T.tune_cache_lookup(path, 100000, 16)["opts"]["tree"] == "binary"
+    assert len(json.load(open(path))["entries"]) == 3
+    with open(path, "w") as f:
+        f.write("not json at all")
+    assert T.tune_cache_lookup(path, 100000, 16) is None  # unreadable: treated as empty
+
+
+def test_tuned_options_reach_plan_query(tmp_path, monkeypatch):
+    from paper_0809_2407_amd import tsqr as T
+    path = str(tmp_path / "tune.json")
+    base = T.plan_query(1 << 20, 32)
+    T.tune_cache_store(path, 1 << 20, 32, {"tree": "hybrid", "flat_len": 3, "waves": 1}, 1.0)
+    monkeypatch.setenv("TSQR_TUNE_CACHE", path)
+    tuned = T.plan_query(1 << 20, 32)
+    assert tuned["leaf_rows"] == 3 * tuned["tile_rows"] and tuned["waves"] == 1
+    assert base["leaf_rows"] != tuned["leaf_rows"]
