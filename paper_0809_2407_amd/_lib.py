@@ -66,6 +66,12 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"libtsqr.so not found at {path}; build it with "
                            f"`python -m paper_0809_2407_amd.build`")
+    # torch carries its own HIP runtime: loading it first makes the library bind
+    # to that one (same soname) instead of bringing a second runtime into the process
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     lib.tsqr_plan_create.argtypes = [ctypes.POINTER(P), i64, i64, ctypes.c_int, ctypes.POINTER(TsqrOpts), P]

@@ -8,7 +8,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/tsqr.h"
+#include "tsqr.h"
 #include "tsqr_internal.h"
 
 namespace tsqr {

@@ -20,7 +20,8 @@ constexpr double kReorthBound = 1e-13;
 // registers; the triangle R itself lives in LDS.
 __host__ __device__ constexpr int tile_rows_for(int np)
 {
-    return (4096 / np / 16 * 16) > 512 ? 512 : (4096 / np / 16 * 16);
+    // at np = 8 a 512-row tile leaves the reflector-keeping kernel short of registers
+    return (4096 / np / 16 * 16) > (np == 8 ? 384 : 512) ? (np == 8 ? 384 : 512) : (4096 / np / 16 * 16);
 }
 
 // Rows per tile of the mixed-precision leaf kernel, whose tile is held in FP32:

@@ -165,7 +165,7 @@ template <typename E>
 __host__ __device__ constexpr int vb_stride_e(int rl) { return sizeof(E) == 8 ? vb_stride(rl) : vb_stride_f(rl); }
 __host__ __device__ constexpr int packed_size(int np) { return np * (np + 1) / 2; }
 // Column groups of the factor layout: 8 when NP is a multiple of 8, else 4.
-__host__ __device__ constexpr int col_groups(int np) { return np % 8 == 0 ? 8 : 4; }
+__host__ __device__ constexpr int col_groups(int np) { return np % 8 == 0 && np > 16 ? 8 : 4; }
 // The Gram area of the factor kernels (packed strictly upper G) also serves as
 // the 16-row chunk buffer of gram_mfma (16 x (np+1) doubles); R-only kernels
 // have none.
@@ -173,13 +173,15 @@ __host__ __device__ constexpr int gram_area(int np)
 {
     return ((np * (np - 1) / 2 > 16 * (np + 1) ? np * (np - 1) / 2 : 16 * (np + 1)) + 1) / 2 * 2;
 }
-// per-wave LDS of the factor kernels: R, Gram entries (with Q), reflector broadcast, tau
+// LDS of the blocked construction of T for 16 < np <= 32 (doubles), after the tau array
+__host__ __device__ constexpr int tb_area(int np) { return np > 16 && np <= 32 ? 32 * 33 : 0; }
+// per-wave LDS of the factor kernels: R, Gram entries (with Q), reflector broadcast, tau, T blocks
 template <typename E = double>
 __host__ __device__ constexpr int factor_lds_doubles(int np, int tile_rows, bool want_q)
 {
     return r_area(np) + (want_q ? gram_area(np) : 0) +
-           ((64 / (np % 8 == 0 ? 8 : 4)) * vb_stride_e<E>(tile_rows / (64 / (np % 8 == 0 ? 8 : 4))) * (int)sizeof(E) + 7) / 8 +
-           np;
+           ((64 / col_groups(np)) * vb_stride_e<E>(tile_rows / (64 / col_groups(np))) * (int)sizeof(E) + 7) / 8 +
+           np + (want_q ? tb_area(np) : 0);
 }
 template <typename E>
 __host__ __device__ constexpr int tile_rows_e(int np) { return sizeof(E) == 8 ? tile_rows_for(np) : tile_rows_f32(np); }
@@ -391,8 +393,9 @@ __device__ __forceinline__ void gram_mfma(const E (&a)[RL][NP / LC], double* cb,
 // T of H_0 ... H_{NP-1} = I - V T V^T from the Gram entries G(c, j) = v_c^T v_j
 // (c < j) and tau: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).
 // Lane t < NP builds row t; T is written packed (column j at j(j+1)/2).
+// The recurrence with the Gram column of each step loaded in chunks of 16.
 template <int NP, typename E = double>
-__device__ __forceinline__ void build_T(const double* Gs, const double* taus, E* __restrict__ Tout, int lane)
+__device__ __forceinline__ void build_T_cols(const double* Gs, const double* taus, E* __restrict__ Tout, int lane)
 {
     double tr[NP];
 #pragma unroll
@@ -417,6 +420,131 @@ __device__ __forceinline__ void build_T(const double* Gs, const double* taus, E*
     }
 }
 
+template <int NP, typename E = double>
+__device__ __forceinline__ void build_T(const double* Gs, const double* taus, E* __restrict__ Tout, int lane)
+{
+    // The packed strictly upper Gram entries lie column after column, in the
+    // order the recurrence reads them (G(0:j, j) is Gs[j(j-1)/2 ...]), so they
+    // stream in as one sequence: loaded DIST entries ahead of their use, across
+    // column boundaries, in groups of R between scheduling barriers; four
+    // accumulation chains per column.
+    constexpr int NN = NP * (NP - 1) / 2, R = 8, DIST = 16, RING = 32;
+    __builtin_amdgcn_sched_barrier(0);  // nothing of the recurrence mixes with the code before it
+    double tr[NP];
+    double ring[RING];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) tr[j] = 0.0;
+#pragma unroll
+    for (int e = 0; e < DIST; ++e)
+        if (e < NN) ring[e % RING] = Gs[e];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < j; ++k) {
+            const int e = j * (j - 1) / 2 + k;  // position in the stream
+            if (e + DIST < NN) ring[(e + DIST) % RING] = Gs[e + DIST];
+            acc[k & 3] = fma(tr[k], ring[e % RING], acc[k & 3]);
+            if ((e % R) == R - 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        const double tj = taus[j];
+        const double sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        const double v = (lane < j) ? -tj * sum : (lane == j ? tj : 0.0);
+        tr[j] = v;
+        if (lane <= j) Tout[j * (j + 1) / 2 + lane] = (E)v;
+    }
+}
+
+// The same T for 16 < NP <= 32 in two 16-column blocks, T = [T11 T12; 0 T22]:
+// the diagonal blocks by the recurrence above, concurrently (lanes 0-15 build
+// the rows of T11, lanes 16-31 those of T22; chains of at most 15 steps), then
+// T12 = -T11 G12 T22 on the matrix cores (two 16x16x16 products).  Scratch
+// Tb (LDS, 1056 doubles): the diagonal Gram blocks restaged so that a lane's
+// addresses are its block's base plus constants (Gd, 2 x 256), and T11, T22
+// (stride 17, 2 x 272) for the operand layout; the f64 output layout of the
+// first product is the B operand of the second as it stands.
+template <int NP, typename E = double>
+__device__ __forceinline__ void build_T2(const double* Gs, const double* taus, double* Tb, E* __restrict__ Tout,
+                                         int lane)
+{
+    static_assert(NP > 16 && NP <= 32, "two 16-column blocks");
+    double* Gd = Tb;         // Gd[256 b + 16 jl + kl] = G(16 b + kl, 16 b + jl), kl < jl
+    double* Td = Tb + 512;   // Td[272 b + r + 17 jl] = T(16 b + r, 16 b + jl)
+    for (int e = lane; e < 512; e += 64) {
+        const int bb = e >> 8, jl = (e >> 4) & 15, kl = e & 15, j = 16 * bb + jl;
+        Gd[e] = (kl < jl && j < NP) ? Gs[gpk(16 * bb + kl, j)] : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int b = (lane >> 4) & 1, r = lane & 15, R0 = 16 * b + r;
+    const bool writer = lane < 32;  // lanes 32-63 repeat the work of lanes 0-31
+    const double* gb = Gd + 256 * b;
+    const double* tb = taus + 16 * b;
+    double* td = Td + 272 * b + r;
+    E* to = Tout + R0;
+    double tr[16];
+#pragma unroll
+    for (int jl = 0; jl < 16; ++jl) tr[jl] = 0.0;
+#pragma unroll
+    for (int jl = 0; jl < 16; ++jl) {
+        const int jmax = NP - 16 * b;  // columns of this lane's block
+        const double tj = jl < jmax ? tb[jl] : 0.0;
+        double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+        for (int kl = 0; kl < jl; ++kl) {
+            if (kl & 1) acc1 = fma(tr[kl], gb[16 * jl + kl], acc1);
+            else acc0 = fma(tr[kl], gb[16 * jl + kl], acc0);
+        }
+        const double acc = acc0 + acc1;
+        const double v = (r < jl) ? -tj * acc : (r == jl ? tj : 0.0);
+        tr[jl] = v;
+        if (writer) {
+            td[17 * jl] = v;
+            const int j = 16 * b + jl;
+            if (jl < jmax && r <= jl) to[j * (j + 1) / 2] = (E)v;
+        }
+        // keep the loads of later columns from being hoisted all at once
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __builtin_amdgcn_wave_barrier();  // T11 and T22 are read across lanes below
+    const int q = lane >> 4, p = lane & 15;
+    dbl4 X = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int c = 16 + 4 * s + q;  // G12(p, c - 16), T22(c - 16, p)
+        const double g = c < NP ? Gs[gpk(p, c < NP ? c : 1)] : 0.0;
+        X = mfma16x16x4(g, Td[272 + (4 * s + q) + 17 * p], X);
+    }
+    dbl4 Y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) Y = mfma16x16x4(Td[p + 17 * (4 * s + q)], X[s], Y);
+    const int col = 16 + p;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int row = q + 4 * rr;
+        if (col < NP) Tout[col * (col + 1) / 2 + row] = (E)(-Y[rr]);
+    }
+    __builtin_amdgcn_wave_barrier();  // the next tile rewrites Gs and Tb
+}
+
+// The streamed recurrence where it compiles without spilling the factor
+// kernels, the column-chunked one elsewhere.
+#ifndef TSQR_T_STREAMED_MASK
+#define TSQR_T_STREAMED_MASK 0xFBull  // widths 4, 8, 16, 20, 24, 28, 32
+#endif
+__host__ __device__ constexpr bool t_streamed(int np) { return (TSQR_T_STREAMED_MASK >> (np / 4 - 1)) & 1; }
+
+// Either construction of T for a width.
+template <int NP, typename E = double>
+__device__ __forceinline__ void make_T(const double* Gs, const double* taus, double* Tb, E* __restrict__ Tout,
+                                       int lane)
+{
+#if defined(TSQR_T_BLOCKED)
+    if constexpr (NP > 16 && NP <= 32) build_T2<NP, E>(Gs, taus, Tb, Tout, lane);
+    else
+#endif
+    if constexpr (t_streamed(NP)) build_T<NP, E>(Gs, taus, Tout, lane);
+    else build_T_cols<NP, E>(Gs, taus, Tout, lane);
+}
 // Tile load/store in the factor layout.  The per-lane part of the address
 // (row rg, column cg) is one loop-invariant offset; the rest is uniform, so the
 // compiler does not keep one address per element alive across the chain.
@@ -521,7 +649,7 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
             // the mixed workspace takes whole tiles (zero rows and columns included)
             store_tile<NP, RL, LC, E>(a, V + row0, ldv, lane_off_v, MIXED ? MT : valid, MIXED ? NP : n, rg, cg);
             gram_mfma<NP, RL, LC, true, E>(a, Gs, Gs, lane);
-            build_T<NP, E>(Gs, taus, Ttile + (leaf * f) * NT, lane);
+            make_T<NP, E>(Gs, taus, taus + NP, Ttile + (leaf * f) * NT, lane);
         }
     }
     for (int64_t t = 1; t < ntl; ++t) {
@@ -533,7 +661,7 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
             scale_tile<NP, RL, LC, false, E>(a, sc, lane);
             store_tile<NP, RL, LC, E>(a, V + t0, ldv, lane_off_v, MIXED ? MT : valid, MIXED ? NP : n, rg, cg);
             gram_mfma<NP, RL, LC, false, E>(a, Gs, Gs, lane);
-            build_T<NP, E>(Gs, taus, Ttile + (leaf * f + t) * NT, lane);
+            make_T<NP, E>(Gs, taus, taus + NP, Ttile + (leaf * f + t) * NT, lane);
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -605,7 +733,7 @@ __device__ __forceinline__ void tree_node(const double* __restrict__ Rin, int64_
     if (WANT_Q) {
         scale_tile<NP, RLN, LC, false>(a, sc, lane);
         gram_mfma<NP, RLN, LC, false>(a, Gs, Gs, lane);
-        build_T<NP>(Gs, taus, Tnode + q * NT, lane);
+        make_T<NP>(Gs, taus, taus + NP, Tnode + q * NT, lane);
         double* Y = Ynode + q * NP * NP;
 #pragma unroll
         for (int i = 0; i < RLN; ++i) {

@@ -19,7 +19,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tsqr.h"
+#include "tsqr.h"
 #include "tsqr_internal.h"
 
 namespace {
