@@ -209,7 +209,8 @@ tsqr_status tsqr_plan_destroy(tsqr_plan p);
  * workgroup of the leaf and Q kernels (1, 2 or 4).  The tile height is fixed
  * by n (it sizes the register-resident tile) and the leaf update is
  * unblocked, so neither is searched.  Accuracy guard: chains (and the flat
- * tree) are capped at 256 tiles, since rounding accumulates along a chain
+ * tree) are capped at 256 tiles (64 for the FP32 tiles of MIXED plans),
+ * since rounding accumulates along a chain
  * (the flat tree is the least accurate shape of Sec. 2).  The choice of the
  * best tree is left open by the paper; this search is the library's own.
  *

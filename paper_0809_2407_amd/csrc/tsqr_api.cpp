@@ -18,7 +18,7 @@ bool tuned_opts(int64_t m, int64_t n, tsqr_precision prec, int want_q, tsqr_opts
 namespace tsqr {
 
 bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves,
-                 bool mixed)
+                 bool mixed, bool want_q)
 {
     if (n < 1 || n > kMaxN || m < n) return false;
     L = Layout();
@@ -28,7 +28,9 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
     L.np = (int)((n + 3) / 4 * 4);
     L.npb = (int)((n + 15) / 16 * 16);
     L.mt = mixed ? tile_rows_f32(L.np) : tile_rows_for(L.np);
-    L.waves = waves > 0 ? waves : (L.np <= 32 ? 4 : 2);
+    // automatic waves per workgroup (leaf and Q kernels): 4 with Q, 1 for R only
+    // (the fastest choices of the autotuner at m = 2^24, n = 32 and 64)
+    L.waves = waves > 0 ? waves : (want_q ? 4 : 1);
     const int64_t tiles_total = (m + L.mt - 1) / L.mt;
     int64_t f;
     if (leaf_rows_req > 0) {
@@ -40,12 +42,21 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
     } else if (tree == TSQR_TREE_HYBRID && flat_len > 0) {
         f = flat_len;
     } else {
-        // automatic: about 4096 leaves, chains of 1..64 tiles, and chains long
-        // enough that the per-leaf factors (R, seed, node Y and T: about 4 np^2
-        // doubles) stay under a quarter of the leaf's f * mt * n doubles
-        f = tiles_total / 4096;
+        // automatic.  With Q: one resident round of leaves (2048 wavefronts --
+        // two per SIMD -- or 1024 at widths above 48, where the LDS of the
+        // reflector-keeping leaf kernel allows four per CU), so that the tree is
+        // as shallow as the device's parallelism allows.  R only: many short
+        // chains (16384 leaves).  Chains are 1..256 tiles, and long enough that
+        // the per-leaf factors (R, seed, node Y and T: about 4 np^2 doubles)
+        // stay under a quarter of the leaf's f * mt * n doubles.
+        // Narrow widths (np <= 24) keep about 4096 leaves.  Mixed precision caps
+        // the chain at kMaxChainF32 tiles (accuracy guard: FP32 rounding grows
+        // along a chain).
+        const int64_t target = !want_q ? 16384 : (L.np > 48 ? 1024 : (L.np > 24 ? 2048 : 4096));
+        f = tiles_total / target;
         const int64_t f_mem = (16 * (int64_t)L.np * L.np + L.mt * n - 1) / (L.mt * n);
-        f = std::max<int64_t>(std::max<int64_t>(1, f_mem), std::min<int64_t>(64, f));
+        f = std::max<int64_t>(std::max<int64_t>(1, f_mem), std::min<int64_t>(256, f));
+        if (mixed) f = std::min<int64_t>(f, kMaxChainF32);
         f = std::min<int64_t>(f, std::max<int64_t>(1, tiles_total));
     }
     if (f < 1) f = 1;
@@ -240,7 +251,8 @@ static tsqr_status check_plan_args(int64_t m, int64_t n, tsqr_precision prec, co
         if (o.waves != 0 && o.waves != 1 && o.waves != 2 && o.waves != 4) return -5;
         if (o.want_q != 0 && o.want_q != 1) return -5;
     }
-    if (!tsqr::make_layout(L, m, n, o.leaf_rows, o.flat_len, o.tree, o.waves, prec == TSQR_MIXED)) return 3;
+    if (!tsqr::make_layout(L, m, n, o.leaf_rows, o.flat_len, o.tree, o.waves, prec == TSQR_MIXED, o.want_q != 0))
+        return 3;
     if (o.tile_rows != 0 && o.tile_rows != L.mt) return -5;
     return 0;
 }

@@ -149,7 +149,7 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
             oi.leaf_rows = tuned.leaf_rows;
             oi.flat_len = tuned.flat_len;
         }
-        if (!tsqr::make_layout(L, m[i], n[i], oi.leaf_rows, oi.flat_len, oi.tree, oi.waves, false) ||
+        if (!tsqr::make_layout(L, m[i], n[i], oi.leaf_rows, oi.flat_len, oi.tree, oi.waves, false, o.want_q != 0) ||
             L.levels >= tsqr::kBatchLevels) {
             delete p;
             return 3;
@@ -272,7 +272,7 @@ tsqr_status tsqr_batched_factor(tsqr_batched_plan p, double* const* A, const int
     if (e == hipSuccess && !p->g_factor) {
         e = capture_graph(p->capture, &p->g_factor, [&](hipStream_t s) {
             for (const tsqr::BatchClass& C : p->classes) {
-                const int waves = p->waves > 0 ? p->waves : (C.np <= 32 ? 4 : 2);
+                const int waves = p->waves > 0 ? p->waves : (p->want_q ? 4 : 1);
                 hipError_t el = tsqr::launch_batch_factor(C, p->d_probs, p->d_args_f, p->ws, p->want_q != 0, waves, s);
                 if (el != hipSuccess) return el;
             }
@@ -305,7 +305,7 @@ tsqr_status tsqr_batched_form_q(tsqr_batched_plan p, double* const* A, const int
     if (e == hipSuccess && !p->g_form_q) {
         e = capture_graph(p->capture, &p->g_form_q, [&](hipStream_t s) {
             for (const tsqr::BatchClass& C : p->classes) {
-                const int waves = p->waves > 0 ? p->waves : (C.np <= 32 ? 4 : 2);
+                const int waves = p->waves > 0 ? p->waves : (p->want_q ? 4 : 1);
                 hipError_t el = tsqr::launch_batch_form_q(C, p->d_probs, p->d_args_q, p->ws, waves, s);
                 if (el != hipSuccess) return el;
             }
@@ -332,7 +332,7 @@ tsqr_status tsqr_batched_problem_info(tsqr_batched_plan p, int index, tsqr_info*
     out->num_tiles = L.ntiles;
     out->tree_levels = L.levels;
     out->tree = L.P == 1 ? TSQR_TREE_FLAT : (L.f == 1 ? TSQR_TREE_BINARY : TSQR_TREE_HYBRID);
-    out->waves = p->waves > 0 ? p->waves : (L.np <= 32 ? 4 : 2);
+    out->waves = L.waves;
     out->precision = p->prec;
     out->workspace_bytes = L.total * (int64_t)sizeof(double);
     return 0;

@@ -12,6 +12,8 @@ constexpr int kMaxN = 64;
 // Mixed precision: the second pass corrects Q and R when ||Q1^T Q1 - I||_F
 // exceeds this bound.
 constexpr double kReorthBound = 1e-13;
+// Mixed precision: longest automatic leaf chain (tiles) of FP32 tiles.
+constexpr int64_t kMaxChainF32 = 64;
 
 // Rows per tile for a padded column count np: about 4096 tile elements per
 // wavefront (64 doubles per lane, the register budget of the leaf kernel), a
@@ -110,7 +112,7 @@ struct BatchClass {
 
 // Fills the geometry.  Returns false for an unsupported shape.
 bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves,
-                 bool mixed);
+                 bool mixed, bool want_q);
 
 // Kernel launchers (tsqr_kernels.hip).  All enqueue on `s` and return the
 // launch status.

@@ -9,7 +9,7 @@
 // panel width to choose.  Accuracy guards: flat chains are capped at
 // kMaxChainTiles tiles (a long flat chain accumulates rounding along the chain
 // -- the flat tree is the least accurate shape), and for the mixed precision
-// the FP32 tiles of a chain are capped the same way.
+// chains of FP32 tiles are capped at kMaxChainF32.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -244,11 +244,12 @@ tsqr_status tsqr_autotune(int64_t m, int64_t n, tsqr_precision prec, int want_q,
     // when within the guard) times 1, 2 or 4 wavefronts per workgroup
     tsqr::Layout L0;
     tsqr_status st = 0;
-    if (he == hipSuccess && !tsqr::make_layout(L0, m, n, 0, 0, TSQR_TREE_AUTO, 0, prec == TSQR_MIXED)) st = 3;
+    if (he == hipSuccess && !tsqr::make_layout(L0, m, n, 0, 0, TSQR_TREE_AUTO, 0, prec == TSQR_MIXED, want_q != 0)) st = 3;
     std::vector<tsqr_opts> cand;
     if (he == hipSuccess && st == 0) {
         const int64_t tiles = (m + L0.mt - 1) / L0.mt;
-        for (int64_t f = 1; f <= std::min<int64_t>(tiles, kMaxChainTiles); f *= 2)
+        const int64_t fmax = prec == TSQR_MIXED ? tsqr::kMaxChainF32 : kMaxChainTiles;
+        for (int64_t f = 1; f <= std::min<int64_t>(tiles, fmax); f *= 2)
             for (int w : {1, 2, 4}) {
                 tsqr_opts o;
                 std::memset(&o, 0, sizeof(o));
@@ -258,7 +259,7 @@ tsqr_status tsqr_autotune(int64_t m, int64_t n, tsqr_precision prec, int want_q,
                 o.want_q = want_q;
                 cand.push_back(o);
             }
-        if (tiles <= kMaxChainTiles)
+        if (tiles <= fmax)
             for (int w : {1, 2, 4}) {
                 tsqr_opts o;
                 std::memset(&o, 0, sizeof(o));
