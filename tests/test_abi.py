@@ -161,3 +161,18 @@ def test_tuned_options_reach_plan_query(tmp_path, monkeypatch):
     tuned = T.plan_query(1 << 20, 32)
     assert tuned["leaf_rows"] == 3 * tuned["tile_rows"] and tuned["waves"] == 1
     assert base["leaf_rows"] != tuned["leaf_rows"]
+
+
+def test_mixed_plan_geometry():
+    """A mixed plan: FP32 tiles of the FP64 height, FP32 chains capped at 64
+    tiles, and a workspace that holds V32, Q1 and the second pass."""
+    from paper_0809_2407_amd import tsqr as T
+    f64 = T.plan_query(1 << 24, 64)
+    mx = T.plan_query(1 << 24, 64, precision="mixed")
+    assert mx["precision"] == 1 and mx["tile_rows"] == f64["tile_rows"] == 64
+    assert mx["leaf_rows"] <= 64 * mx["tile_rows"]
+    # V32 and Q1: 2 x 4 bytes per element at least
+    assert mx["workspace_bytes"] >= 8 * (1 << 24) * 64
+    # R only: no FP32 cap needed for accuracy of Q, still FP32 tiles
+    r_only = T.plan_query(1 << 20, 16, precision="mixed", want_q=False)
+    assert r_only["precision"] == 1

@@ -136,3 +136,28 @@ def test_mixed_rejects_apply_qt_and_matches_fp64_plan():
             p.mixed_q1()
         assert e.value.status == 3
     torch.cuda.synchronize()
+
+
+def test_mixed_leading_dimensions_and_q_over_a():
+    """lda > m and ldq > m; Q may overwrite the original A on a mixed plan
+    (its reflectors live in the plan)."""
+    torch = need_gpu()
+    from paper_0809_2407_amd import tsqr as T
+
+    m, n = 9000, 24
+    A, _ = synth.prescribed_sigma(m, n, seed=950, decades=6)
+    Ad = T.colmajor(m, n, ld=m + 7)
+    Ad.copy_(torch.from_numpy(A))
+    Qd = T.colmajor(m, n, ld=m + 3)
+    announce("mixed ld > m")
+    with T.Plan(m, n, precision="mixed") as p:
+        R1 = p.factor(Ad)
+        p.form_q(None, Qd)
+        R2 = p.factor(Ad)
+        p.form_q(None, Ad)  # overwrite A with Q
+        torch.cuda.synchronize()
+    R1, R2 = R1.cpu().numpy(), R2.cpu().numpy()
+    Q1, Q2 = Qd.cpu().numpy(), Ad.cpu().numpy()
+    assert np.array_equal(R1, R2) and np.array_equal(Q1, Q2)
+    assert backward_error(A, Q1, R1) <= BWD_MIXED
+    assert orthogonality(Q1) <= ORTH_MIXED

@@ -194,3 +194,27 @@ def test_writes_stay_inside_the_outputs(m, n):
     assert outside_untouched(Bbuf, m, k)
     Qh, Rh = Q.cpu().numpy(), R.cpu().numpy()
     assert backward_error(A, Qh, Rh) <= fp64_bound(n)
+
+
+def test_leading_dimensions_past_32_bit_offsets():
+    """Leading dimensions whose byte offsets inside a 16 x 4 block pass 2^32
+    (the Q kernel then addresses with 64-bit per-lane offsets); m is small,
+    the matrices are sparse in memory (about 5.7 GB each)."""
+    torch = need_gpu()
+    from paper_0809_2407_amd import tsqr as T
+
+    m, n, ld = 3000, 4, 179_000_000
+    A = synth.gaussian(m, n, seed=41)
+    announce(f"ld = {ld}")
+    Ad = T.colmajor(m, n, ld=ld)
+    Ad.copy_(torch.from_numpy(A))
+    Qd = T.colmajor(m, n, ld=ld)
+    with T.Plan(m, n, tree="hybrid", flat_len=2) as p:
+        info = p.info()
+        R = p.factor(Ad)
+        p.form_q(Ad, Qd)
+        torch.cuda.synchronize()
+    R, Q = R.cpu().numpy(), Qd.cpu().numpy()
+    del Ad, Qd
+    torch.cuda.empty_cache()
+    _check_against_oracle(A, R, Q, info, elementwise_q=True)
