@@ -182,7 +182,8 @@ typedef enum {
     TSQR_PHASE_APPLY = 5,   /* tsqr_apply_qt */
     TSQR_PHASE_Q1 = 6,      /* MIXED: the FP32 first-pass Q1 (inside tsqr_factor) */
     TSQR_PHASE_REORTH = 7,  /* MIXED: second pass -- Gram, check, Cholesky, R = R2 R1 */
-    TSQR_NUM_PHASES = 8
+    TSQR_PHASE_LEAF_T = 8,  /* plans with Q: the compact-WY T of every leaf tile (Sec. 3.2) */
+    TSQR_NUM_PHASES = 9
 } tsqr_phase;
 
 typedef struct {

@@ -29,8 +29,11 @@ class TsqrInfo(ctypes.Structure):
                 ("orth_estimate", ctypes.c_double)]
 
 
+PHASES = ["leaf", "tree", "root", "seeds", "form_q", "apply_qt", "q1", "reorth", "leaf_t"]
+
+
 class TsqrTimings(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("calls", i64 * 8)]
+    _fields_ = [("ms", ctypes.c_double * len(PHASES)), ("calls", i64 * len(PHASES))]
 
 
 class TsqrTuneResult(ctypes.Structure):
@@ -38,7 +41,6 @@ class TsqrTuneResult(ctypes.Structure):
                 ("from_cache", ctypes.c_int)]
 
 
-PHASES = ["leaf", "tree", "root", "seeds", "form_q", "apply_qt", "q1", "reorth"]
 
 EXPORTED = [
     "tsqr_plan_create", "tsqr_plan_query", "tsqr_factor", "tsqr_factor_into", "tsqr_form_q", "tsqr_apply_qt",

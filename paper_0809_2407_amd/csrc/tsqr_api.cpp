@@ -43,8 +43,8 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
         f = flat_len;
     } else {
         // automatic.  With Q: one resident round of leaves (2048 wavefronts --
-        // two per SIMD -- or 1024 at widths above 48, where the LDS of the
-        // reflector-keeping leaf kernel allows four per CU), so that the tree is
+        // two per SIMD -- or 1024 where the LDS of the reflector-keeping leaf
+        // kernel allows only four per CU), so that the tree is
         // as shallow as the device's parallelism allows.  R only: many short
         // chains (16384 leaves).  Chains are 1..256 tiles, and long enough that
         // the per-leaf factors (R, seed, node Y and T: about 4 np^2 doubles)
@@ -52,7 +52,8 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
         // Narrow widths (np <= 24) keep about 4096 leaves.  Mixed precision caps
         // the chain at kMaxChainF32 tiles (accuracy guard: FP32 rounding grows
         // along a chain).
-        const int64_t target = !want_q ? 16384 : (L.np > 48 ? 1024 : (L.np > 24 ? 2048 : 4096));
+        const bool two_per_simd = leaf_lds_bytes(L.np, mixed, want_q) <= 20480;
+        const int64_t target = !want_q ? 16384 : (!two_per_simd ? 1024 : (L.np > 24 ? 2048 : 4096));
         f = tiles_total / target;
         const int64_t f_mem = (16 * (int64_t)L.np * L.np + L.mt * n - 1) / (L.mt * n);
         f = std::max<int64_t>(std::max<int64_t>(1, f_mem), std::min<int64_t>(256, f));
@@ -193,6 +194,8 @@ tsqr_status factor_mixed(tsqr_plan_s* p, const double* A, int64_t lda, double* R
     const bool want_q = p->want_q != 0;
     const tsqr::Layout& L = p->L;
     hipError_t e = run_phase(p, TSQR_PHASE_LEAF, [&] { return tsqr::launch_mixed_leaf(L, A, lda, p->ws, want_q, p->stream); });
+    if (e == hipSuccess && want_q)
+        e = run_phase(p, TSQR_PHASE_LEAF_T, [&] { return tsqr::launch_build_T(L, p->ws, p->stream); });
     if (e == hipSuccess && L.levels > 0)
         e = run_phase(p, TSQR_PHASE_TREE, [&] { return tsqr::launch_tree(L, p->ws, want_q, p->stream); });
     if (e == hipSuccess)
@@ -342,6 +345,8 @@ tsqr_status tsqr_factor_into(tsqr_plan p, const double* A, int64_t lda, double* 
     hipError_t e = run_phase(p, TSQR_PHASE_LEAF, [&] {
         return tsqr::launch_leaf_factor(p->L, A, lda, V, want_q ? ldv : lda, p->ws, want_q, p->stream);
     });
+    if (e == hipSuccess && want_q)
+        e = run_phase(p, TSQR_PHASE_LEAF_T, [&] { return tsqr::launch_build_T(p->L, p->ws, p->stream); });
     if (e == hipSuccess && p->L.levels > 0)
         e = run_phase(p, TSQR_PHASE_TREE, [&] { return tsqr::launch_tree(p->L, p->ws, want_q, p->stream); });
     if (e == hipSuccess)

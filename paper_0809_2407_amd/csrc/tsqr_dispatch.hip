@@ -88,6 +88,29 @@ hipError_t launch_mixed_leaf(const Layout& L, const double* A, int64_t lda, doub
 #undef CALL
 }
 
+hipError_t launch_build_T(const Layout& L, double* ws, hipStream_t s)
+{
+#define CALL(NP) build_T_np<NP>(L, ws, s)
+    TSQR_NP_SWITCH(L.np, CALL)
+#undef CALL
+}
+
+int leaf_lds_bytes(int np, bool mixed, bool want_q)
+{
+#if defined(TSQR_ONLY_NP)
+    return np == TSQR_ONLY_NP ? leaf_lds_bytes_np<TSQR_ONLY_NP>(mixed, want_q) : 0;
+#else
+    switch (np) {
+#define CASE(NP) \
+    case NP: return leaf_lds_bytes_np<NP>(mixed, want_q);
+        CASE(4) CASE(8) CASE(12) CASE(16) CASE(20) CASE(24) CASE(28) CASE(32)
+        CASE(36) CASE(40) CASE(44) CASE(48) CASE(52) CASE(56) CASE(60) CASE(64)
+#undef CASE
+    default: return 0;
+    }
+#endif
+}
+
 hipError_t launch_form_q1(const Layout& L, double* ws, hipStream_t s)
 {
 #define CALL(NP) form_q1_np<NP>(L, ws, s)

@@ -28,7 +28,9 @@ __host__ __device__ constexpr int tile_rows_for(int np)
 
 // Rows per tile of the mixed-precision leaf kernel, whose tile is held in FP32:
 // twice the FP64 tile in the same registers, at most 1024.
-#define TSQR_F32_TILE_SCALE 1
+#ifndef TSQR_F32_TILE_SCALE
+#define TSQR_F32_TILE_SCALE 2
+#endif
 __host__ __device__ constexpr int tile_rows_f32(int np) { return TSQR_F32_TILE_SCALE * tile_rows_for(np); }
 
 // Geometry of one TSQR problem: tiles, leaves (flat chains of tiles) and the
@@ -128,6 +130,11 @@ hipError_t launch_apply_qt(const Layout& L, const double* A, int64_t lda, int64_
 // mixed precision: FP32 leaf chains, FP32 Q1, FP64 second pass (Gram,
 // Cholesky, check, R = R2 R1 to the caller's R) and the corrected Q
 hipError_t launch_mixed_leaf(const Layout& L, const double* A, int64_t lda, double* ws, bool want_q, hipStream_t s);
+// T of every leaf tile from the tau and Gram entries the leaf kernel left in
+// the tile's T slot (plans with Q, both precisions).
+hipError_t launch_build_T(const Layout& L, double* ws, hipStream_t s);
+// LDS bytes per wavefront of the single-problem leaf kernel for a padded width.
+int leaf_lds_bytes(int np, bool mixed, bool want_q);
 hipError_t launch_form_q1(const Layout& L, double* ws, hipStream_t s);
 hipError_t launch_reorth(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s);
 hipError_t launch_reorth_q(const Layout& L, double* ws, double* Q, int64_t ldq, hipStream_t s);
@@ -156,6 +163,10 @@ hipError_t apply_qt_np(const Layout& L, const double* A, int64_t lda, int64_t k,
                        double* ws, hipStream_t s);
 template <int NP>
 hipError_t mixed_leaf_np(const Layout& L, const double* A, int64_t lda, double* ws, bool want_q, hipStream_t s);
+template <int NP>
+hipError_t build_T_np(const Layout& L, double* ws, hipStream_t s);
+template <int NP>
+int leaf_lds_bytes_np(bool mixed, bool want_q);
 template <int NP>
 hipError_t form_q1_np(const Layout& L, double* ws, hipStream_t s);
 template <int NP>

@@ -183,6 +183,27 @@ __host__ __device__ constexpr int factor_lds_doubles(int np, int tile_rows, bool
            ((64 / col_groups(np)) * vb_stride_e<E>(tile_rows / (64 / col_groups(np))) * (int)sizeof(E) + 7) / 8 +
            np + (want_q ? tb_area(np) : 0);
 }
+// The single-problem leaf kernel leaves T to k_build_T: with Q it keeps only a
+// chunk buffer of the Gram (CH rows of np + 1 doubles).  CH = 16 where the
+// per-wave LDS then stays within 20 KiB (two wavefronts per SIMD), else 4.
+template <typename E = double>
+__host__ __device__ constexpr int leaf_lds_doubles_ch(int np, int tile_rows, bool want_q, int ch)
+{
+    return r_area(np) + (want_q ? (ch * (np + 1) + 1) / 2 * 2 : 0) +
+           ((64 / col_groups(np)) * vb_stride_e<E>(tile_rows / (64 / col_groups(np))) * (int)sizeof(E) + 7) / 8 +
+           np;
+}
+constexpr int kLeafLdsBudget = 20480 / 8;  // doubles per wavefront for two wavefronts per SIMD
+template <typename E = double>
+__host__ __device__ constexpr int leaf_gram_chunk(int np, int tile_rows)
+{
+    return leaf_lds_doubles_ch<E>(np, tile_rows, true, 16) <= kLeafLdsBudget ? 16 : 4;
+}
+template <typename E = double>
+__host__ __device__ constexpr int leaf_lds_doubles(int np, int tile_rows, bool want_q)
+{
+    return leaf_lds_doubles_ch<E>(np, tile_rows, want_q, leaf_gram_chunk<E>(np, tile_rows));
+}
 template <typename E>
 __host__ __device__ constexpr int tile_rows_e(int np) { return sizeof(E) == 8 ? tile_rows_for(np) : tile_rows_f32(np); }
 
@@ -333,27 +354,27 @@ __device__ __forceinline__ void scale_tile(E (&a)[RL][NP / LC], const E (&sc)[NP
 // V^T (A) and V (B).  Reflectors: FIRST tiles have v_c(r) = 0 above the
 // diagonal and 1 on it; chained tiles [e_c; y_c] contribute y_c^T y_d
 // (c != d).  Writes the strictly upper part G(c, d), c < d, to Gs.
-template <int NP, int RL, int LC, bool FIRST, typename E = double>
-__device__ __forceinline__ void gram_mfma(const E (&a)[RL][NP / LC], double* cb, double* Gs, int lane)
+template <int NP, int RL, int LC, bool FIRST, int CH, typename E>
+__device__ __forceinline__ void gram_accumulate(const E (&a)[RL][NP / LC], double* cb,
+                                                dbl4 (&acc)[round16(NP) / 16][round16(NP) / 16], int lane)
 {
     constexpr int KC = NP / LC, LR = 64 / LC, MT = LR * RL, LDP = NP + 1;
     constexpr int NPB = round16(NP), JB = NPB / 16;
-    static_assert(MT % 16 == 0, "gram_mfma reads whole 16-row chunks");
+    static_assert(MT % CH == 0 && CH % 4 == 0, "gram chunks are whole multiples of the K step");
     const int cg = lane / LR, rg = lane % LR;
     const int q = lane >> 4, p = lane & 15;
-    dbl4 acc[JB][JB];
 #pragma unroll
     for (int ib = 0; ib < JB; ++ib)
 #pragma unroll
         for (int jb = 0; jb < JB; ++jb) acc[ib][jb] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int c0 = 0; c0 < MT; c0 += 16) {
-        // this lane's rows inside the chunk [c0, c0 + 16)
+    for (int c0 = 0; c0 < MT; c0 += CH) {
+        // this lane's rows inside the chunk [c0, c0 + CH)
 #pragma unroll
         for (int i = 0; i < RL; ++i) {
             const int row = LR * i + rg;
-            if (LR * i + LR <= c0 || LR * i >= c0 + 16) continue;  // slot outside the chunk (compile-time test
-            if (row < c0 || row >= c0 + 16) continue;               // on i, runtime on rg)
+            if (LR * i + LR <= c0 || LR * i >= c0 + CH) continue;  // slot outside the chunk (compile-time test
+            if (row < c0 || row >= c0 + CH) continue;               // on i, runtime on rg)
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
                 const int col = LC * k + cg;
@@ -364,7 +385,7 @@ __device__ __forceinline__ void gram_mfma(const E (&a)[RL][NP / LC], double* cb,
         }
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < CH / 4; ++s) {
             double vv[JB];
 #pragma unroll
             for (int b = 0; b < JB; ++b) {
@@ -378,6 +399,15 @@ __device__ __forceinline__ void gram_mfma(const E (&a)[RL][NP / LC], double* cb,
         }
         __builtin_amdgcn_wave_barrier();
     }
+}
+
+template <int NP, int RL, int LC, bool FIRST, typename E = double>
+__device__ __forceinline__ void gram_mfma(const E (&a)[RL][NP / LC], double* cb, double* Gs, int lane)
+{
+    constexpr int JB = round16(NP) / 16;
+    const int q = lane >> 4, p = lane & 15;
+    dbl4 acc[JB][JB];
+    gram_accumulate<NP, RL, LC, FIRST, 16, E>(a, cb, acc, lane);
 #pragma unroll
     for (int ib = 0; ib < JB; ++ib)
 #pragma unroll
@@ -390,11 +420,54 @@ __device__ __forceinline__ void gram_mfma(const E (&a)[RL][NP / LC], double* cb,
     __builtin_amdgcn_wave_barrier();
 }
 
+// Position of G(k, j), k < j, in the strictly upper Gram packed by rows.
+__host__ __device__ constexpr int grow(int np, int k, int j) { return k * (np - 1) - k * (k - 1) / 2 + (j - k - 1); }
+// G(k, j) in either packing (ROWS: by rows, as the leaf kernel leaves it in a
+// T slot; else by columns).
+template <int NP, bool ROWS>
+__host__ __device__ constexpr int gidx(int k, int j) { return ROWS ? grow(NP, k, j) : gpk(k, j); }
+// The column j of the e-th strictly upper entry in column order (j(j-1)/2 <= e).
+__host__ __device__ constexpr int gcol(int e)
+{
+    int j = 1;
+    while ((j + 1) * j / 2 <= e) ++j;
+    return j;
+}
+
+// The factors of a tile's T for a later construction (k_build_T): the tile's
+// T slot of np(np+1)/2 entries receives tau (np entries) followed by the
+// strictly upper Gram packed by rows (a row of a 16 x 16 output block is 16
+// consecutive entries, so the stores coalesce).  CH: rows per LDS chunk of the
+// Gram (4 where the leaf's LDS would otherwise cost occupancy).
+template <int NP, int RL, int LC, bool FIRST, int CH, typename E>
+__device__ __forceinline__ void gram_out(const E (&a)[RL][NP / LC], double* cb, const double* taus,
+                                         E* __restrict__ slot, int lane)
+{
+    constexpr int JB = round16(NP) / 16;
+    const int q = lane >> 4, p = lane & 15;
+    dbl4 acc[JB][JB];
+    gram_accumulate<NP, RL, LC, FIRST, CH, E>(a, cb, acc, lane);
+    if (lane < NP) slot[lane] = (E)taus[lane];
+    // uniform base plus a 32-bit per-lane byte offset (one address register)
+    E* g = slot + NP;
+    const int qo = opaque(q), po = opaque(p);
+#pragma unroll
+    for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+        for (int jb = ib; jb < JB; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * ib + qo + 4 * r, col = 16 * jb + po;
+                if (row < col && col < NP)
+                    st_at(g, (uint32_t)(grow(NP, row, col) * (int)sizeof(E)), (E)acc[ib][jb][r]);
+            }
+}
+
 // T of H_0 ... H_{NP-1} = I - V T V^T from the Gram entries G(c, j) = v_c^T v_j
 // (c < j) and tau: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).
 // Lane t < NP builds row t; T is written packed (column j at j(j+1)/2).
 // The recurrence with the Gram column of each step loaded in chunks of 16.
-template <int NP, typename E = double>
+template <int NP, typename E = double, bool ROWS = false>
 __device__ __forceinline__ void build_T_cols(const double* Gs, const double* taus, E* __restrict__ Tout, int lane)
 {
     double tr[NP];
@@ -406,8 +479,8 @@ __device__ __forceinline__ void build_T_cols(const double* Gs, const double* tau
         double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
         for (int k = 0; k < j; ++k) {
-            if (k & 1) acc1 = fma(tr[k], Gs[gpk(k, j)], acc1);
-            else acc0 = fma(tr[k], Gs[gpk(k, j)], acc0);
+            if (k & 1) acc1 = fma(tr[k], Gs[gidx<NP, ROWS>(k, j)], acc1);
+            else acc0 = fma(tr[k], Gs[gidx<NP, ROWS>(k, j)], acc0);
             // at most 16 loads of G in flight
             if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
         }
@@ -420,15 +493,20 @@ __device__ __forceinline__ void build_T_cols(const double* Gs, const double* tau
     }
 }
 
-template <int NP, typename E = double>
+template <int NP, typename E = double, bool ROWS = false>
 __device__ __forceinline__ void build_T(const double* Gs, const double* taus, E* __restrict__ Tout, int lane)
 {
     // The packed strictly upper Gram entries lie column after column, in the
     // order the recurrence reads them (G(0:j, j) is Gs[j(j-1)/2 ...]), so they
     // stream in as one sequence: loaded DIST entries ahead of their use, across
     // column boundaries, in groups of R between scheduling barriers; four
-    // accumulation chains per column.
+    // accumulation chains per column.  (With ROWS the sequence is gathered from
+    // the row packing; every position is a compile-time constant.)
     constexpr int NN = NP * (NP - 1) / 2, R = 8, DIST = 16, RING = 32;
+    auto at = [&](int e) {
+        const int j = gcol(e);
+        return Gs[gidx<NP, ROWS>(e - j * (j - 1) / 2, j)];
+    };
     __builtin_amdgcn_sched_barrier(0);  // nothing of the recurrence mixes with the code before it
     double tr[NP];
     double ring[RING];
@@ -436,14 +514,14 @@ __device__ __forceinline__ void build_T(const double* Gs, const double* taus, E*
     for (int j = 0; j < NP; ++j) tr[j] = 0.0;
 #pragma unroll
     for (int e = 0; e < DIST; ++e)
-        if (e < NN) ring[e % RING] = Gs[e];
+        if (e < NN) ring[e % RING] = at(e);
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < j; ++k) {
             const int e = j * (j - 1) / 2 + k;  // position in the stream
-            if (e + DIST < NN) ring[(e + DIST) % RING] = Gs[e + DIST];
+            if (e + DIST < NN) ring[(e + DIST) % RING] = at(e + DIST);
             acc[k & 3] = fma(tr[k], ring[e % RING], acc[k & 3]);
             if ((e % R) == R - 1) __builtin_amdgcn_sched_barrier(0);
         }
@@ -463,7 +541,7 @@ __device__ __forceinline__ void build_T(const double* Gs, const double* taus, E*
 // addresses are its block's base plus constants (Gd, 2 x 256), and T11, T22
 // (stride 17, 2 x 272) for the operand layout; the f64 output layout of the
 // first product is the B operand of the second as it stands.
-template <int NP, typename E = double>
+template <int NP, typename E = double, bool ROWS = false>
 __device__ __forceinline__ void build_T2(const double* Gs, const double* taus, double* Tb, E* __restrict__ Tout,
                                          int lane)
 {
@@ -472,7 +550,7 @@ __device__ __forceinline__ void build_T2(const double* Gs, const double* taus, d
     double* Td = Tb + 512;   // Td[272 b + r + 17 jl] = T(16 b + r, 16 b + jl)
     for (int e = lane; e < 512; e += 64) {
         const int bb = e >> 8, jl = (e >> 4) & 15, kl = e & 15, j = 16 * bb + jl;
-        Gd[e] = (kl < jl && j < NP) ? Gs[gpk(16 * bb + kl, j)] : 0.0;
+        Gd[e] = (kl < jl && j < NP) ? Gs[gidx<NP, ROWS>(16 * bb + kl, j)] : 0.0;
     }
     __builtin_amdgcn_wave_barrier();
     const int b = (lane >> 4) & 1, r = lane & 15, R0 = 16 * b + r;
@@ -511,7 +589,7 @@ __device__ __forceinline__ void build_T2(const double* Gs, const double* taus, d
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int c = 16 + 4 * s + q;  // G12(p, c - 16), T22(c - 16, p)
-        const double g = c < NP ? Gs[gpk(p, c < NP ? c : 1)] : 0.0;
+        const double g = c < NP ? Gs[gidx<NP, ROWS>(p, c < NP ? c : p + 1)] : 0.0;
         X = mfma16x16x4(g, Td[272 + (4 * s + q) + 17 * p], X);
     }
     dbl4 Y = {0.0, 0.0, 0.0, 0.0};
@@ -534,16 +612,16 @@ __device__ __forceinline__ void build_T2(const double* Gs, const double* taus, d
 __host__ __device__ constexpr bool t_streamed(int np) { return (TSQR_T_STREAMED_MASK >> (np / 4 - 1)) & 1; }
 
 // Either construction of T for a width.
-template <int NP, typename E = double>
+template <int NP, typename E = double, bool ROWS = false>
 __device__ __forceinline__ void make_T(const double* Gs, const double* taus, double* Tb, E* __restrict__ Tout,
                                        int lane)
 {
 #if defined(TSQR_T_BLOCKED)
-    if constexpr (NP > 16 && NP <= 32) build_T2<NP, E>(Gs, taus, Tb, Tout, lane);
+    if constexpr (NP > 16 && NP <= 32) build_T2<NP, E, ROWS>(Gs, taus, Tb, Tout, lane);
     else
 #endif
-    if constexpr (t_streamed(NP)) build_T<NP, E>(Gs, taus, Tout, lane);
-    else build_T_cols<NP, E>(Gs, taus, Tout, lane);
+    if constexpr (t_streamed(NP)) build_T<NP, E, ROWS>(Gs, taus, Tout, lane);
+    else build_T_cols<NP, E, ROWS>(Gs, taus, Tout, lane);
 }
 // Tile load/store in the factor layout.  The per-lane part of the address
 // (row rg, column cg) is one loop-invariant offset; the rest is uniform, so the
@@ -604,7 +682,10 @@ __device__ __forceinline__ void store_tile(const E (&a)[RL][NP / LC], E* tb, int
 // running triangle R and the Gram entries of T stay FP64.  V goes to a
 // workspace of whole tiles (rows past m and columns past n are zeros) and T is
 // rounded to FP32.
-template <int NP, bool WANT_Q, typename E>
+// DEFER_T: each tile's T slot receives tau and the Gram entries (gram_out) and
+// k_build_T forms T afterwards, so the leaf's LDS holds no Gram area; else T
+// is formed here.
+template <int NP, bool WANT_Q, typename E, bool DEFER_T = false>
 __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, int64_t ldv, int64_t m, int n,
                                            int64_t P, int64_t leaf_rows, int64_t f, E* __restrict__ Ttile,
                                            double* __restrict__ Rleaf, int64_t leaf, double* wsm, int lane)
@@ -612,7 +693,8 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
     constexpr bool MIXED = sizeof(E) == 4;
     constexpr int LC = col_groups(NP), LR = 64 / LC, MT = tile_rows_e<E>(NP), RL = MT / LR, KC = NP / LC;
     constexpr int NT = packed_size(NP);
-    constexpr int GA = WANT_Q ? gram_area(NP) : 0;
+    constexpr int CH = leaf_gram_chunk<E>(NP, MT);
+    constexpr int GA = !WANT_Q ? 0 : DEFER_T ? (CH * (NP + 1) + 1) / 2 * 2 : gram_area(NP);
     const int cg = lane / LR, rg = lane % LR;
     double* Rs = wsm;
     double* Gs = Rs + r_area(NP);
@@ -648,8 +730,12 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
             scale_tile<NP, RL, LC, true, E>(a, sc, lane);
             // the mixed workspace takes whole tiles (zero rows and columns included)
             store_tile<NP, RL, LC, E>(a, V + row0, ldv, lane_off_v, MIXED ? MT : valid, MIXED ? NP : n, rg, cg);
-            gram_mfma<NP, RL, LC, true, E>(a, Gs, Gs, lane);
-            make_T<NP, E>(Gs, taus, taus + NP, Ttile + (leaf * f) * NT, lane);
+            if (DEFER_T) {
+                gram_out<NP, RL, LC, true, CH, E>(a, Gs, taus, Ttile + (leaf * f) * NT, lane);
+            } else {
+                gram_mfma<NP, RL, LC, true, E>(a, Gs, Gs, lane);
+                make_T<NP, E>(Gs, taus, taus + NP, Ttile + (leaf * f) * NT, lane);
+            }
         }
     }
     for (int64_t t = 1; t < ntl; ++t) {
@@ -660,8 +746,12 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
         if (WANT_Q) {
             scale_tile<NP, RL, LC, false, E>(a, sc, lane);
             store_tile<NP, RL, LC, E>(a, V + t0, ldv, lane_off_v, MIXED ? MT : valid, MIXED ? NP : n, rg, cg);
-            gram_mfma<NP, RL, LC, false, E>(a, Gs, Gs, lane);
-            make_T<NP, E>(Gs, taus, taus + NP, Ttile + (leaf * f + t) * NT, lane);
+            if (DEFER_T) {
+                gram_out<NP, RL, LC, false, CH, E>(a, Gs, taus, Ttile + (leaf * f + t) * NT, lane);
+            } else {
+                gram_mfma<NP, RL, LC, false, E>(a, Gs, Gs, lane);
+                make_T<NP, E>(Gs, taus, taus + NP, Ttile + (leaf * f + t) * NT, lane);
+            }
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -677,14 +767,147 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                                                      int64_t m, int n, int64_t P, int64_t leaf_rows, int64_t f,
                                                      E* __restrict__ Ttile, double* __restrict__ Rleaf)
 {
-    constexpr int WS = factor_lds_doubles<E>(NP, tile_rows_e<E>(NP), WANT_Q);
+    constexpr int WS = leaf_lds_doubles<E>(NP, tile_rows_e<E>(NP), WANT_Q);
     extern __shared__ double smem[];
     const int wave = wave_index(), lane = threadIdx.x & 63;
     const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (leaf >= P) return;
-    leaf_chain<NP, WANT_Q, E>(A, lda, V, ldv, m, n, P, leaf_rows, f, Ttile, Rleaf, leaf, smem + wave * WS, lane);
+    leaf_chain<NP, WANT_Q, E, true>(A, lda, V, ldv, m, n, P, leaf_rows, f, Ttile, Rleaf, leaf, smem + wave * WS,
+                                    lane);
 }
 
+// T of every leaf tile (slots 0 .. ntiles-1, one wavefront each) from the tau
+// and Gram entries the leaf kernel left in the slot (see gram_out), in place,
+// in 16-column blocks (NB = ceil(NP / 16)):
+//  - the diagonal blocks T_bb by the column recurrence of build_T, block b on
+//    lanes 16b .. 16b+15 (lane 16b + r builds its row r), all blocks at once;
+//  - then block column j = 1 .. NB-1 from the columns left of it on the matrix
+//    cores, T(0:16j, blk j) = -T(0:16j, 0:16j) G(0:16j, blk j) T_jj (the
+//    compact-WY product of two reflector blocks, Sec. 3.2): X_i = G_ij T_jj,
+//    T_ij = -sum_{k=i}^{j-1} T_ik X_k.
+// Each lane reads only its own operands (no broadcast of the whole Gram to
+// every lane).  The blocks of T are staged in LDS at stride 17 (16 x 17
+// doubles); the dense diagonal Gram blocks are staged in the space of the
+// off-diagonal T blocks where it suffices (they are consumed before those are
+// written).  Every read of the slot comes before the first write of T.
+template <int NP>
+struct BuildTLds {
+    static constexpr int NB = round16(NP) / 16, NBLK = NB * (NB + 1) / 2;
+    static constexpr bool GD_SHARED = (NBLK - NB) * 272 >= NB * 256;
+    static constexpr int GD_OFF = GD_SHARED ? NB * 272 : NBLK * 272;
+    static constexpr int TAU_OFF = GD_SHARED ? NBLK * 272 : NBLK * 272 + NB * 256;
+    static constexpr int WS = TAU_OFF + 64;
+};
+
+template <int NP, typename E>
+__device__ __forceinline__ void build_T_slot(E* __restrict__ slot, double* W, int lane)
+{
+    using S = BuildTLds<NP>;
+    constexpr int NB = S::NB, NOFF = NB * (NB - 1) / 2;
+    double* Gd = W + S::GD_OFF;
+    double* taus = W + S::TAU_OFF;
+    const E* gsl = slot + NP;
+    const int q = lane >> 4, p = lane & 15;
+
+    // ---- reads: tau, the dense diagonal Gram blocks, the off-diagonal ones as
+    // A operands (ga[o][s] = G(16 i + p, 16 j + 4 s + q) for the o-th pair i < j)
+    const double tau_l = lane < NP ? (double)slot[lane] : 0.0;
+    double gdv[NB * 4];
+#pragma unroll
+    for (int u = 0; u < NB * 4; ++u) {
+        const int e = 64 * u + lane, bb = e >> 8, jl = (e >> 4) & 15, kl = e & 15, j = 16 * bb + jl;
+        gdv[u] = (kl < jl && j < NP) ? (double)gsl[grow(NP, 16 * bb + kl, j)] : 0.0;
+    }
+    double ga[NOFF > 0 ? NOFF : 1][4];
+#pragma unroll
+    for (int j = 1; j < NB; ++j)
+#pragma unroll
+        for (int i = 0; i < j; ++i)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int col = 16 * j + 4 * s + q;
+                ga[j * (j - 1) / 2 + i][s] = col < NP ? (double)gsl[grow(NP, 16 * i + p, col)] : 0.0;
+            }
+    taus[lane] = tau_l;
+#pragma unroll
+    for (int u = 0; u < NB * 4; ++u) Gd[64 * u + lane] = gdv[u];
+    __builtin_amdgcn_wave_barrier();
+
+    // ---- diagonal blocks (columns past NP have tau = 0 and come out zero)
+    {
+        const int b = q < NB ? q : NB - 1, r = p;
+        const double* gb = Gd + 256 * b;
+        const double* tb = taus + 16 * b;
+        double* td = W + 272 * b + r;
+        double tr[16];
+#pragma unroll
+        for (int jl = 0; jl < 16; ++jl) tr[jl] = 0.0;
+#pragma unroll
+        for (int jl = 0; jl < 16; ++jl) {
+            const double tj = tb[jl];
+            double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+            for (int kl = 0; kl < jl; ++kl) {
+                if (kl & 1) acc1 = fma(tr[kl], gb[16 * jl + kl], acc1);
+                else acc0 = fma(tr[kl], gb[16 * jl + kl], acc0);
+            }
+            const double v = (r < jl) ? -tj * (acc0 + acc1) : (r == jl ? tj : 0.0);
+            tr[jl] = v;
+            if (q < NB) td[17 * jl] = v;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();  // the diagonal blocks are read across lanes, Gd is dead
+
+    // ---- block columns 1 .. NB-1
+#pragma unroll
+    for (int j = 1; j < NB; ++j) {
+        const double* Tjj = W + 272 * j;
+        dbl4 X[NB > 1 ? NB - 1 : 1];
+#pragma unroll
+        for (int i = 0; i < j; ++i) {
+            X[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                X[i] = mfma16x16x4(ga[j * (j - 1) / 2 + i][s], Tjj[(4 * s + q) + 17 * p], X[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < j; ++i) {
+            dbl4 Y = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = i; k < j; ++k) {
+                const double* Tik = W + 272 * (k == i ? i : NB + k * (k - 1) / 2 + i);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) Y = mfma16x16x4(Tik[p + 17 * (4 * s + q)], X[k][s], Y);
+            }
+            double* Tij = W + 272 * (NB + j * (j - 1) / 2 + i);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) Tij[(4 * rr + q) + 17 * p] = -Y[rr];
+        }
+        __builtin_amdgcn_wave_barrier();  // block column j is an operand of the next ones
+    }
+
+    // ---- T packed by columns (column c at c(c+1)/2), lane r writes row r
+    const int bi = lane >> 4, rl = lane & 15;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+        const int cb = c / 16;
+        const int blk = bi == cb ? cb : NB + cb * (cb - 1) / 2 + (bi < cb ? bi : 0);
+        const double v = W[272 * blk + rl + 17 * (c % 16)];
+        if (lane <= c) slot[c * (c + 1) / 2 + lane] = (E)v;
+    }
+    __builtin_amdgcn_wave_barrier();  // a next slot rewrites this wave's LDS
+}
+
+template <int NP, typename E>
+__global__ void __launch_bounds__(256) k_build_T(E* __restrict__ Ttile, int64_t ntiles)
+{
+    extern __shared__ double smem[];
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (g >= ntiles) return;
+    build_T_slot<NP, E>(Ttile + g * packed_size(NP), smem + wave * BuildTLds<NP>::WS, lane);
+}
 // --------------------------------------------------------------------------
 // One level of the binary tree: node q stacks R_{2q} on R_{2q+1} (lower index
 // on top) and factors the pair; an odd last entry is passed up unchanged
@@ -1607,7 +1830,7 @@ hipError_t leaf_factor_np(const Layout& L, const double* A, int64_t lda, double*
                           bool want_q, hipStream_t s)
 {
     constexpr int MT = tile_rows_for(NP);
-    const size_t lds = (size_t)L.waves * factor_lds_doubles(NP, MT, want_q) * sizeof(double);
+    const size_t lds = (size_t)L.waves * leaf_lds_doubles(NP, MT, want_q) * sizeof(double);
     const dim3 grid(grid_for(L.P, L.waves)), block(64 * L.waves);
     if (want_q) {
         allow_lds(k_leaf_factor<NP, true>, lds);
@@ -1617,6 +1840,25 @@ hipError_t leaf_factor_np(const Layout& L, const double* A, int64_t lda, double*
         allow_lds(k_leaf_factor<NP, false>, lds);
         hipLaunchKernelGGL((k_leaf_factor<NP, false>), grid, block, lds, s, A, lda, V, ldv, L.m, (int)L.n, L.P,
                            L.leaf_rows, L.f, ws + L.off_T, ws + L.off_R[0]);
+    }
+    return hipGetLastError();
+}
+
+// T of every leaf tile from what the leaf kernel left in its slot (FP32 slots
+// for the mixed path).
+template <int NP>
+hipError_t build_T_np(const Layout& L, double* ws, hipStream_t s)
+{
+    constexpr int waves = 4;
+    const size_t lds = (size_t)waves * BuildTLds<NP>::WS * sizeof(double);
+    const dim3 grid(grid_for(L.ntiles, waves)), block(64 * waves);
+    if (L.mixed) {
+        allow_lds(k_build_T<NP, float>, lds);
+        hipLaunchKernelGGL((k_build_T<NP, float>), grid, block, lds, s, reinterpret_cast<float*>(ws + L.off_T32),
+                           L.ntiles);
+    } else {
+        allow_lds(k_build_T<NP, double>, lds);
+        hipLaunchKernelGGL((k_build_T<NP, double>), grid, block, lds, s, ws + L.off_T, L.ntiles);
     }
     return hipGetLastError();
 }
@@ -1726,7 +1968,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                                                     const BatchArgs* __restrict__ args, double* ws,
                                                     const int64_t* __restrict__ items, int64_t nitems)
 {
-    constexpr int WS = factor_lds_doubles<double>(NP, tile_rows_for(NP), WANT_Q);
+    constexpr int WS = leaf_lds_doubles<double>(NP, tile_rows_for(NP), WANT_Q);
     extern __shared__ double smem[];
     const int wave = wave_index(), lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -1736,9 +1978,32 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         const BatchProblem& B = probs[p];
         const BatchArgs X = args[p];
         double* w = ws + B.ws_off;
-        leaf_chain<NP, WANT_Q, double>(X.A, X.lda, X.A, X.lda, B.m, B.n, B.P, B.leaf_rows, B.f, w + B.off_T,
-                                       w + B.off_R[0], leaf, smem + wave * WS, lane);
+        leaf_chain<NP, WANT_Q, double, true>(X.A, X.lda, X.A, X.lda, B.m, B.n, B.P, B.leaf_rows, B.f,
+                                             w + B.off_T, w + B.off_R[0], leaf, smem + wave * WS, lane);
         __builtin_amdgcn_wave_barrier();  // the next item rewrites this wave's LDS
+    }
+}
+
+// T of every tile of every leaf item (the tiles of one leaf on one wavefront),
+// from what k_leaf_batch left in the slots; the arithmetic of k_build_T.
+template <int NP>
+__global__ void __launch_bounds__(256) k_build_T_batch(const BatchProblem* __restrict__ probs, double* ws,
+                                                       const int64_t* __restrict__ items, int64_t nitems)
+{
+    constexpr int MT = tile_rows_for(NP), NT = packed_size(NP);
+    extern __shared__ double smem[];
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    double* W = smem + wave * BuildTLds<NP>::WS;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < nitems; it += nw) {
+        const int64_t item = items[it];
+        const int64_t p = item >> 32, leaf = item & 0xffffffff;
+        const BatchProblem& B = probs[p];
+        const int64_t row0 = leaf * B.leaf_rows;
+        const int64_t rows = (leaf == B.P - 1) ? (B.m - row0) : B.leaf_rows;
+        const int64_t ntl = (rows + MT - 1) / MT;
+        double* T = ws + B.ws_off + B.off_T + leaf * B.f * NT;
+        for (int64_t t = 0; t < ntl; ++t) build_T_slot<NP, double>(T + t * NT, W, lane);
     }
 }
 
@@ -1829,7 +2094,7 @@ hipError_t batch_factor_np(const BatchClass& C, const BatchProblem* probs, const
                            bool want_q, int waves, hipStream_t s)
 {
     {
-        const size_t lds = (size_t)waves * factor_lds_doubles(NP, tile_rows_for(NP), want_q) * sizeof(double);
+        const size_t lds = (size_t)waves * leaf_lds_doubles(NP, tile_rows_for(NP), want_q) * sizeof(double);
         const dim3 grid(batch_grid(C.n_leaf, waves)), block(64 * waves);
         if (want_q) {
             allow_lds(k_leaf_batch<NP, true>, lds);
@@ -1840,6 +2105,13 @@ hipError_t batch_factor_np(const BatchClass& C, const BatchProblem* probs, const
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        if (want_q) {
+            const size_t blds = (size_t)waves * BuildTLds<NP>::WS * sizeof(double);
+            allow_lds(k_build_T_batch<NP>, blds);
+            hipLaunchKernelGGL((k_build_T_batch<NP>), grid, block, blds, s, probs, ws, C.leaf_items, C.n_leaf);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
     const int tw = NP <= 32 ? 4 : 2;
     const size_t tlds = (size_t)tw * factor_lds_doubles(NP, round16(NP), want_q) * sizeof(double);
@@ -1888,7 +2160,7 @@ template <int NP>
 hipError_t mixed_leaf_np(const Layout& L, const double* A, int64_t lda, double* ws, bool want_q, hipStream_t s)
 {
     constexpr int MT = tile_rows_f32(NP);
-    const size_t lds = (size_t)L.waves * factor_lds_doubles<float>(NP, MT, want_q) * sizeof(double);
+    const size_t lds = (size_t)L.waves * leaf_lds_doubles<float>(NP, MT, want_q) * sizeof(double);
     const dim3 grid(grid_for(L.P, L.waves)), block(64 * L.waves);
     float* V32 = reinterpret_cast<float*>(ws + L.off_V32);
     float* T32 = reinterpret_cast<float*>(ws + L.off_T32);
@@ -1968,6 +2240,17 @@ hipError_t leaf_factor_np(const Layout& L, const double* A, int64_t lda, double*
     return detail::leaf_factor_np<NP>(L, A, lda, V, ldv, ws, want_q, s);
 }
 template <int NP>
+hipError_t build_T_np(const Layout& L, double* ws, hipStream_t s)
+{
+    return detail::build_T_np<NP>(L, ws, s);
+}
+template <int NP>
+int leaf_lds_bytes_np(bool mixed, bool want_q)
+{
+    return 8 * (mixed ? detail::leaf_lds_doubles<float>(NP, tile_rows_f32(NP), want_q)
+                      : detail::leaf_lds_doubles<double>(NP, tile_rows_for(NP), want_q));
+}
+template <int NP>
 hipError_t tree_np(const Layout& L, double* ws, bool want_q, hipStream_t s)
 {
     return detail::tree_np<NP>(L, ws, want_q, s);
@@ -2033,6 +2316,8 @@ hipError_t batch_form_q_np(const BatchClass& C, const BatchProblem* probs, const
 #define TSQR_INSTANTIATE(NP)                                                                                   \
     template hipError_t leaf_factor_np<NP>(const Layout&, const double*, int64_t, double*, int64_t, double*, bool, \
                                            hipStream_t);                                                     \
+    template hipError_t build_T_np<NP>(const Layout&, double*, hipStream_t);                                   \
+    template int leaf_lds_bytes_np<NP>(bool, bool);                                                            \
     template hipError_t tree_np<NP>(const Layout&, double*, bool, hipStream_t);                                \
     template hipError_t root_np<NP>(const Layout&, double*, double*, int64_t, hipStream_t);                    \
     template hipError_t seeds_np<NP>(const Layout&, double*, hipStream_t);                                     \

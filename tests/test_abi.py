@@ -164,12 +164,13 @@ def test_tuned_options_reach_plan_query(tmp_path, monkeypatch):
 
 
 def test_mixed_plan_geometry():
-    """A mixed plan: FP32 tiles of the FP64 height, FP32 chains capped at 64
+    """A mixed plan: FP32 tiles of twice the FP64 height, FP32 chains capped at 64
     tiles, and a workspace that holds V32, Q1 and the second pass."""
     from paper_0809_2407_amd import tsqr as T
     f64 = T.plan_query(1 << 24, 64)
     mx = T.plan_query(1 << 24, 64, precision="mixed")
-    assert mx["precision"] == 1 and mx["tile_rows"] == f64["tile_rows"] == 64
+    # the FP32 tile of the mixed leaf holds twice the rows in the same registers
+    assert mx["precision"] == 1 and mx["tile_rows"] == 2 * f64["tile_rows"] == 128
     assert mx["leaf_rows"] <= 64 * mx["tile_rows"]
     # V32 and Q1: 2 x 4 bytes per element at least
     assert mx["workspace_bytes"] >= 8 * (1 << 24) * 64
