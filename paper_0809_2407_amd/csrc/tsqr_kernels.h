@@ -908,6 +908,29 @@ __global__ void __launch_bounds__(256) k_build_T(E* __restrict__ Ttile, int64_t 
     if (g >= ntiles) return;
     build_T_slot<NP, E>(Ttile + g * packed_size(NP), smem + wave * BuildTLds<NP>::WS, lane);
 }
+// Visits the NP x NP doubles at src, lane-strided (element idx = 64 u + lane),
+// with the global loads issued 16 at a time before their uses: a plain strided
+// loop waits for every load in turn.
+template <int NP, typename F>
+__device__ __forceinline__ void visit_block(const double* __restrict__ src, int lane, F&& f)
+{
+    constexpr int U = (NP * NP + 63) / 64, CHUNK = 16;
+#pragma unroll
+    for (int u0 = 0; u0 < U; u0 += CHUNK) {
+        double v[CHUNK];
+#pragma unroll
+        for (int u = 0; u < CHUNK; ++u) {
+            const int idx = 64 * (u0 + u) + lane;
+            v[u] = (u0 + u < U && idx < NP * NP) ? src[idx] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < CHUNK; ++u) {
+            const int idx = 64 * (u0 + u) + lane;
+            if (u0 + u < U && idx < NP * NP) f(idx, v[u]);
+        }
+    }
+}
+
 // --------------------------------------------------------------------------
 // One level of the binary tree: node q stacks R_{2q} on R_{2q+1} (lower index
 // on top) and factors the pair; an odd last entry is passed up unchanged
@@ -929,17 +952,17 @@ __device__ __forceinline__ void tree_node(const double* __restrict__ Rin, int64_
     const double* Ra = Rin + ia * NP * NP;
     double* Ro = Rout + q * NP * NP;
     if (ib >= cin) {
-        for (int idx = lane; idx < NP * NP; idx += 64) Ro[idx] = Ra[idx];
+        visit_block<NP>(Ra, lane, [&](int idx, double v) { Ro[idx] = v; });
         return;
     }
     double* Rs = wsm;
     double* Gs = Rs + r_area(NP);
     double* vb = Gs + GA;
     double* taus = vb + LR * vb_stride(RLN);
-    for (int idx = lane; idx < NP * NP; idx += 64) {
+    visit_block<NP>(Ra, lane, [&](int idx, double v) {
         const int r = idx % NP, c = idx / NP;
-        if (r <= c) Rs[rpk<NP>(r, c)] = Ra[idx];
-    }
+        if (r <= c) Rs[rpk<NP>(r, c)] = v;
+    });
     const double* Rb = Rin + ib * NP * NP;
     double a[RLN][KC], sc[KC];
 #pragma unroll
@@ -1116,7 +1139,7 @@ __device__ __forceinline__ void seed_node(const double* __restrict__ Sp, const d
     const int64_t ia = 2 * q, ib = 2 * q + 1;
     const double* S = Sp + q * NP * NP;
     if (ib >= cin) {
-        for (int idx = lane; idx < NP * NP; idx += 64) Sc[ia * NP * NP + idx] = S[idx];
+        visit_block<NP>(S, lane, [&](int idx, double v) { Sc[ia * NP * NP + idx] = v; });
         return;
     }
     double Sr[KS][JB], Zr[KS][JB];
