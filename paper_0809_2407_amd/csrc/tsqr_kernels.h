@@ -183,21 +183,37 @@ __host__ __device__ constexpr int factor_lds_doubles(int np, int tile_rows, bool
            ((64 / col_groups(np)) * vb_stride_e<E>(tile_rows / (64 / col_groups(np))) * (int)sizeof(E) + 7) / 8 +
            np + (want_q ? tb_area(np) : 0);
 }
+// Widths whose FP64 leaf factors chained tiles in 16-column panels with the
+// trailing update on the matrix cores (factor_tile_blocked), one bit per width
+// np = 4 (bit + 1); they use the four-group layout.
+#ifndef TSQR_BLOCKED_MASK
+#define TSQR_BLOCKED_MASK 0x80ull  // np = 32
+#endif
+template <typename E = double>
+__host__ __device__ constexpr bool leaf_blocked(int np)
+{
+    return sizeof(E) == 8 && np % 16 == 0 && ((TSQR_BLOCKED_MASK >> (np / 4 - 1)) & 1);
+}
+template <typename E = double>
+__host__ __device__ constexpr int leaf_col_groups(int np) { return leaf_blocked<E>(np) ? 4 : col_groups(np); }
 // The single-problem leaf kernel leaves T to k_build_T: with Q it keeps only a
 // chunk buffer of the Gram (CH rows of np + 1 doubles).  CH = 16 where the
 // per-wave LDS then stays within 20 KiB (two wavefronts per SIMD), else 4.
+// Blocked widths also hold the chunk buffer without Q, and the panel's dense
+// Gram and T (256 + 272 doubles).
 template <typename E = double>
 __host__ __device__ constexpr int leaf_lds_doubles_ch(int np, int tile_rows, bool want_q, int ch)
 {
-    return r_area(np) + (want_q ? (ch * (np + 1) + 1) / 2 * 2 : 0) +
-           ((64 / col_groups(np)) * vb_stride_e<E>(tile_rows / (64 / col_groups(np))) * (int)sizeof(E) + 7) / 8 +
-           np;
+    return r_area(np) + (want_q || leaf_blocked<E>(np) ? (ch * (np + 1) + 1) / 2 * 2 : 0) +
+           ((64 / leaf_col_groups<E>(np)) * vb_stride_e<E>(tile_rows / (64 / leaf_col_groups<E>(np))) *
+                (int)sizeof(E) + 7) / 8 +
+           np + (leaf_blocked<E>(np) ? 256 + 272 : 0);
 }
 constexpr int kLeafLdsBudget = 20480 / 8;  // doubles per wavefront for two wavefronts per SIMD
 template <typename E = double>
 __host__ __device__ constexpr int leaf_gram_chunk(int np, int tile_rows)
 {
-    return leaf_lds_doubles_ch<E>(np, tile_rows, true, 16) <= kLeafLdsBudget ? 16 : 4;
+    return leaf_blocked<E>(np) || leaf_lds_doubles_ch<E>(np, tile_rows, true, 16) <= kLeafLdsBudget ? 16 : 4;
 }
 template <typename E = double>
 __host__ __device__ constexpr int leaf_lds_doubles(int np, int tile_rows, bool want_q)
@@ -229,7 +245,9 @@ __host__ __device__ constexpr int tile_rows_e(int np) { return sizeof(E) == 8 ? 
 // The magnitudes are assumed to keep (alpha - beta) * beta within the normal
 // FP64 range (no scaling of the column norm).
 // --------------------------------------------------------------------------
-template <int NP, int RL, int LC, bool FIRST, typename E = double>
+// KLO, KHI: factor only the columns held in slots [KLO, KHI) and update only
+// those (a panel of the blocked factorization below); the default is the tile.
+template <int NP, int RL, int LC, bool FIRST, typename E = double, int KLO = 0, int KHI = NP / LC>
 __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC], double* Rs, E* vb,
                                             double* taus, int lane)
 {
@@ -239,7 +257,7 @@ __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC
 #pragma unroll
     for (int k = 0; k < KC; ++k) sc[k] = E(1);
 #pragma unroll
-    for (int kb = 0; kb < KC; ++kb) {
+    for (int kb = KLO; kb < KHI; ++kb) {
         const int ij = (LC * kb) / LR;   // register slot of the pivot rows of this block
         const int rg0 = (LC * kb) % LR;  // lane (within a group) of the block's first pivot row
 #pragma unroll 1
@@ -292,7 +310,7 @@ __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
                 d[k] = E(0);
-                if (k < kb) continue;
+                if (k < kb || k >= KHI) continue;
                 E acc0 = E(0), acc1 = E(0);
 #pragma unroll
                 for (int i = 0; i < RL; ++i) {
@@ -304,7 +322,7 @@ __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
                 const int c = LC * k + cg;
-                if (k < kb) continue;
+                if (k < kb || k >= KHI) continue;
                 // k == kb: only the columns right of the pivot are trailing
                 const bool trailing = (k > kb) || (cg > cgj);
                 double w = (double)d[k];
@@ -328,6 +346,120 @@ __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC
     }
     // R and tau are read by other lanes after the tile
     __builtin_amdgcn_wave_barrier();
+}
+
+// --------------------------------------------------------------------------
+// Blocked factorization of a chained tile ([R; A_k], reflectors [e_j; y_j]) in
+// the four-group layout (LC = 4: lane 16 cg + rg holds rows 16 i + rg, columns
+// 4 k + cg), in panels of 16 columns (four slots).  A panel is factored by
+// factor_tile restricted to its slots; its reflectors are scaled in place; then
+// every later 16-column block C (slots 4b .. 4b+3) takes the panel's compact-WY
+// update at once (Sec. 3.2):
+//   W = R(P, C) + Y_P^T A_C,   W' = T_P^T W,   R(P, C) -= W',   A_C -= Y_P W'.
+// Y_P^T [Y_P | A_C] contracts over rows, which sit on the lanes of a group, so
+// 16-row chunks go through LDS (cb) into the f64 16x16x4 operand layout, as in
+// gram_accumulate; Y_P^T Y_P gives T_P by the recurrence of build_T (Gd: dense
+// 16 x 16 Gram, Ts: T_P at stride 17).  A_C -= Y_P W' maps the register layout
+// onto itself: the output rows 4r + q of the op are the columns 4r + cg of slot
+// 4b + r, its columns p the rows 16 i + rg, and the B operand of K step s is
+// slot 4P + s of the same rows.
+// --------------------------------------------------------------------------
+template <int NP, int RL, int P>
+__device__ __forceinline__ void panel_update(double (&a)[RL][NP / 4], double* Rs, double* cb, double* Gd,
+                                             double* Ts, const double* taus, int lane)
+{
+    constexpr int NB = NP / 16, LDP = NP + 1, NL = NB - P - 1;  // later 16-column blocks
+    const int q = lane >> 4, p = lane & 15;
+    dbl4 G = dbl4{0.0, 0.0, 0.0, 0.0};
+    dbl4 Z[NL > 0 ? NL : 1];
+#pragma unroll
+    for (int b = 0; b < NL; ++b) Z[b] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+        // chunk = rows 16 i .. 16 i + 15: lane (q, p) holds row p of it, columns 4 k + q
+#pragma unroll
+        for (int k = 4 * P; k < NP / 4; ++k) cb[p * LDP + 4 * k + q] = a[i][k];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const double y = cb[(4 * s + q) * LDP + 16 * P + p];  // Y_P(4s + q, p)
+            G = mfma16x16x4(y, y, G);
+#pragma unroll
+            for (int b = 0; b < NL; ++b) Z[b] = mfma16x16x4(y, cb[(4 * s + q) * LDP + 16 * (P + 1 + b) + p], Z[b]);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    // T_P: lane (q, p) holds G(4r + q, p); the recurrence on row p (every group alike)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Gd[16 * p + 4 * r + q] = (4 * r + q < p) ? G[r] : 0.0;
+    __builtin_amdgcn_wave_barrier();
+    {
+        const double* tb = taus + 16 * P;
+        double tr[16];
+#pragma unroll
+        for (int jl = 0; jl < 16; ++jl) tr[jl] = 0.0;
+#pragma unroll
+        for (int jl = 0; jl < 16; ++jl) {
+            const double tj = tb[jl];
+            double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+            for (int kl = 0; kl < jl; ++kl) {
+                if (kl & 1) acc1 = fma(tr[kl], Gd[16 * jl + kl], acc1);
+                else acc0 = fma(tr[kl], Gd[16 * jl + kl], acc0);
+            }
+            const double v = (p < jl) ? -tj * (acc0 + acc1) : (p == jl ? tj : 0.0);
+            tr[jl] = v;
+            if (q == 0) Ts[p + 17 * jl] = v;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int b = 0; b < NL; ++b) {
+        const int c0 = 16 * (P + 1 + b);
+        // W = R(16P + 4r + q, c0 + p) + Z[r];  W' = T_P^T W
+        dbl4 Rv, Wv;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Rv[r] = Rs[rpk<NP>(16 * P + 4 * r + q, c0 + p)];
+            Wv[r] = Rv[r] + Z[b][r];
+        }
+        dbl4 Wp = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) Wp = mfma16x16x4(Ts[(4 * s + q) + 17 * p], Wv[s], Wp);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Rs[rpk<NP>(16 * P + 4 * r + q, c0 + p)] = Rv[r] - Wp[r];
+        // A_C -= Y_P W', one 16-row block at a time, in place
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+            dbl4 c = dbl4{a[i][4 * (P + 1 + b) + 0], a[i][4 * (P + 1 + b) + 1], a[i][4 * (P + 1 + b) + 2],
+                          a[i][4 * (P + 1 + b) + 3]};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) c = mfma16x16x4(-Wp[s], a[i][4 * P + s], c);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[i][4 * (P + 1 + b) + r] = c[r];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The blocked chained factorization (FP64, LC = 4, NP a multiple of 16).
+// On return every reflector is scaled (sc is all ones).
+template <int NP, int RL, int P = 0>
+__device__ __forceinline__ void factor_tile_blocked(double (&a)[RL][NP / 4], double (&sc)[NP / 4], double* Rs,
+                                                    double* vb, double* taus, double* cb, double* Gd, double* Ts,
+                                                    int lane)
+{
+    factor_tile<NP, RL, 4, false, double, 4 * P, 4 * P + 4>(a, sc, Rs, vb, taus, lane);
+#pragma unroll
+    for (int k = 4 * P; k < 4 * P + 4; ++k) {
+#pragma unroll
+        for (int i = 0; i < RL; ++i) a[i][k] *= sc[k];
+        sc[k] = 1.0;
+    }
+    if constexpr (P + 1 < NP / 16) {
+        panel_update<NP, RL, P>(a, Rs, cb, Gd, Ts, taus, lane);
+        factor_tile_blocked<NP, RL, P + 1>(a, sc, Rs, vb, taus, cb, Gd, Ts, lane);
+    }
 }
 
 // Applies the deferred reflector scales: y = x * sc below the diagonal (FIRST)
@@ -691,15 +823,19 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
                                            double* __restrict__ Rleaf, int64_t leaf, double* wsm, int lane)
 {
     constexpr bool MIXED = sizeof(E) == 4;
-    constexpr int LC = col_groups(NP), LR = 64 / LC, MT = tile_rows_e<E>(NP), RL = MT / LR, KC = NP / LC;
+    constexpr bool BLK = leaf_blocked<E>(NP);
+    constexpr int LC = leaf_col_groups<E>(NP), LR = 64 / LC, MT = tile_rows_e<E>(NP), RL = MT / LR, KC = NP / LC;
     constexpr int NT = packed_size(NP);
     constexpr int CH = leaf_gram_chunk<E>(NP, MT);
-    constexpr int GA = !WANT_Q ? 0 : DEFER_T ? (CH * (NP + 1) + 1) / 2 * 2 : gram_area(NP);
+    constexpr int GA = (!WANT_Q && !BLK) ? 0 : DEFER_T ? (CH * (NP + 1) + 1) / 2 * 2 : gram_area(NP);
+    static_assert(!BLK || DEFER_T, "the blocked leaf keeps no Gram area for an in-kernel T");
     const int cg = lane / LR, rg = lane % LR;
     double* Rs = wsm;
     double* Gs = Rs + r_area(NP);
     E* vb = reinterpret_cast<E*>(Gs + GA);
     double* taus = Gs + GA + (LR * vb_stride_e<E>(RL) * (int)sizeof(E) + 7) / 8;
+    double* Gd = taus + NP;  // blocked widths: the panel's dense Gram, then its T
+    double* Ts = Gd + 256;
 
     const int64_t row0 = leaf * leaf_rows;
     const int64_t rows = (leaf == P - 1) ? (m - row0) : leaf_rows;
@@ -742,7 +878,8 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
         const int64_t t0 = row0 + t * MT;
         const int64_t valid = (rows - t * MT) < MT ? (rows - t * MT) : MT;
         load_tile<NP, RL, LC, E>(a, A + t0, lda, lane_off, valid, n, rg, cg);
-        factor_tile<NP, RL, LC, false, E>(a, sc, Rs, vb, taus, lane);
+        if constexpr (BLK) factor_tile_blocked<NP, RL>(a, sc, Rs, vb, taus, Gs, Gd, Ts, lane);
+        else factor_tile<NP, RL, LC, false, E>(a, sc, Rs, vb, taus, lane);
         if (WANT_Q) {
             scale_tile<NP, RL, LC, false, E>(a, sc, lane);
             store_tile<NP, RL, LC, E>(a, V + t0, ldv, lane_off_v, MIXED ? MT : valid, MIXED ? NP : n, rg, cg);
