@@ -199,15 +199,15 @@ __host__ __device__ constexpr int leaf_col_groups(int np) { return leaf_blocked<
 // The single-problem leaf kernel leaves T to k_build_T: with Q it keeps only a
 // chunk buffer of the Gram (CH rows of np + 1 doubles).  CH = 16 where the
 // per-wave LDS then stays within 20 KiB (two wavefronts per SIMD), else 4.
-// Blocked widths also hold the chunk buffer without Q, and the panel's dense
-// Gram and T (256 + 272 doubles).
+// Blocked widths also hold the chunk buffer without Q (the panel update uses
+// it).
 template <typename E = double>
 __host__ __device__ constexpr int leaf_lds_doubles_ch(int np, int tile_rows, bool want_q, int ch)
 {
     return r_area(np) + (want_q || leaf_blocked<E>(np) ? (ch * (np + 1) + 1) / 2 * 2 : 0) +
            ((64 / leaf_col_groups<E>(np)) * vb_stride_e<E>(tile_rows / (64 / leaf_col_groups<E>(np))) *
                 (int)sizeof(E) + 7) / 8 +
-           np + (leaf_blocked<E>(np) ? 256 + 272 : 0);
+           np;
 }
 constexpr int kLeafLdsBudget = 20480 / 8;  // doubles per wavefront for two wavefronts per SIMD
 template <typename E = double>
@@ -359,16 +359,20 @@ __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC
 // Y_P^T [Y_P | A_C] contracts over rows, which sit on the lanes of a group, so
 // 16-row chunks go through LDS (cb) into the f64 16x16x4 operand layout, as in
 // gram_accumulate; Y_P^T Y_P gives T_P by the recurrence of build_T (Gd: dense
-// 16 x 16 Gram, Ts: T_P at stride 17).  A_C -= Y_P W' maps the register layout
+// 16 x 16 Gram, Ts: T_P at stride 17, both in the chunk buffer once the chunks
+// are done: 16 (NP + 1) >= 256 + 272).  A_C -= Y_P W' maps the register layout
 // onto itself: the output rows 4r + q of the op are the columns 4r + cg of slot
 // 4b + r, its columns p the rows 16 i + rg, and the B operand of K step s is
 // slot 4P + s of the same rows.
 // --------------------------------------------------------------------------
 template <int NP, int RL, int P>
-__device__ __forceinline__ void panel_update(double (&a)[RL][NP / 4], double* Rs, double* cb, double* Gd,
-                                             double* Ts, const double* taus, int lane)
+__device__ __forceinline__ void panel_update(double (&a)[RL][NP / 4], double* Rs, double* cb, const double* taus,
+                                             int lane)
 {
     constexpr int NB = NP / 16, LDP = NP + 1, NL = NB - P - 1;  // later 16-column blocks
+    static_assert(16 * LDP >= 256 + 272, "the panel's Gram and T fit in the chunk buffer");
+    double* Gd = cb;
+    double* Ts = cb + 256;
     const int q = lane >> 4, p = lane & 15;
     dbl4 G = dbl4{0.0, 0.0, 0.0, 0.0};
     dbl4 Z[NL > 0 ? NL : 1];
@@ -446,8 +450,7 @@ __device__ __forceinline__ void panel_update(double (&a)[RL][NP / 4], double* Rs
 // On return every reflector is scaled (sc is all ones).
 template <int NP, int RL, int P = 0>
 __device__ __forceinline__ void factor_tile_blocked(double (&a)[RL][NP / 4], double (&sc)[NP / 4], double* Rs,
-                                                    double* vb, double* taus, double* cb, double* Gd, double* Ts,
-                                                    int lane)
+                                                    double* vb, double* taus, double* cb, int lane)
 {
     factor_tile<NP, RL, 4, false, double, 4 * P, 4 * P + 4>(a, sc, Rs, vb, taus, lane);
 #pragma unroll
@@ -457,8 +460,8 @@ __device__ __forceinline__ void factor_tile_blocked(double (&a)[RL][NP / 4], dou
         sc[k] = 1.0;
     }
     if constexpr (P + 1 < NP / 16) {
-        panel_update<NP, RL, P>(a, Rs, cb, Gd, Ts, taus, lane);
-        factor_tile_blocked<NP, RL, P + 1>(a, sc, Rs, vb, taus, cb, Gd, Ts, lane);
+        panel_update<NP, RL, P>(a, Rs, cb, taus, lane);
+        factor_tile_blocked<NP, RL, P + 1>(a, sc, Rs, vb, taus, cb, lane);
     }
 }
 
@@ -834,8 +837,6 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
     double* Gs = Rs + r_area(NP);
     E* vb = reinterpret_cast<E*>(Gs + GA);
     double* taus = Gs + GA + (LR * vb_stride_e<E>(RL) * (int)sizeof(E) + 7) / 8;
-    double* Gd = taus + NP;  // blocked widths: the panel's dense Gram, then its T
-    double* Ts = Gd + 256;
 
     const int64_t row0 = leaf * leaf_rows;
     const int64_t rows = (leaf == P - 1) ? (m - row0) : leaf_rows;
@@ -878,7 +879,7 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
         const int64_t t0 = row0 + t * MT;
         const int64_t valid = (rows - t * MT) < MT ? (rows - t * MT) : MT;
         load_tile<NP, RL, LC, E>(a, A + t0, lda, lane_off, valid, n, rg, cg);
-        if constexpr (BLK) factor_tile_blocked<NP, RL>(a, sc, Rs, vb, taus, Gs, Gd, Ts, lane);
+        if constexpr (BLK) factor_tile_blocked<NP, RL>(a, sc, Rs, vb, taus, Gs, lane);
         else factor_tile<NP, RL, LC, false, E>(a, sc, Rs, vb, taus, lane);
         if (WANT_Q) {
             scale_tile<NP, RL, LC, false, E>(a, sc, lane);
