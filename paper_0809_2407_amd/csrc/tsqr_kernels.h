@@ -1333,7 +1333,18 @@ __global__ void __launch_bounds__(256) k_seed_level(const double* __restrict__ S
 // they read the same V tiles at about the same time, the second read coming
 // from L2.  The products run on the matrix cores; Q may alias V.
 // --------------------------------------------------------------------------
-constexpr int fq_col_blocks(int np) { return round16(np) / 16 <= 3 ? round16(np) / 16 : 1; }
+// Column windows of 16 per wavefront: all of them up to 48 columns; above, two
+// per wavefront in FP64 (a leaf on two wavefronts), all four in FP32 (one).
+// Every wavefront of a leaf reads the leaf's V and T tiles, so fewer, wider
+// windows cut that repeated traffic, as far as the registers allow.
+#ifndef TSQR_FQ_F32_WINDOWS
+#define TSQR_FQ_F32_WINDOWS 4
+#endif
+template <typename E = double>
+constexpr int fq_col_blocks(int np)
+{
+    return round16(np) / 16 <= 3 ? round16(np) / 16 : (sizeof(E) == 8 ? 2 : TSQR_FQ_F32_WINDOWS);
+}
 
 // E = float is the first pass of the mixed-precision path: V and T in FP32
 // from the mixed leaf kernel, the FP64 seeds rounded to FP32, products on the
@@ -1352,7 +1363,7 @@ __device__ __forceinline__ void form_q_leaf(const E* V, int64_t lda, int64_t m, 
     // k-steps of the expansion: the FP32 permutation of k mixes the columns of
     // a 16-block, so whole blocks are contracted (their padding is zero)
     constexpr int KX = MIXED ? KS : KC;
-    constexpr int JW = fq_col_blocks(NP), SPLIT = JB / JW;
+    constexpr int JW = fq_col_blocks<E>(NP), SPLIT = JB / JW;
     constexpr int FQU = NP > 48 ? 1 : 2;  // row blocks in flight; more spills at the widest tiles
     static_assert(JB % JW == 0, "column window must divide the padded width");
     typedef Mfma<E> MM;
@@ -1490,7 +1501,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                                                 int64_t leaf_rows, int64_t f, const E* __restrict__ Ttile,
                                                 const double* __restrict__ Sleaf, E* Q, int64_t ldq)
 {
-    constexpr int NPB = round16(NP), JW = fq_col_blocks(NP), SPLIT = NPB / 16 / JW;
+    constexpr int NPB = round16(NP), JW = fq_col_blocks<E>(NP), SPLIT = NPB / 16 / JW;
     extern __shared__ double smem_d[];
     E* smem = reinterpret_cast<E*>(smem_d);
     const int wave = wave_index(), lane = threadIdx.x & 63;
@@ -2073,7 +2084,7 @@ template <int NP>
 hipError_t form_q_np(const Layout& L, const double* A, int64_t lda, double* ws, double* Q, int64_t ldq,
                      hipStream_t s)
 {
-    constexpr int NPB = round16(NP), JW = fq_col_blocks(NP), SPLIT = NPB / 16 / JW;
+    constexpr int NPB = round16(NP), JW = fq_col_blocks<double>(NP), SPLIT = NPB / 16 / JW;
     const size_t lds = (size_t)L.waves * NPB * 16 * JW * sizeof(double);
     const dim3 grid(grid_for(L.P * SPLIT, L.waves)), block(64 * L.waves);
     if (lane_offsets_fit_32(lda) && lane_offsets_fit_32(ldq)) {
@@ -2224,7 +2235,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                                                     const BatchArgs* __restrict__ args, double* ws,
                                                     const int64_t* __restrict__ items, int64_t nitems)
 {
-    constexpr int NPB = round16(NP), JW = fq_col_blocks(NP), SPLIT = NPB / 16 / JW;
+    constexpr int NPB = round16(NP), JW = fq_col_blocks<double>(NP), SPLIT = NPB / 16 / JW;
     extern __shared__ double smem[];
     const int wave = wave_index(), lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -2303,7 +2314,7 @@ hipError_t batch_form_q_np(const BatchClass& C, const BatchProblem* probs, const
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    constexpr int NPB = round16(NP), JW = fq_col_blocks(NP), SPLIT = NPB / 16 / JW;
+    constexpr int NPB = round16(NP), JW = fq_col_blocks<double>(NP), SPLIT = NPB / 16 / JW;
     const size_t lds = (size_t)waves * NPB * 16 * JW * sizeof(double);
     allow_lds(k_form_q_batch<NP>, lds);
     hipLaunchKernelGGL((k_form_q_batch<NP>), dim3(batch_grid(C.n_leaf * SPLIT, waves)), dim3(64 * waves), lds, s,
@@ -2340,7 +2351,7 @@ hipError_t mixed_leaf_np(const Layout& L, const double* A, int64_t lda, double* 
 template <int NP>
 hipError_t form_q1_np(const Layout& L, double* ws, hipStream_t s)
 {
-    constexpr int NPB = round16(NP), JW = fq_col_blocks(NP), SPLIT = NPB / 16 / JW;
+    constexpr int NPB = round16(NP), JW = fq_col_blocks<float>(NP), SPLIT = NPB / 16 / JW;
     const size_t lds = (size_t)L.waves * NPB * 16 * JW * sizeof(float);
     const dim3 grid(grid_for(L.P * SPLIT, L.waves)), block(64 * L.waves);
     const float* V32 = reinterpret_cast<const float*>(ws + L.off_V32);
