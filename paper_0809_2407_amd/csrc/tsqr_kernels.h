@@ -944,17 +944,33 @@ __device__ __forceinline__ void build_T_slot(E* __restrict__ slot, double* W, in
     constexpr int NB = S::NB, NOFF = NB * (NB - 1) / 2;
     double* Gd = W + S::GD_OFF;
     double* taus = W + S::TAU_OFF;
-    const E* gsl = slot + NP;
     const int q = lane >> 4, p = lane & 15;
 
-    // ---- reads: tau, the dense diagonal Gram blocks, the off-diagonal ones as
-    // A operands (ga[o][s] = G(16 i + p, 16 j + 4 s + q) for the o-th pair i < j)
-    const double tau_l = lane < NP ? (double)slot[lane] : 0.0;
+    // ---- reads: tau, the dense diagonal Gram blocks and the off-diagonal ones
+    // as A operands (ga[o][s] = G(16 i + p, 16 j + 4 s + q) for the o-th pair
+    // i < j).  FP32 slots are first copied, coalesced, into LDS as they stand
+    // (the T-block area, not in use yet) and gathered there (per-lane gathers of
+    // 4-byte entries waste most of each line); FP64 entries are gathered from
+    // the slot directly, which measured faster.
+    constexpr int NT = packed_size(NP), U = (NT + 63) / 64;
+    constexpr bool STAGE = sizeof(E) == 4;
+    static_assert(NT <= S::NBLK * 272, "the slot fits in the T-block area");
+    if constexpr (STAGE) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = 64 * u + lane < NT ? (double)slot[64 * u + lane] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (64 * u + lane < NT) W[64 * u + lane] = v[u];
+        __builtin_amdgcn_wave_barrier();
+    }
+    auto graw = [&](int e) { return STAGE ? W[NP + e] : (double)slot[NP + e]; };
+    const double tau_l = lane < NP ? (STAGE ? W[lane] : (double)slot[lane]) : 0.0;
     double gdv[NB * 4];
 #pragma unroll
     for (int u = 0; u < NB * 4; ++u) {
         const int e = 64 * u + lane, bb = e >> 8, jl = (e >> 4) & 15, kl = e & 15, j = 16 * bb + jl;
-        gdv[u] = (kl < jl && j < NP) ? (double)gsl[grow(NP, 16 * bb + kl, j)] : 0.0;
+        gdv[u] = (kl < jl && j < NP) ? graw(grow(NP, 16 * bb + kl, j)) : 0.0;
     }
     double ga[NOFF > 0 ? NOFF : 1][4];
 #pragma unroll
@@ -964,8 +980,9 @@ __device__ __forceinline__ void build_T_slot(E* __restrict__ slot, double* W, in
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int col = 16 * j + 4 * s + q;
-                ga[j * (j - 1) / 2 + i][s] = col < NP ? (double)gsl[grow(NP, 16 * i + p, col)] : 0.0;
+                ga[j * (j - 1) / 2 + i][s] = col < NP ? graw(grow(NP, 16 * i + p, col)) : 0.0;
             }
+    __builtin_amdgcn_wave_barrier();  // Gd and tau below overwrite the staged slot
     taus[lane] = tau_l;
 #pragma unroll
     for (int u = 0; u < NB * 4; ++u) Gd[64 * u + lane] = gdv[u];
