@@ -129,6 +129,10 @@ struct tsqr_plan_s {
     tsqr_tree tree = TSQR_TREE_AUTO;
     int want_q = 1;
     hipStream_t stream = nullptr;
+    // plans with Q: the T kernel runs on a side stream, concurrently with the
+    // tree levels (both need only the leaves), joined back with an event
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     double* ws = nullptr;
     int state = 0;  // 0: nothing factored, 1: factored with reflectors, 2: R only
     // profiling: event pairs recorded since the last tsqr_plan_timings
@@ -146,17 +150,19 @@ tsqr_status hip_status(hipError_t e)
     return 1;
 }
 
-// Runs one launch phase, bracketed by events when profiling is on.
+// Runs one launch phase, bracketed by events when profiling is on (on stream s,
+// the plan's stream by default).
 template <typename F>
-hipError_t run_phase(tsqr_plan_s* p, int phase, F&& launch)
+hipError_t run_phase(tsqr_plan_s* p, int phase, F&& launch, hipStream_t s = nullptr)
 {
     if (!p->profile) return launch();
+    if (!s) s = p->stream;
     PhaseEvent ev{phase, nullptr, nullptr};
     hipError_t e = hipEventCreate(&ev.start);
     if (e == hipSuccess) e = hipEventCreate(&ev.stop);
-    if (e == hipSuccess) e = hipEventRecord(ev.start, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev.start, s);
     if (e == hipSuccess) e = launch();
-    if (e == hipSuccess) e = hipEventRecord(ev.stop, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev.stop, s);
     if (e == hipSuccess) {
         p->events.push_back(ev);
     } else {
@@ -164,6 +170,32 @@ hipError_t run_phase(tsqr_plan_s* p, int phase, F&& launch)
         if (ev.stop) hipEventDestroy(ev.stop);
     }
     return e;
+}
+
+// The T kernel after the leaves, on the side stream (fork); join_T makes the
+// plan's stream wait for it.
+hipError_t fork_T(tsqr_plan_s* p)
+{
+    hipError_t e = hipEventRecord(p->fork_ev, p->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork_ev, 0);
+    if (e == hipSuccess)
+        e = run_phase(p, TSQR_PHASE_LEAF_T, [&] { return tsqr::launch_build_T(p->L, p->ws, p->side); }, p->side);
+    if (e == hipSuccess) e = hipEventRecord(p->join_ev, p->side);
+    return e;
+}
+
+hipError_t join_T(tsqr_plan_s* p) { return hipStreamWaitEvent(p->stream, p->join_ev, 0); }
+
+void release_streams(tsqr_plan_s* p)
+{
+    if (p->side) {
+        hipStreamSynchronize(p->side);
+        hipStreamDestroy(p->side);
+    }
+    if (p->fork_ev) hipEventDestroy(p->fork_ev);
+    if (p->join_ev) hipEventDestroy(p->join_ev);
+    p->side = nullptr;
+    p->fork_ev = p->join_ev = nullptr;
 }
 
 hipError_t drain_events(tsqr_plan_s* p)
@@ -194,8 +226,7 @@ tsqr_status factor_mixed(tsqr_plan_s* p, const double* A, int64_t lda, double* R
     const bool want_q = p->want_q != 0;
     const tsqr::Layout& L = p->L;
     hipError_t e = run_phase(p, TSQR_PHASE_LEAF, [&] { return tsqr::launch_mixed_leaf(L, A, lda, p->ws, want_q, p->stream); });
-    if (e == hipSuccess && want_q)
-        e = run_phase(p, TSQR_PHASE_LEAF_T, [&] { return tsqr::launch_build_T(L, p->ws, p->stream); });
+    if (e == hipSuccess && want_q) e = fork_T(p);
     if (e == hipSuccess && L.levels > 0)
         e = run_phase(p, TSQR_PHASE_TREE, [&] { return tsqr::launch_tree(L, p->ws, want_q, p->stream); });
     if (e == hipSuccess)
@@ -205,6 +236,7 @@ tsqr_status factor_mixed(tsqr_plan_s* p, const double* A, int64_t lda, double* R
         });
     if (e == hipSuccess && want_q) {
         if (L.levels > 0) e = run_phase(p, TSQR_PHASE_SEEDS, [&] { return tsqr::launch_seeds(L, p->ws, p->stream); });
+        if (e == hipSuccess) e = join_T(p);
         if (e == hipSuccess) e = run_phase(p, TSQR_PHASE_Q1, [&] { return tsqr::launch_form_q1(L, p->ws, p->stream); });
         if (e == hipSuccess)
             e = run_phase(p, TSQR_PHASE_REORTH, [&] { return tsqr::launch_reorth(L, p->ws, R, ldr, p->stream); });
@@ -310,6 +342,17 @@ tsqr_status tsqr_plan_create(tsqr_plan* p, int64_t m, int64_t n, tsqr_precision 
         delete P;
         return hip_status(e);
     }
+    if (P->want_q) {
+        e = hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            release_streams(P);
+            hipFree(P->ws);
+            delete P;
+            return hip_status(e);
+        }
+    }
     if (P->L.mixed) {
         // the FP32 workspaces are read in whole tiles and 16-column blocks: what
         // the kernels never write (rows past the last tile, columns past np) stays zero
@@ -317,6 +360,7 @@ tsqr_status tsqr_plan_create(tsqr_plan* p, int64_t m, int64_t n, tsqr_precision 
         e = hipMemsetAsync(P->ws + P->L.off_V32, 0, bytes, P->stream);
         if (e == hipSuccess) e = hipMemsetAsync(P->ws + P->L.off_Q1, 0, bytes, P->stream);
         if (e != hipSuccess) {
+            release_streams(P);
             hipFree(P->ws);
             delete P;
             return hip_status(e);
@@ -345,12 +389,12 @@ tsqr_status tsqr_factor_into(tsqr_plan p, const double* A, int64_t lda, double* 
     hipError_t e = run_phase(p, TSQR_PHASE_LEAF, [&] {
         return tsqr::launch_leaf_factor(p->L, A, lda, V, want_q ? ldv : lda, p->ws, want_q, p->stream);
     });
-    if (e == hipSuccess && want_q)
-        e = run_phase(p, TSQR_PHASE_LEAF_T, [&] { return tsqr::launch_build_T(p->L, p->ws, p->stream); });
+    if (e == hipSuccess && want_q) e = fork_T(p);
     if (e == hipSuccess && p->L.levels > 0)
         e = run_phase(p, TSQR_PHASE_TREE, [&] { return tsqr::launch_tree(p->L, p->ws, want_q, p->stream); });
     if (e == hipSuccess)
         e = run_phase(p, TSQR_PHASE_ROOT, [&] { return tsqr::launch_root(p->L, p->ws, R, ldr, p->stream); });
+    if (e == hipSuccess && want_q) e = join_T(p);
     if (e != hipSuccess) return hip_status(e);
     p->state = want_q ? 1 : 2;
     return 0;
@@ -465,6 +509,7 @@ tsqr_status tsqr_plan_destroy(tsqr_plan p)
     hipError_t e = hipSuccess;
     if (p->ws) {
         e = hipStreamSynchronize(p->stream);
+        release_streams(p);
         hipError_t e2 = hipFree(p->ws);
         if (e == hipSuccess) e = e2;
     }
