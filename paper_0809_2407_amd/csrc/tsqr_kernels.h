@@ -817,10 +817,10 @@ __device__ __forceinline__ void store_tile(const E (&a)[RL][NP / LC], E* tb, int
 // running triangle R and the Gram entries of T stay FP64.  V goes to a
 // workspace of whole tiles (rows past m and columns past n are zeros) and T is
 // rounded to FP32.
-// DEFER_T: each tile's T slot receives tau and the Gram entries (gram_out) and
-// k_build_T forms T afterwards, so the leaf's LDS holds no Gram area; else T
-// is formed here.
-template <int NP, bool WANT_Q, typename E, bool DEFER_T = false>
+// With Q, each tile's T slot receives tau and the Gram entries (gram_out) and
+// the T kernel (k_build_T, k_build_T_batch) forms T afterwards, so the leaf's
+// LDS holds only a chunk buffer for the Gram.
+template <int NP, bool WANT_Q, typename E>
 __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, int64_t ldv, int64_t m, int n,
                                            int64_t P, int64_t leaf_rows, int64_t f, E* __restrict__ Ttile,
                                            double* __restrict__ Rleaf, int64_t leaf, double* wsm, int lane)
@@ -830,8 +830,7 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
     constexpr int LC = leaf_col_groups<E>(NP), LR = 64 / LC, MT = tile_rows_e<E>(NP), RL = MT / LR, KC = NP / LC;
     constexpr int NT = packed_size(NP);
     constexpr int CH = leaf_gram_chunk<E>(NP, MT);
-    constexpr int GA = (!WANT_Q && !BLK) ? 0 : DEFER_T ? (CH * (NP + 1) + 1) / 2 * 2 : gram_area(NP);
-    static_assert(!BLK || DEFER_T, "the blocked leaf keeps no Gram area for an in-kernel T");
+    constexpr int GA = (!WANT_Q && !BLK) ? 0 : (CH * (NP + 1) + 1) / 2 * 2;
     const int cg = lane / LR, rg = lane % LR;
     double* Rs = wsm;
     double* Gs = Rs + r_area(NP);
@@ -867,12 +866,7 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
             scale_tile<NP, RL, LC, true, E>(a, sc, lane);
             // the mixed workspace takes whole tiles (zero rows and columns included)
             store_tile<NP, RL, LC, E>(a, V + row0, ldv, lane_off_v, MIXED ? MT : valid, MIXED ? NP : n, rg, cg);
-            if (DEFER_T) {
-                gram_out<NP, RL, LC, true, CH, E>(a, Gs, taus, Ttile + (leaf * f) * NT, lane);
-            } else {
-                gram_mfma<NP, RL, LC, true, E>(a, Gs, Gs, lane);
-                make_T<NP, E>(Gs, taus, taus + NP, Ttile + (leaf * f) * NT, lane);
-            }
+            gram_out<NP, RL, LC, true, CH, E>(a, Gs, taus, Ttile + (leaf * f) * NT, lane);
         }
     }
     for (int64_t t = 1; t < ntl; ++t) {
@@ -884,12 +878,7 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
         if (WANT_Q) {
             scale_tile<NP, RL, LC, false, E>(a, sc, lane);
             store_tile<NP, RL, LC, E>(a, V + t0, ldv, lane_off_v, MIXED ? MT : valid, MIXED ? NP : n, rg, cg);
-            if (DEFER_T) {
-                gram_out<NP, RL, LC, false, CH, E>(a, Gs, taus, Ttile + (leaf * f + t) * NT, lane);
-            } else {
-                gram_mfma<NP, RL, LC, false, E>(a, Gs, Gs, lane);
-                make_T<NP, E>(Gs, taus, taus + NP, Ttile + (leaf * f + t) * NT, lane);
-            }
+            gram_out<NP, RL, LC, false, CH, E>(a, Gs, taus, Ttile + (leaf * f + t) * NT, lane);
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -910,8 +899,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     const int wave = wave_index(), lane = threadIdx.x & 63;
     const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (leaf >= P) return;
-    leaf_chain<NP, WANT_Q, E, true>(A, lda, V, ldv, m, n, P, leaf_rows, f, Ttile, Rleaf, leaf, smem + wave * WS,
-                                    lane);
+    leaf_chain<NP, WANT_Q, E>(A, lda, V, ldv, m, n, P, leaf_rows, f, Ttile, Rleaf, leaf, smem + wave * WS, lane);
 }
 
 // T of every leaf tile (slots 0 .. ntiles-1, one wavefront each) from the tau
@@ -2167,8 +2155,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         const BatchProblem& B = probs[p];
         const BatchArgs X = args[p];
         double* w = ws + B.ws_off;
-        leaf_chain<NP, WANT_Q, double, true>(X.A, X.lda, X.A, X.lda, B.m, B.n, B.P, B.leaf_rows, B.f,
-                                             w + B.off_T, w + B.off_R[0], leaf, smem + wave * WS, lane);
+        leaf_chain<NP, WANT_Q, double>(X.A, X.lda, X.A, X.lda, B.m, B.n, B.P, B.leaf_rows, B.f, w + B.off_T,
+                                       w + B.off_R[0], leaf, smem + wave * WS, lane);
         __builtin_amdgcn_wave_barrier();  // the next item rewrites this wave's LDS
     }
 }
