@@ -259,14 +259,16 @@ tsqr_status tsqr_tune_cache_store(const char* cache_path, int64_t m, int64_t n, 
  * (problem, tree node) items, one launch per phase and tree level, and the
  * whole sequence is captured once into a HIP graph that each call replays
  * (one small pointer upload and one graph launch on the plan's stream, no
- * host synchronisation).  Batched plans are FP64 only (MIXED returns 3); opts
- * apply to every problem (tile_rows must be 0). */
+ * host synchronisation).  MIXED batched plans hold one single-problem MIXED
+ * plan per problem and run them in turn on the plan's stream (each with its own
+ * FP32 workspaces and second pass; no persistent launch), with the results of
+ * those plans.  opts apply to every problem (tile_rows must be 0). */
 typedef struct tsqr_batched_plan_s* tsqr_batched_plan;
 
 /* count problems with sizes m[i] x n[i] (host arrays).  Errors: -1 p NULL,
  * -2 count < 1, -3 m NULL or some m[i] < n[i] or m[i] < 1 or n[i] < 1, -4 n
- * NULL, -5 bad precision, -6 bad option field; 3 MIXED, n[i] > 64 or a tree too
- * deep; 2 out of memory. */
+ * NULL, -5 bad precision, -6 bad option field; 3 n[i] > 64 or a tree too deep;
+ * 2 out of memory. */
 tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* p, int count, const int64_t* m, const int64_t* n,
                                      tsqr_precision prec, const tsqr_opts* opts, void* hip_stream);
 

@@ -44,6 +44,9 @@ struct tsqr_batched_plan_s {
     hipEvent_t ev_f = nullptr, ev_q = nullptr;  // the staging copies have been consumed
     hipGraphExec_t g_factor = nullptr, g_form_q = nullptr;
     int state = 0;  // 0: nothing factored, 1: factored with reflectors, 2: R only
+    // MIXED: one single-problem plan per problem, run in turn on the stream
+    // (no persistent launch: the FP32 workspaces and the second pass are per plan)
+    std::vector<tsqr_plan> singles;
 };
 
 namespace {
@@ -57,6 +60,8 @@ tsqr_status hstatus(hipError_t e)
 
 void release(tsqr_batched_plan_s* p)
 {
+    for (tsqr_plan s : p->singles)
+        if (s) tsqr_plan_destroy(s);
     if (p->g_factor) hipGraphExecDestroy(p->g_factor);
     if (p->g_form_q) hipGraphExecDestroy(p->g_form_q);
     if (p->ev_f) hipEventDestroy(p->ev_f);
@@ -127,8 +132,6 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
         if (n[i] < 1 || m[i] < 1 || m[i] < n[i]) return -3;
         if (n[i] > tsqr::kMaxN) return 3;
     }
-    if (prec == TSQR_MIXED) return 3;  // batched plans are FP64
-
     tsqr_batched_plan_s* p = new (std::nothrow) tsqr_batched_plan_s();
     if (!p) return 2;
     p->count = count;
@@ -136,6 +139,23 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
     p->want_q = o.want_q;
     p->waves = o.waves;
     p->stream = (hipStream_t)hip_stream;
+    if (prec == TSQR_MIXED) {
+        p->L.resize(count);  // only m and n, for the argument checks
+        for (int i = 0; i < count; ++i) {
+            p->L[i].m = m[i];
+            p->L[i].n = n[i];
+        }
+        p->singles.assign(count, nullptr);
+        for (int i = 0; i < count; ++i) {
+            const tsqr_status st = tsqr_plan_create(&p->singles[i], m[i], n[i], TSQR_MIXED, opts, hip_stream);
+            if (st != 0) {
+                release(p);
+                return st > 0 ? st : 3;
+            }
+        }
+        *out = p;
+        return 0;
+    }
     p->L.resize(count);
     std::vector<tsqr::BatchProblem> bp(count);
     int64_t off = 0;
@@ -268,6 +288,14 @@ tsqr_status tsqr_batched_factor(tsqr_batched_plan p, double* const* A, const int
         if (ldr[i] < p->L[i].n) return -5;
     }
     p->state = 0;
+    if (p->prec == TSQR_MIXED) {
+        for (int i = 0; i < p->count; ++i) {
+            const tsqr_status st = tsqr_factor(p->singles[i], A[i], lda[i], R[i], ldr[i]);
+            if (st != 0) return st > 0 ? st : 1;
+        }
+        p->state = p->want_q ? 1 : 2;
+        return 0;
+    }
     hipError_t e = stage_args(p, p->h_args_f, p->d_args_f, p->ev_f, A, lda, R, ldr);
     if (e == hipSuccess && !p->g_factor) {
         e = capture_graph(p->capture, &p->g_factor, [&](hipStream_t s) {
@@ -301,6 +329,13 @@ tsqr_status tsqr_batched_form_q(tsqr_batched_plan p, double* const* A, const int
         if (Q[i] == A[i] && ldq[i] != lda[i]) return -5;
     }
     if (p->state != 1) return 4;
+    if (p->prec == TSQR_MIXED) {
+        for (int i = 0; i < p->count; ++i) {
+            const tsqr_status st = tsqr_form_q(p->singles[i], A[i], lda[i], Q[i], ldq[i]);
+            if (st != 0) return st > 0 ? st : 1;
+        }
+        return 0;
+    }
     hipError_t e = stage_args(p, p->h_args_q, p->d_args_q, p->ev_q, A, lda, Q, ldq);
     if (e == hipSuccess && !p->g_form_q) {
         e = capture_graph(p->capture, &p->g_form_q, [&](hipStream_t s) {
@@ -321,6 +356,7 @@ tsqr_status tsqr_batched_problem_info(tsqr_batched_plan p, int index, tsqr_info*
     if (!p) return -1;
     if (index < 0 || index >= p->count) return -2;
     if (!out) return -3;
+    if (p->prec == TSQR_MIXED) return tsqr_plan_info(p->singles[index], out);
     const tsqr::Layout& L = p->L[index];
     std::memset(out, 0, sizeof(*out));
     out->m = L.m;

@@ -122,7 +122,6 @@ def test_batched_argument_errors_without_device():
     assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, ms, ns, 7, None, None) == -5
     assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, I64(100, 10), ns, 0, None, None) == -3
     assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, ms, I64(8, 65), 0, None, None) == 3
-    assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, ms, ns, 1, None, None) == 3
     assert lib.tsqr_batched_factor(None, None, None, None, None) == -1
     assert lib.tsqr_batched_plan_destroy(None) == -1
 

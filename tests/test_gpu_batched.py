@@ -108,7 +108,34 @@ def test_batched_r_only_and_errors():
         with pytest.raises(TsqrError) as e:
             bp.form_q(As)
         assert e.value.status == 4
-    with pytest.raises(TsqrError) as e:
-        T.BatchedPlan([100], [8], precision="mixed")
-    assert e.value.status == 3
     torch.cuda.synchronize()
+
+
+def test_batched_mixed_equals_single_mixed_plans():
+    """MIXED batched plans give each problem the results of a single MIXED plan,
+    within the mixed bounds against the FP64 oracle."""
+    torch = need_gpu()
+    from paper_0809_2407_amd import tsqr as T
+
+    shapes = [(30000, 64), (1500, 8), (4100, 33), (20000, 32), (777, 3), (9000, 17)]
+    mats = [synth.gaussian(m, n, seed=950 + i) for i, (m, n) in enumerate(shapes)]
+    announce(f"batched mixed {len(mats)} problems")
+    with T.BatchedPlan([m for m, _ in shapes], [n for _, n in shapes], precision="mixed") as bp:
+        As = [T.to_colmajor(torch.from_numpy(A)) for A in mats]
+        Rs = bp.factor(As)
+        Qs = bp.form_q(As, [T.colmajor(m, n) for m, n in shapes])
+        torch.cuda.synchronize()
+        assert bp.problem_info(0)["precision"] == 1
+        for i, A in enumerate(mats):
+            m, n = A.shape
+            announce(f"batched mixed problem {i} {A.shape}")
+            Ad = T.to_colmajor(torch.from_numpy(A))
+            with T.Plan(m, n, precision="mixed") as p:
+                R1 = p.factor(Ad)
+                Q1 = p.form_q(Ad, T.colmajor(m, n))
+                torch.cuda.synchronize()
+            R, Q = Rs[i].cpu().numpy(), Qs[i].cpu().numpy()
+            assert np.array_equal(R, R1.cpu().numpy()) and np.array_equal(Q, Q1.cpu().numpy())
+            assert backward_error(A, Q, R) <= 1e-6
+            assert orthogonality(Q) <= 1e-13
+            assert rel_diff(R, oracle.qr_reference(A, want_q=False)) <= 1e-5
