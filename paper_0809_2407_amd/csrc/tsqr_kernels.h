@@ -7,7 +7,9 @@
 // The leaf R factors are then combined on a binary tree, one launch per level,
 // one wavefront per node (the parallel TSQR of Alg. 1, with the stacked pair
 // [R_a; R_b] factored by the triangle-aware QR of Sec. 3.1).  The explicit Q is
-// the tree replayed top-down (applying Q is a broadcast, Sec. 4.1).
+// the tree replayed top-down (applying Q is a broadcast, Sec. 4.1).  Each
+// tile's compact-WY T is formed by its own kernel (k_build_T) from the tau and
+// Gram entries the leaf kernel leaves in the tile's T slot.
 //
 // Register layout of a tile ("L layout").  A tile has 16*RL rows and NP
 // columns (NP = n rounded up to a multiple of 4; padded columns are zero and

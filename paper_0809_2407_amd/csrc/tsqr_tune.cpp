@@ -5,8 +5,8 @@
 // Tunable here: the leaf length (tiles per flat chain, hence the tree:
 // binary, hybrid or one flat chain) and the wavefronts per workgroup of the
 // leaf and Q kernels.  The tile height is fixed by the width (it sizes the
-// register-resident tile), and the leaf update is unblocked, so there is no
-// panel width to choose.  Accuracy guards: flat chains are capped at
+// register-resident tile), and the panel width of the blocked leaf is one
+// matrix-core block (16 columns), so neither is searched.  Accuracy guards: flat chains are capped at
 // kMaxChainTiles tiles (a long flat chain accumulates rounding along the chain
 // -- the flat tree is the least accurate shape), and for the mixed precision
 // chains of FP32 tiles are capped at kMaxChainF32.
