@@ -40,6 +40,10 @@ WORKLOADS = {
     # then Q^T applied to 32 iid N(0,1) right-hand sides
     "tsqr_fp64_rq_qtb_krylov_m4194304_n17_k32": dict(m=2048 * 2048, n=17, decades=None, mode="rq",
                                                      krylov=(2048, 16), rhs=32),
+    # the same basis, R + Q only: the FP64 path and the mixed path with its second pass
+    "tsqr_fp64_rq_krylov_m4194304_n17": dict(m=2048 * 2048, n=17, decades=None, mode="rq", krylov=(2048, 16)),
+    "tsqr_mixed_rq_krylov_m4194304_n17": dict(m=2048 * 2048, n=17, decades=None, mode="rq", krylov=(2048, 16),
+                                              precision="mixed"),
 }
 DEFAULT = "tsqr_fp64_rq_m16777216_n32_kappa1e12"
 
