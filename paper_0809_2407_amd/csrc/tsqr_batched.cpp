@@ -44,9 +44,6 @@ struct tsqr_batched_plan_s {
     hipEvent_t ev_f = nullptr, ev_q = nullptr;  // the staging copies have been consumed
     hipGraphExec_t g_factor = nullptr, g_form_q = nullptr;
     int state = 0;  // 0: nothing factored, 1: factored with reflectors, 2: R only
-    // MIXED: one single-problem plan per problem, run in turn on the stream
-    // (no persistent launch: the FP32 workspaces and the second pass are per plan)
-    std::vector<tsqr_plan> singles;
 };
 
 namespace {
@@ -60,8 +57,6 @@ tsqr_status hstatus(hipError_t e)
 
 void release(tsqr_batched_plan_s* p)
 {
-    for (tsqr_plan s : p->singles)
-        if (s) tsqr_plan_destroy(s);
     if (p->g_factor) hipGraphExecDestroy(p->g_factor);
     if (p->g_form_q) hipGraphExecDestroy(p->g_form_q);
     if (p->ev_f) hipEventDestroy(p->ev_f);
@@ -139,23 +134,7 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
     p->want_q = o.want_q;
     p->waves = o.waves;
     p->stream = (hipStream_t)hip_stream;
-    if (prec == TSQR_MIXED) {
-        p->L.resize(count);  // only m and n, for the argument checks
-        for (int i = 0; i < count; ++i) {
-            p->L[i].m = m[i];
-            p->L[i].n = n[i];
-        }
-        p->singles.assign(count, nullptr);
-        for (int i = 0; i < count; ++i) {
-            const tsqr_status st = tsqr_plan_create(&p->singles[i], m[i], n[i], TSQR_MIXED, opts, hip_stream);
-            if (st != 0) {
-                release(p);
-                return st > 0 ? st : 3;
-            }
-        }
-        *out = p;
-        return 0;
-    }
+    const bool mixed = prec == TSQR_MIXED;
     p->L.resize(count);
     std::vector<tsqr::BatchProblem> bp(count);
     int64_t off = 0;
@@ -169,7 +148,7 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
             oi.leaf_rows = tuned.leaf_rows;
             oi.flat_len = tuned.flat_len;
         }
-        if (!tsqr::make_layout(L, m[i], n[i], oi.leaf_rows, oi.flat_len, oi.tree, oi.waves, false, o.want_q != 0) ||
+        if (!tsqr::make_layout(L, m[i], n[i], oi.leaf_rows, oi.flat_len, oi.tree, oi.waves, mixed, o.want_q != 0) ||
             L.levels >= tsqr::kBatchLevels) {
             delete p;
             return 3;
@@ -191,6 +170,18 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
             b.off_TN[l] = L.off_TN[l];
             b.count[l] = L.count[l];
         }
+        b.ld32 = L.ld32;
+        b.off_V32 = L.off_V32;
+        b.off_T32 = L.off_T32;
+        b.off_Q1 = L.off_Q1;
+        b.off_Gp = L.off_Gp;
+        b.off_Gq = L.off_Gq;
+        b.off_G = L.off_G;
+        b.off_R1 = L.off_R1;
+        b.off_R2inv = L.off_R2inv;
+        b.off_info = L.off_info;
+        b.gram_waves = L.gram_waves;
+        b.gram_rows = L.gram_rows;
         off += L.total;
     }
     p->ws_doubles = off;
@@ -203,7 +194,7 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
     std::sort(widths.begin(), widths.end());
     std::vector<std::vector<int64_t>> lists;  // host copies, concatenated below
     struct ClassLists {
-        size_t leaf, root, level[tsqr::kBatchLevels];
+        size_t leaf, root, level[tsqr::kBatchLevels], gram, gsum, rq;
     };
     std::vector<ClassLists> where;
     for (int np : widths) {
@@ -235,6 +226,26 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
             w.level[l] = lists.size();
             lists.push_back(lv);
         }
+        // mixed with Q: the second pass's items
+        std::vector<int64_t> gram, gsum, rq;
+        if (mixed && o.want_q) {
+            for (int i : probs) {
+                const tsqr::Layout& Li = p->L[i];
+                for (int64_t g = 0; g < Li.gram_waves; ++g) gram.push_back(tsqr::batch_item(i, g));
+                for (int64_t g = 0; g < (Li.gram_waves + 63) / 64; ++g) gsum.push_back(tsqr::batch_item(i, g));
+                const int64_t nblocks = (Li.m + 15) / 16;
+                for (int64_t c = 0; c < (nblocks + 63) / 64; ++c) rq.push_back(tsqr::batch_item(i, c));
+            }
+        }
+        C.n_gram = (int64_t)gram.size();
+        C.n_gsum = (int64_t)gsum.size();
+        C.n_rq = (int64_t)rq.size();
+        w.gram = lists.size();
+        lists.push_back(gram);
+        w.gsum = lists.size();
+        lists.push_back(gsum);
+        w.rq = lists.size();
+        lists.push_back(rq);
         p->classes.push_back(C);
         where.push_back(w);
     }
@@ -268,6 +279,18 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
         C.leaf_items = p->d_items + start[where[c].leaf];
         C.root_items = p->d_items + start[where[c].root];
         for (int l = 1; l <= C.max_levels; ++l) C.level_items[l] = p->d_items + start[where[c].level[l]];
+        C.gram_items = p->d_items + start[where[c].gram];
+        C.gsum_items = p->d_items + start[where[c].gsum];
+        C.rq_items = p->d_items + start[where[c].rq];
+    }
+    if (mixed) {
+        // the FP32 workspaces are read in whole tiles and 16-column blocks: what
+        // the kernels never write (rows past the last tile, columns past np) stays zero
+        e = hipMemset(p->ws, 0, (size_t)p->ws_doubles * sizeof(double));
+        if (e != hipSuccess) {
+            release(p);
+            return hstatus(e);
+        }
     }
     *out = p;
     return 0;
@@ -288,20 +311,15 @@ tsqr_status tsqr_batched_factor(tsqr_batched_plan p, double* const* A, const int
         if (ldr[i] < p->L[i].n) return -5;
     }
     p->state = 0;
-    if (p->prec == TSQR_MIXED) {
-        for (int i = 0; i < p->count; ++i) {
-            const tsqr_status st = tsqr_factor(p->singles[i], A[i], lda[i], R[i], ldr[i]);
-            if (st != 0) return st > 0 ? st : 1;
-        }
-        p->state = p->want_q ? 1 : 2;
-        return 0;
-    }
     hipError_t e = stage_args(p, p->h_args_f, p->d_args_f, p->ev_f, A, lda, R, ldr);
     if (e == hipSuccess && !p->g_factor) {
         e = capture_graph(p->capture, &p->g_factor, [&](hipStream_t s) {
             for (const tsqr::BatchClass& C : p->classes) {
                 const int waves = p->waves > 0 ? p->waves : (p->want_q ? 4 : 1);
-                hipError_t el = tsqr::launch_batch_factor(C, p->d_probs, p->d_args_f, p->ws, p->want_q != 0, waves, s);
+                hipError_t el =
+                    p->prec == TSQR_MIXED
+                        ? tsqr::launch_batch_factor_mixed(C, p->d_probs, p->d_args_f, p->ws, p->want_q != 0, waves, s)
+                        : tsqr::launch_batch_factor(C, p->d_probs, p->d_args_f, p->ws, p->want_q != 0, waves, s);
                 if (el != hipSuccess) return el;
             }
             return hipSuccess;
@@ -329,19 +347,14 @@ tsqr_status tsqr_batched_form_q(tsqr_batched_plan p, double* const* A, const int
         if (Q[i] == A[i] && ldq[i] != lda[i]) return -5;
     }
     if (p->state != 1) return 4;
-    if (p->prec == TSQR_MIXED) {
-        for (int i = 0; i < p->count; ++i) {
-            const tsqr_status st = tsqr_form_q(p->singles[i], A[i], lda[i], Q[i], ldq[i]);
-            if (st != 0) return st > 0 ? st : 1;
-        }
-        return 0;
-    }
     hipError_t e = stage_args(p, p->h_args_q, p->d_args_q, p->ev_q, A, lda, Q, ldq);
     if (e == hipSuccess && !p->g_form_q) {
         e = capture_graph(p->capture, &p->g_form_q, [&](hipStream_t s) {
             for (const tsqr::BatchClass& C : p->classes) {
                 const int waves = p->waves > 0 ? p->waves : (p->want_q ? 4 : 1);
-                hipError_t el = tsqr::launch_batch_form_q(C, p->d_probs, p->d_args_q, p->ws, waves, s);
+                hipError_t el = p->prec == TSQR_MIXED
+                                    ? tsqr::launch_batch_form_q_mixed(C, p->d_probs, p->d_args_q, p->ws, s)
+                                    : tsqr::launch_batch_form_q(C, p->d_probs, p->d_args_q, p->ws, waves, s);
                 if (el != hipSuccess) return el;
             }
             return hipSuccess;
@@ -356,7 +369,6 @@ tsqr_status tsqr_batched_problem_info(tsqr_batched_plan p, int index, tsqr_info*
     if (!p) return -1;
     if (index < 0 || index >= p->count) return -2;
     if (!out) return -3;
-    if (p->prec == TSQR_MIXED) return tsqr_plan_info(p->singles[index], out);
     const tsqr::Layout& L = p->L[index];
     std::memset(out, 0, sizeof(*out));
     out->m = L.m;
@@ -371,6 +383,17 @@ tsqr_status tsqr_batched_problem_info(tsqr_batched_plan p, int index, tsqr_info*
     out->waves = L.waves;
     out->precision = p->prec;
     out->workspace_bytes = L.total * (int64_t)sizeof(double);
+    if (p->prec == TSQR_MIXED && p->want_q && p->state == 1) {
+        // the second pass's check (synchronises the plan's stream)
+        double info[2] = {0.0, 0.0};
+        hipError_t e = hipStreamSynchronize(p->stream);
+        int64_t off = 0;
+        for (int i = 0; i < index; ++i) off += p->L[i].total;
+        if (e == hipSuccess) e = hipMemcpy(info, p->ws + off + L.off_info, sizeof(info), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hstatus(e);
+        out->orth_estimate = info[0];
+        out->reorth_applied = info[1] != 0.0;
+    }
     return 0;
 }
 

@@ -148,4 +148,20 @@ hipError_t launch_batch_form_q(const BatchClass& C, const BatchProblem* probs, c
 #undef CALL
 }
 
+hipError_t launch_batch_factor_mixed(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args,
+                                     double* ws, bool want_q, int waves, hipStream_t s)
+{
+#define CALL(NP) batch_factor_mixed_np<NP>(C, probs, args, ws, want_q, waves, s)
+    TSQR_NP_SWITCH(C.np, CALL)
+#undef CALL
+}
+
+hipError_t launch_batch_form_q_mixed(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args,
+                                     double* ws, hipStream_t s)
+{
+#define CALL(NP) batch_form_q_mixed_np<NP>(C, probs, args, ws, s)
+    TSQR_NP_SWITCH(C.np, CALL)
+#undef CALL
+}
+
 }  // namespace tsqr

@@ -85,6 +85,10 @@ struct BatchProblem {
     int64_t off_R[kBatchLevels] = {0}, off_S[kBatchLevels] = {0};
     int64_t off_Y[kBatchLevels] = {0}, off_TN[kBatchLevels] = {0};
     int64_t count[kBatchLevels] = {0};
+    // mixed precision (offsets in doubles inside the problem's workspace)
+    int64_t ld32 = 0, off_V32 = 0, off_T32 = 0, off_Q1 = 0;
+    int64_t off_Gp = 0, off_Gq = 0, off_G = 0, off_R1 = 0, off_R2inv = 0, off_info = 0;
+    int64_t gram_waves = 0, gram_rows = 0;
 };
 
 // Per-call matrices of one problem: A (factored in place) and the output
@@ -110,6 +114,14 @@ struct BatchClass {
     const int64_t* root_items = nullptr;  // (problem, 0)
     const int64_t* level_items[kBatchLevels] = {nullptr};  // (problem, node) of level l >= 1
     int64_t n_level[kBatchLevels] = {0};
+    // mixed precision: partial Gram matrices (problem, w), their groups of 64
+    // (problem, g), and the 1024-row chunks of Q = Q1 R2^{-1} (problem, c)
+    const int64_t* gram_items = nullptr;
+    int64_t n_gram = 0;
+    const int64_t* gsum_items = nullptr;
+    int64_t n_gsum = 0;
+    const int64_t* rq_items = nullptr;
+    int64_t n_rq = 0;
 };
 
 // Fills the geometry.  Returns false for an unsupported shape.
@@ -144,6 +156,10 @@ hipError_t launch_batch_factor(const BatchClass& C, const BatchProblem* probs, c
                                bool want_q, int waves, hipStream_t s);
 hipError_t launch_batch_form_q(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
                                int waves, hipStream_t s);
+hipError_t launch_batch_factor_mixed(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args,
+                                     double* ws, bool want_q, int waves, hipStream_t s);
+hipError_t launch_batch_form_q_mixed(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args,
+                                     double* ws, hipStream_t s);
 
 // Per-width launchers behind the dispatch (one instantiation per padded width).
 template <int NP>
@@ -179,5 +195,11 @@ hipError_t batch_factor_np(const BatchClass& C, const BatchProblem* probs, const
 template <int NP>
 hipError_t batch_form_q_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
                            int waves, hipStream_t s);
+template <int NP>
+hipError_t batch_factor_mixed_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                                 bool want_q, int waves, hipStream_t s);
+template <int NP>
+hipError_t batch_form_q_mixed_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                                 hipStream_t s);
 
 }  // namespace tsqr

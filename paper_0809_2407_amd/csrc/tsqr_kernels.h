@@ -1535,14 +1535,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 // s of a 64-row group, lane (q, p) supplies row 16 q + s of columns 16 b + p:
 // the 16 rows a lane needs are consecutive, four 16-byte loads per block.
 template <int NP>
-__global__ void __launch_bounds__(256) k_gram_q1(const float* __restrict__ Q1, int64_t ldq1, int64_t rows_total,
-                                                 int64_t rw, int64_t nw, double* __restrict__ Gp)
+__device__ __forceinline__ void gram_q1_wave(const float* __restrict__ Q1, int64_t ldq1, int64_t rows_total,
+                                             int64_t rw, int64_t w, double* __restrict__ Gp, int lane)
 {
     constexpr int NPB = round16(NP), JB = NPB / 16;
-    const int wave = wave_index(), lane = threadIdx.x & 63;
     const int q = lane >> 4, p = lane & 15;
-    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-    if (w >= nw) return;
     dbl4 acc[JB][JB];
 #pragma unroll
     for (int ib = 0; ib < JB; ++ib)
@@ -1580,17 +1577,24 @@ __global__ void __launch_bounds__(256) k_gram_q1(const float* __restrict__ Q1, i
             for (int r = 0; r < 4; ++r) G[(16 * ib + q + 4 * r) + (16 * jb + p) * NPB] = acc[ib][jb][r];
 }
 
+template <int NP>
+__global__ void __launch_bounds__(256) k_gram_q1(const float* __restrict__ Q1, int64_t ldq1, int64_t rows_total,
+                                                 int64_t rw, int64_t nw, double* __restrict__ Gp)
+{
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (w >= nw) return;
+    gram_q1_wave<NP>(Q1, ldq1, rows_total, rw, w, Gp, lane);
+}
+
 // Sum of the partial Gram matrices in two stages, both pairwise, so that every
 // entry carries O(log nw) rounding steps (the check it feeds is 1e-13).
 // Stage 1: block (x, g) adds partials [64 g, 64 g + 64) of 256 entries (eight
 // interleaved accumulators, combined as a tree) into Gq[g].
 template <int NP>
-__global__ void __launch_bounds__(256) k_gram_sum64(const double* __restrict__ Gp, int64_t nw, double* __restrict__ Gq)
+__device__ __forceinline__ double gram_sum64_entry(const double* __restrict__ Gp, int64_t nw, int64_t g, int e)
 {
     constexpr int NPB = round16(NP);
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t g = blockIdx.y;
-    if (e >= NPB * NPB) return;
     double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int64_t w0 = 64 * g, wn = (nw - w0) < 64 ? (nw - w0) : 64;
     if (wn == 64) {
@@ -1599,16 +1603,24 @@ __global__ void __launch_bounds__(256) k_gram_sum64(const double* __restrict__ G
     } else {
         for (int64_t u = 0; u < wn; ++u) a[u % 8] += Gp[(w0 + u) * NPB * NPB + e];
     }
-    Gq[g * NPB * NPB + e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+template <int NP>
+__global__ void __launch_bounds__(256) k_gram_sum64(const double* __restrict__ Gp, int64_t nw, double* __restrict__ Gq)
+{
+    constexpr int NPB = round16(NP);
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = blockIdx.y;
+    if (e >= NPB * NPB) return;
+    Gq[g * NPB * NPB + e] = gram_sum64_entry<NP>(Gp, nw, g, e);
 }
 
 // Stage 2: one thread per entry merges the ng group sums as a binary counter.
 template <int NP>
-__global__ void __launch_bounds__(256) k_gram_sum(const double* __restrict__ Gq, int64_t ng, double* __restrict__ G)
+__device__ __forceinline__ double gram_sum_entry(const double* __restrict__ Gq, int64_t ng, int e)
 {
     constexpr int NPB = round16(NP);
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= NPB * NPB) return;
     double stack[32];
     int64_t cnt = 0;
     for (int64_t g = 0; g < ng; ++g) {
@@ -1621,7 +1633,16 @@ __global__ void __launch_bounds__(256) k_gram_sum(const double* __restrict__ Gq,
     double sum = 0.0;
     for (int lvl = 0; cnt >> lvl; ++lvl)
         if ((cnt >> lvl) & 1) sum = stack[lvl] + sum;
-    G[e] = sum;
+    return sum;
+}
+
+template <int NP>
+__global__ void __launch_bounds__(256) k_gram_sum(const double* __restrict__ Gq, int64_t ng, double* __restrict__ G)
+{
+    constexpr int NPB = round16(NP);
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= NPB * NPB) return;
+    G[e] = gram_sum_entry<NP>(Gq, ng, e);
 }
 
 // One wavefront: the check ||G - I||_F, the flag, the Cholesky factor R2 of
@@ -1630,13 +1651,12 @@ __global__ void __launch_bounds__(256) k_gram_sum(const double* __restrict__ Gq,
 // G and then R2 sit in LDS (column j owned by lane j); column j of R2^{-1} is
 // written by lane j straight to R2inv (NPB x NPB, zero past n).
 template <int NP>
-__global__ void __launch_bounds__(64) k_reorth_factor(const double* __restrict__ G, const double* __restrict__ R1,
-                                                      int n, double bound, double* __restrict__ Xs,
-                                                      double* __restrict__ info, double* __restrict__ R, int64_t ldr)
+__device__ __forceinline__ void reorth_factor_body(const double* __restrict__ G, const double* __restrict__ R1,
+                                                   int n, double bound, double* __restrict__ Xs,
+                                                   double* __restrict__ info, double* __restrict__ R, int64_t ldr,
+                                                   double* Gs, int lane)
 {
     constexpr int NPB = round16(NP), LD = NPB + 1, XLD = NPB;
-    __shared__ double Gs[NPB * LD];
-    const int lane = threadIdx.x;
     // symmetric G from its upper triangle; lane j owns column j
     double dev = 0.0;
     for (int j = lane; j < NPB; j += 64)
@@ -1704,26 +1724,35 @@ __global__ void __launch_bounds__(64) k_reorth_factor(const double* __restrict__
     }
 }
 
+template <int NP>
+__global__ void __launch_bounds__(64) k_reorth_factor(const double* __restrict__ G, const double* __restrict__ R1,
+                                                      int n, double bound, double* __restrict__ Xs,
+                                                      double* __restrict__ info, double* __restrict__ R, int64_t ldr)
+{
+    constexpr int NPB = round16(NP);
+    __shared__ double Gs[NPB * (NPB + 1)];
+    reorth_factor_body<NP>(G, R1, n, bound, Xs, info, R, ldr, Gs, threadIdx.x);
+}
+
 // Q = Q1 R2^{-1} in FP64 (R2^{-1} = I when the check passed), 16 rows at a
 // time: D = R2^{-T} Q1^T on the matrix cores, so that a lane's outputs are 16
 // consecutive rows of one column of Q.  R2^{-1} is upper triangular: output
 // block ob needs k < 16 (ob + 1) only.
+// Row blocks rb = rb0, rb0 + step, ... below rb1 of one problem.
 template <int NP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_reorth_q(const float* __restrict__ Q1, int64_t ldq1, int64_t m, int n,
-                                                  const double* __restrict__ R2inv, double* __restrict__ Q,
-                                                  int64_t ldq, int64_t nblocks)
+__device__ __forceinline__ void reorth_q_blocks(const float* __restrict__ Q1, int64_t ldq1, int64_t m, int n,
+                                                const double* __restrict__ R2inv, double* __restrict__ Q,
+                                                int64_t ldq, int64_t rb0, int64_t rb1, int64_t step, int lane)
 {
     constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
-    const int wave = wave_index(), lane = threadIdx.x & 63;
     const int q = lane >> 4, p = lane & 15;
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     // A operands R2^{-T}(16 ob + p, 4 s + q) = R2^{-1}(4 s + q, 16 ob + p), kept for the whole run
     double ra[JB][KS];
 #pragma unroll
     for (int ob = 0; ob < JB; ++ob)
 #pragma unroll
         for (int s = 0; s < KS; ++s) ra[ob][s] = (s < 4 * (ob + 1)) ? R2inv[(4 * s + q) + (16 * ob + p) * NPB] : 0.0;
-    for (int64_t rb = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; rb < nblocks; rb += nwaves) {
+    for (int64_t rb = rb0; rb < rb1; rb += step) {
         const int64_t row = 16 * rb + p;
         double x[KS];
 #pragma unroll
@@ -1740,6 +1769,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             }
         }
     }
+}
+
+template <int NP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_reorth_q(const float* __restrict__ Q1, int64_t ldq1, int64_t m, int n,
+                                                  const double* __restrict__ R2inv, double* __restrict__ Q,
+                                                  int64_t ldq, int64_t nblocks)
+{
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    reorth_q_blocks<NP>(Q1, ldq1, m, n, R2inv, Q, ldq, (int64_t)blockIdx.x * (blockDim.x >> 6) + wave, nblocks, nwaves,
+                        lane);
 }
 
 // --------------------------------------------------------------------------
@@ -2329,6 +2369,275 @@ hipError_t batch_form_q_np(const BatchClass& C, const BatchProblem* probs, const
     return hipGetLastError();
 }
 
+// ---- batched mixed precision ------------------------------------------------
+// The single-problem mixed path per item: FP32 leaf chains into V32 / T32, T
+// from the FP32 slots, the FP64 tree, R1 into the workspace, the seeds, Q1 in
+// FP32, then the second pass (partial Gram matrices over row groups, the two
+// pairwise sums, the check / Cholesky / R = R2 R1 per problem) and, for the
+// explicit Q, Q = Q1 R2^{-1} over 16-row blocks.
+
+template <int NP, bool WANT_Q>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_leaf_batch_mx(const BatchProblem* __restrict__ probs,
+                                                    const BatchArgs* __restrict__ args, double* ws,
+                                                    const int64_t* __restrict__ items, int64_t nitems)
+{
+    constexpr int WS = leaf_lds_doubles<float>(NP, tile_rows_f32(NP), WANT_Q);
+    extern __shared__ double smem[];
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < nitems; it += nw) {
+        const int64_t item = items[it];
+        const int64_t p = item >> 32, leaf = item & 0xffffffff;
+        const BatchProblem& B = probs[p];
+        const BatchArgs X = args[p];
+        double* w = ws + B.ws_off;
+        leaf_chain<NP, WANT_Q, float>(X.A, X.lda, reinterpret_cast<float*>(w + B.off_V32), B.ld32, B.m, B.n, B.P,
+                                      B.leaf_rows, B.f, reinterpret_cast<float*>(w + B.off_T32), w + B.off_R[0],
+                                      leaf, smem + wave * WS, lane);
+        __builtin_amdgcn_wave_barrier();  // the next item rewrites this wave's LDS
+    }
+}
+
+template <int NP>
+__global__ void __launch_bounds__(256) k_build_T_batch_mx(const BatchProblem* __restrict__ probs, double* ws,
+                                                          const int64_t* __restrict__ items, int64_t nitems)
+{
+    constexpr int MT = tile_rows_f32(NP), NT = packed_size(NP);
+    extern __shared__ double smem[];
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    double* W = smem + wave * BuildTLds<NP>::WS;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < nitems; it += nw) {
+        const int64_t item = items[it];
+        const int64_t p = item >> 32, leaf = item & 0xffffffff;
+        const BatchProblem& B = probs[p];
+        const int64_t row0 = leaf * B.leaf_rows;
+        const int64_t rows = (leaf == B.P - 1) ? (B.m - row0) : B.leaf_rows;
+        const int64_t ntl = (rows + MT - 1) / MT;
+        float* T = reinterpret_cast<float*>(ws + B.ws_off + B.off_T32) + leaf * B.f * NT;
+        for (int64_t t = 0; t < ntl; ++t) build_T_slot<NP, float>(T + t * NT, W, lane);
+    }
+}
+
+// R (sign-normalised) of every problem into its R1 (leading dimension NP) and
+// its root seed.
+template <int NP>
+__global__ void __launch_bounds__(256) k_root_batch_mx(const BatchProblem* __restrict__ probs, double* ws,
+                                                       const int64_t* __restrict__ items, int64_t nitems)
+{
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < nitems; it += nw) {
+        const BatchProblem& B = probs[items[it] >> 32];
+        double* w = ws + B.ws_off;
+        root_body<NP>(w + B.off_R[B.levels], B.n, w + B.off_R1, NP, w + B.off_D, w + B.off_S[B.levels], lane);
+    }
+}
+
+template <int NP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_form_q1_batch(const BatchProblem* __restrict__ probs,
+                                                    double* ws, const int64_t* __restrict__ items, int64_t nitems)
+{
+    constexpr int NPB = round16(NP), JW = fq_col_blocks<float>(NP), SPLIT = NPB / 16 / JW;
+    extern __shared__ double smem_d[];
+    float* smem = reinterpret_cast<float*>(smem_d);
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < nitems * SPLIT; it += nw) {
+        const int64_t item = items[it / SPLIT];
+        const int j0 = (int)(it % SPLIT) * JW;
+        const int64_t p = item >> 32, leaf = item & 0xffffffff;
+        const BatchProblem& B = probs[p];
+        double* w = ws + B.ws_off;
+        const float* V32 = reinterpret_cast<const float*>(w + B.off_V32);
+        form_q_leaf<NP, true, float>(V32, B.ld32, B.m, B.n, B.P, B.leaf_rows, B.f,
+                                     reinterpret_cast<const float*>(w + B.off_T32), w + B.off_S[0],
+                                     reinterpret_cast<float*>(w + B.off_Q1), B.ld32, leaf, j0,
+                                     smem + wave * NPB * 16 * JW, lane);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// items: (problem, partial Gram index w)
+template <int NP>
+__global__ void __launch_bounds__(256) k_gram_q1_batch(const BatchProblem* __restrict__ probs, double* ws,
+                                                       const int64_t* __restrict__ items, int64_t nitems)
+{
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < nitems; it += nw) {
+        const int64_t item = items[it];
+        const BatchProblem& B = probs[item >> 32];
+        double* w = ws + B.ws_off;
+        gram_q1_wave<NP>(reinterpret_cast<const float*>(w + B.off_Q1), B.ld32, B.ld32, B.gram_rows,
+                         item & 0xffffffff, w + B.off_Gp, lane);
+    }
+}
+
+// items: (problem, group g of 64 partials); one workgroup of 256 per item
+template <int NP>
+__global__ void __launch_bounds__(256) k_gram_sum64_batch(const BatchProblem* __restrict__ probs, double* ws,
+                                                          const int64_t* __restrict__ items, int64_t nitems)
+{
+    constexpr int NPB = round16(NP);
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int64_t item = items[it];
+        const BatchProblem& B = probs[item >> 32];
+        double* w = ws + B.ws_off;
+        const int64_t g = item & 0xffffffff;
+        for (int e = threadIdx.x; e < NPB * NPB; e += blockDim.x)
+            w[B.off_Gq + g * NPB * NPB + e] = gram_sum64_entry<NP>(w + B.off_Gp, B.gram_waves, g, e);
+    }
+}
+
+// items: (problem, 0); one workgroup of 256 per item
+template <int NP>
+__global__ void __launch_bounds__(256) k_gram_sum_batch(const BatchProblem* __restrict__ probs, double* ws,
+                                                        const int64_t* __restrict__ items, int64_t nitems)
+{
+    constexpr int NPB = round16(NP);
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BatchProblem& B = probs[items[it] >> 32];
+        double* w = ws + B.ws_off;
+        const int64_t ng = (B.gram_waves + 63) / 64;
+        for (int e = threadIdx.x; e < NPB * NPB; e += blockDim.x)
+            w[B.off_G + e] = gram_sum_entry<NP>(w + B.off_Gq, ng, e);
+    }
+}
+
+// items: (problem, 0); one workgroup of one wavefront per item; R to the caller
+template <int NP>
+__global__ void __launch_bounds__(64) k_reorth_factor_batch(const BatchProblem* __restrict__ probs,
+                                                            const BatchArgs* __restrict__ args, double* ws,
+                                                            const int64_t* __restrict__ items, int64_t nitems,
+                                                            double bound)
+{
+    constexpr int NPB = round16(NP);
+    __shared__ double Gs[NPB * (NPB + 1)];
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int64_t p = items[it] >> 32;
+        const BatchProblem& B = probs[p];
+        const BatchArgs X = args[p];
+        double* w = ws + B.ws_off;
+        reorth_factor_body<NP>(w + B.off_G, w + B.off_R1, B.n, bound, w + B.off_R2inv, w + B.off_info, X.X, X.ldx,
+                               Gs, threadIdx.x);
+        __syncthreads();  // the next item rewrites Gs
+    }
+}
+
+// items: (problem, chunk c): 16-row blocks [64 c, 64 c + 64) of the problem
+template <int NP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_reorth_q_batch(const BatchProblem* __restrict__ probs,
+                                                    const BatchArgs* __restrict__ args, double* ws,
+                                                    const int64_t* __restrict__ items, int64_t nitems)
+{
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < nitems; it += nw) {
+        const int64_t item = items[it];
+        const int64_t p = item >> 32, c = item & 0xffffffff;
+        const BatchProblem& B = probs[p];
+        const BatchArgs X = args[p];
+        double* w = ws + B.ws_off;
+        const int64_t nblocks = (B.m + 15) / 16;
+        const int64_t rb1 = 64 * c + 64 < nblocks ? 64 * c + 64 : nblocks;
+        reorth_q_blocks<NP>(reinterpret_cast<const float*>(w + B.off_Q1), B.ld32, B.m, B.n, w + B.off_R2inv, X.X,
+                            X.ldx, 64 * c, rb1, 1, lane);
+    }
+}
+
+template <int NP>
+hipError_t batch_factor_mixed_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                                 bool want_q, int waves, hipStream_t s)
+{
+    hipError_t e;
+    {
+        const size_t lds = (size_t)waves * leaf_lds_doubles<float>(NP, tile_rows_f32(NP), want_q) * sizeof(double);
+        const dim3 grid(batch_grid(C.n_leaf, waves)), block(64 * waves);
+        if (want_q) {
+            allow_lds(k_leaf_batch_mx<NP, true>, lds);
+            hipLaunchKernelGGL((k_leaf_batch_mx<NP, true>), grid, block, lds, s, probs, args, ws, C.leaf_items,
+                               C.n_leaf);
+        } else {
+            allow_lds(k_leaf_batch_mx<NP, false>, lds);
+            hipLaunchKernelGGL((k_leaf_batch_mx<NP, false>), grid, block, lds, s, probs, args, ws, C.leaf_items,
+                               C.n_leaf);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (want_q) {
+            const size_t blds = (size_t)waves * BuildTLds<NP>::WS * sizeof(double);
+            allow_lds(k_build_T_batch_mx<NP>, blds);
+            hipLaunchKernelGGL((k_build_T_batch_mx<NP>), grid, block, blds, s, probs, ws, C.leaf_items, C.n_leaf);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    const int tw = NP <= 32 ? 4 : 2;
+    const size_t tlds = (size_t)tw * factor_lds_doubles(NP, round16(NP), want_q) * sizeof(double);
+    for (int l = 1; l <= C.max_levels; ++l) {
+        const dim3 grid(batch_grid(C.n_level[l], tw)), block(64 * tw);
+        if (want_q) {
+            allow_lds(k_tree_batch<NP, true>, tlds);
+            hipLaunchKernelGGL((k_tree_batch<NP, true>), grid, block, tlds, s, probs, ws, C.level_items[l], C.n_level[l], l);
+        } else {
+            allow_lds(k_tree_batch<NP, false>, tlds);
+            hipLaunchKernelGGL((k_tree_batch<NP, false>), grid, block, tlds, s, probs, ws, C.level_items[l], C.n_level[l], l);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (!want_q) {
+        // R only: the first pass is the result
+        hipLaunchKernelGGL((k_root_batch<NP>), dim3(batch_grid(C.nprob, 4)), dim3(256), 0, s, probs, args, ws,
+                           C.root_items, C.nprob, 0);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_root_batch_mx<NP>), dim3(batch_grid(C.nprob, 4)), dim3(256), 0, s, probs, ws, C.root_items,
+                       C.nprob);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int l = C.max_levels; l >= 1; --l) {
+        hipLaunchKernelGGL((k_seed_batch<NP>), dim3(batch_grid(C.n_level[l], 4)), dim3(256), 0, s, probs, ws,
+                           C.level_items[l], C.n_level[l], l);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    {
+        constexpr int NPB = round16(NP), JW = fq_col_blocks<float>(NP), SPLIT = NPB / 16 / JW;
+        const size_t lds = (size_t)waves * NPB * 16 * JW * sizeof(float);
+        allow_lds(k_form_q1_batch<NP>, lds);
+        hipLaunchKernelGGL((k_form_q1_batch<NP>), dim3(batch_grid(C.n_leaf * SPLIT, waves)), dim3(64 * waves), lds,
+                           s, probs, ws, C.leaf_items, C.n_leaf);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_gram_q1_batch<NP>), dim3(batch_grid(C.n_gram, 4)), dim3(256), 0, s, probs, ws, C.gram_items,
+                       C.n_gram);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_gram_sum64_batch<NP>), dim3((unsigned)(C.n_gsum < 4096 ? C.n_gsum : 4096)), dim3(256), 0, s,
+                       probs, ws, C.gsum_items, C.n_gsum);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_gram_sum_batch<NP>), dim3((unsigned)(C.nprob < 4096 ? C.nprob : 4096)), dim3(256), 0, s,
+                       probs, ws, C.root_items, C.nprob);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_reorth_factor_batch<NP>), dim3((unsigned)(C.nprob < 4096 ? C.nprob : 4096)), dim3(64), 0,
+                       s, probs, args, ws, C.root_items, C.nprob, kReorthBound);
+    return hipGetLastError();
+}
+
+template <int NP>
+hipError_t batch_form_q_mixed_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL((k_reorth_q_batch<NP>), dim3(batch_grid(C.n_rq, 4)), dim3(256), 0, s, probs, args, ws,
+                       C.rq_items, C.n_rq);
+    return hipGetLastError();
+}
+
 // ---- mixed precision -------------------------------------------------------
 
 // True when the byte offset of element (15, 12) of a 16 x 16 FP32 block with
@@ -2490,6 +2799,18 @@ hipError_t batch_form_q_np(const BatchClass& C, const BatchProblem* probs, const
 {
     return detail::batch_form_q_np<NP>(C, probs, args, ws, waves, s);
 }
+template <int NP>
+hipError_t batch_factor_mixed_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                                 bool want_q, int waves, hipStream_t s)
+{
+    return detail::batch_factor_mixed_np<NP>(C, probs, args, ws, want_q, waves, s);
+}
+template <int NP>
+hipError_t batch_form_q_mixed_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                                 hipStream_t s)
+{
+    return detail::batch_form_q_mixed_np<NP>(C, probs, args, ws, s);
+}
 
 // Every per-width launcher of one padded width (used by the tsqr_np_*.hip units).
 #define TSQR_INSTANTIATE(NP)                                                                                   \
@@ -2511,6 +2832,10 @@ hipError_t batch_form_q_np(const BatchClass& C, const BatchProblem* probs, const
     template hipError_t batch_factor_np<NP>(const BatchClass&, const BatchProblem*, const BatchArgs*, double*,  \
                                             bool, int, hipStream_t);                                          \
     template hipError_t batch_form_q_np<NP>(const BatchClass&, const BatchProblem*, const BatchArgs*, double*,  \
-                                            int, hipStream_t);
+                                            int, hipStream_t);                                                \
+    template hipError_t batch_factor_mixed_np<NP>(const BatchClass&, const BatchProblem*, const BatchArgs*,    \
+                                                  double*, bool, int, hipStream_t);                           \
+    template hipError_t batch_form_q_mixed_np<NP>(const BatchClass&, const BatchProblem*, const BatchArgs*,    \
+                                                  double*, hipStream_t);
 
 }  // namespace tsqr
