@@ -259,10 +259,11 @@ tsqr_status tsqr_tune_cache_store(const char* cache_path, int64_t m, int64_t n, 
  * (problem, tree node) items, one launch per phase and tree level, and the
  * whole sequence is captured once into a HIP graph that each call replays
  * (one small pointer upload and one graph launch on the plan's stream, no
- * host synchronisation).  MIXED batched plans hold one single-problem MIXED
- * plan per problem and run them in turn on the plan's stream (each with its own
- * FP32 workspaces and second pass; no persistent launch), with the results of
- * those plans.  opts apply to every problem (tile_rows must be 0). */
+ * host synchronisation).  MIXED batched plans run the mixed path the same way
+ * (FP32 first pass, FP64 second pass per problem inside the same graphs) with
+ * the results of single MIXED plans; tsqr_batched_problem_info then reports
+ * each problem's check (and synchronises the plan's stream).  opts apply to
+ * every problem (tile_rows must be 0). */
 typedef struct tsqr_batched_plan_s* tsqr_batched_plan;
 
 /* count problems with sizes m[i] x n[i] (host arrays).  Errors: -1 p NULL,
