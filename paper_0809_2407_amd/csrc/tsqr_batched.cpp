@@ -4,7 +4,8 @@
 // Problems are grouped by padded width (one kernel instantiation per width).
 // For each width class the plan holds device work lists -- the (problem,
 // leaf) items of the leaf chains and of the explicit-Q pass, the (problem,
-// node) items of every tree level, one root item per problem -- and the
+// node) items of every tree level, one root item per problem; for mixed
+// precision also the (problem, row group) items of the second pass -- and the
 // persistent batched kernels walk them.  The per-problem geometry and
 // workspace offsets are uploaded once; the matrix pointers of a call go
 // through a pinned staging buffer to a small device table, so the captured
