@@ -91,7 +91,7 @@ typedef struct {
 /* What the plan chose, and (MIXED) what the second pass measured. */
 typedef struct {
     int64_t m, n;
-    int64_t n_padded;        /* n rounded up to the kernels' column granularity */
+    int64_t n_padded;        /* kernel column count: n rounded up to 4; 64 for n = 57..60 */
     int64_t tile_rows;       /* rows per tile */
     int64_t leaf_rows;       /* rows per leaf (the last leaf also takes the remainder) */
     int64_t num_leaves;      /* P */
@@ -199,7 +199,9 @@ tsqr_status tsqr_plan_profile(tsqr_plan p, int enable);
  * Errors: -1 p, -2 out NULL; 1 HIP error. */
 tsqr_status tsqr_plan_timings(tsqr_plan p, tsqr_timings* out);
 
-/* Free the plan and its workspace (synchronises its stream first). */
+/* Free the plan and its workspace (synchronises its stream first).  The plan
+ * is freed whatever the status: a HIP error of earlier work on the stream is
+ * reported, but p must not be used or destroyed again.  Errors: -1 p; 1 HIP. */
 tsqr_status tsqr_plan_destroy(tsqr_plan p);
 
 /* ---- Autotuner --------------------------------------------------------------
@@ -291,7 +293,8 @@ tsqr_status tsqr_batched_form_q(tsqr_batched_plan p, double* const* A, const int
 /* What the plan chose for problem `index`.  Errors: -1 p, -2 index, -3 out. */
 tsqr_status tsqr_batched_problem_info(tsqr_batched_plan p, int index, tsqr_info* out);
 
-/* Free the batched plan (synchronises its stream first). */
+/* Free the batched plan (synchronises its stream first).  Freed whatever the
+ * status, as for tsqr_plan_destroy.  Errors: -1 p; 1 HIP. */
 tsqr_status tsqr_batched_plan_destroy(tsqr_batched_plan p);
 
 /* Static, human-readable text for a status code. */

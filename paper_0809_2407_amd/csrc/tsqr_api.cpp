@@ -25,7 +25,7 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
     L.m = m;
     L.n = n;
     L.mixed = mixed;
-    L.np = (int)((n + 3) / 4 * 4);
+    L.np = padded_width(n);
     L.npb = (int)((n + 15) / 16 * 16);
     L.mt = mixed ? tile_rows_f32(L.np) : tile_rows_for(L.np);
     // automatic waves per workgroup (leaf and Q kernels): 4 with Q, 1 for R only

@@ -26,6 +26,18 @@ __host__ __device__ constexpr int tile_rows_for(int np)
     return (4096 / np / 16 * 16) > (np == 8 ? 384 : 512) ? (np == 8 ? 384 : 512) : (4096 / np / 16 * 16);
 }
 
+// Padded column count of the kernels for n columns: n rounded up to a multiple
+// of 4, except that widths 57-60 run on the 64-column kernels.  At 60 columns
+// the factor layout gives each lane 15 columns, and the compiler leaves the
+// column loops of that instantiation rolled, which puts the whole tile in
+// scratch memory; four more zero columns (tau = 0 reflectors) cost less.
+__host__ __device__ constexpr int padded_width(int64_t n)
+{
+    return (n > 56 && n <= 60) ? 64 : (int)((n + 3) / 4 * 4);
+}
+// Most zero columns padded_width adds at a padded count np.
+__host__ __device__ constexpr int max_padding(int np) { return np == 64 ? 7 : 3; }
+
 // Rows per tile of the mixed-precision leaf kernel, whose tile is held in FP32:
 // twice the FP64 tile in the same registers, at most 1024.
 #ifndef TSQR_F32_TILE_SCALE
@@ -37,7 +49,7 @@ __host__ __device__ constexpr int tile_rows_f32(int np) { return TSQR_F32_TILE_S
 // binary tree over the leaves, plus the offsets of every workspace buffer.
 struct Layout {
     int64_t m = 0, n = 0;
-    int np = 0;          // n rounded up to a multiple of 4 (kernel column granularity)
+    int np = 0;          // padded column count of the kernels (padded_width)
     int npb = 0;         // n rounded up to a multiple of 16 (matrix-core block)
     int64_t mt = 0;      // tile rows
     int waves = 0;       // wavefronts per workgroup of the leaf kernel

@@ -12,7 +12,7 @@
 // Gram entries the leaf kernel leaves in the tile's T slot.
 //
 // Register layout of a tile ("L layout").  A tile has 16*RL rows and NP
-// columns (NP = n rounded up to a multiple of 4; padded columns are zero and
+// columns (NP = padded_width(n); padded columns are zero and
 // stay zero).  Lane l = 16*cg + rg holds rows 16*i + rg (i < RL) and columns
 // 4*k + cg (k < NP/4) in a[i][k].  Consequences:
 //   - a sum over the rows of a column is a sum over the 16 lanes of one DPP row
@@ -1398,9 +1398,15 @@ __device__ __forceinline__ void form_q_leaf(const E* V, int64_t lda, int64_t m, 
         const int cstep = MIXED ? 4 : 1;  // column distance of the lane groups
         const off_t lane_v = (off_t)(lrg + cstep * lcg * lda) * (off_t)sizeof(E);
         const off_t lane_q = (off_t)(lrg + cstep * lcg * ldq) * (off_t)sizeof(E);
-        // FP64, last column group: columns past n read column n - 1 instead (then zeroed)
-        const int cl_last = 4 * (KC - 1) + lcg < n ? lcg : n - 1 - 4 * (KC - 1);
-        const off_t lane_vl = (off_t)(lrg + cl_last * lda) * (off_t)sizeof(E);
+        // FP64: only the last TAIL groups of four columns can reach past n;
+        // there a column past n reads column n - 1 instead (then zeroed)
+        constexpr int TAIL = (max_padding(NP) + 3) / 4;
+        int64_t tail_off[TAIL];
+#pragma unroll
+        for (int j = 0; j < TAIL; ++j) {
+            const int c = 4 * (KX - TAIL + j) + lcg;
+            tail_off[j] = lrg + (int64_t)(c < n ? c : n - 1) * lda;
+        }
         const E* T = Ttile + (leaf * f + t) * NT;
         const int64_t t0 = row0 + t * MT;
         const int64_t valid = MIXED ? MT : ((rows - t * MT) < MT ? (rows - t * MT) : MT);
@@ -1457,11 +1463,14 @@ __device__ __forceinline__ void form_q_leaf(const E* V, int64_t lda, int64_t m, 
 #pragma unroll
                 for (int k = 0; k < KX; ++k) y[k] = ld_at(vb + (int64_t)(16 * (k / 4) + k % 4) * lda, lane_v);
             } else if (full) {
-                // only the last group of four columns can reach past n (NP = n rounded up to 4)
 #pragma unroll
-                for (int k = 0; k < KX - 1; ++k) y[k] = ld_at(vb + (int64_t)(4 * k) * lda, lane_v);
-                const E yl = ld_at(vb + (int64_t)(4 * (KX - 1)) * lda, lane_vl);
-                y[KX - 1] = 4 * (KX - 1) + lcg < n ? yl : E(0);
+                for (int k = 0; k < KX - TAIL; ++k) y[k] = ld_at(vb + (int64_t)(4 * k) * lda, lane_v);
+#pragma unroll
+                for (int j = 0; j < TAIL; ++j) {
+                    const int k = KX - TAIL + j;
+                    const E v = vb[tail_off[j]];
+                    y[k] = 4 * k + lcg < n ? v : E(0);
+                }
             } else {
                 // ragged tile or padded columns: clamp to an element that exists, then zero
                 const int rc = rv ? rl : (int)valid - 1;

@@ -87,10 +87,13 @@ class Plan:
         self._h = h
 
     def close(self) -> None:
+        # the library frees the plan even when it reports an error (say, a
+        # fault of earlier work seen at the final synchronisation): forget the
+        # handle first so that __del__ never destroys it a second time
         h = getattr(self, "_h", None)
+        self._h = None
         if h is not None and h.value:
             check("tsqr_plan_destroy", self._lib.tsqr_plan_destroy(h))
-        self._h = None
 
     def __del__(self):
         try:
@@ -212,10 +215,13 @@ class BatchedPlan:
         return {f: getattr(out, f) for f, _ in TsqrInfo._fields_}
 
     def close(self) -> None:
+        # the library frees the plan even when it reports an error (say, a
+        # fault of earlier work seen at the final synchronisation): forget the
+        # handle first so that __del__ never destroys it a second time
         h = getattr(self, "_h", None)
+        self._h = None
         if h is not None and h.value:
             check("tsqr_batched_plan_destroy", self._lib.tsqr_batched_plan_destroy(h))
-        self._h = None
 
     def __del__(self):
         try:

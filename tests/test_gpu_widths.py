@@ -1,0 +1,72 @@
+"""Every padded column count of the kernels (widths rounded up to a multiple of
+4, widths 57-60 on the 64-column kernels), with widths that are not a multiple
+of 4 so the zero columns past n are exercised in each: the FP64 path against
+the oracle run on the same tree, element by element, and the mixed path
+against the bounds of the method."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import announce, need_gpu, run_tsqr
+from metrics import backward_error, fp64_bound, is_upper, orthogonality, rel_diff
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = [2, 7, 10, 13, 19, 22, 26, 31, 34, 38, 43, 46, 50, 53, 55, 57, 58, 60, 62, 63]
+
+
+@pytest.mark.parametrize("n", WIDTHS)
+def test_fp64_every_kernel_width(n):
+    """A Gaussian matrix (well conditioned, so Q itself is determined to
+    rounding and can be compared element by element)."""
+    need_gpu()
+    A = synth.gaussian(6000 + 3 * n, n, seed=1000 + n)
+    announce(f"fp64 width {n}: {A.shape[0]}x{n} hybrid3")
+    R, Q, _, info = run_tsqr(A, tree="hybrid", flat_len=3)
+    assert info["n_padded"] == (64 if 57 <= n <= 60 else (n + 3) // 4 * 4)
+    assert info["num_leaves"] > 1
+    assert is_upper(R) and np.all(np.diag(R) >= 0)
+    t = oracle.TSQR(A, info["leaf_rows"], info["tile_rows"])
+    Ro, Qo = t.R(), t.form_q()
+    assert np.abs(R - Ro).max() <= 1e-13 * np.linalg.norm(Ro)
+    assert np.abs(Q - Qo).max() <= 1e-13
+    assert backward_error(A, Q, R) <= fp64_bound(n)
+    assert orthogonality(Q) <= fp64_bound(n)
+
+
+@pytest.mark.parametrize("n", [13, 31, 50, 57, 60, 63])
+def test_fp64_ill_conditioned_widths(n):
+    """sigma from 1 to 1e-12: Q's last columns are determined only to about
+    eps * kappa, so the checks are the method's bounds and R against the
+    reference QR."""
+    need_gpu()
+    A, _ = synth.prescribed_sigma(5000 + 7 * n, n, seed=1200 + n, decades=12)
+    announce(f"fp64 ill-conditioned width {n}: {A.shape[0]}x{n}")
+    R, Q, _, _ = run_tsqr(A, tree="hybrid", flat_len=2)
+    assert is_upper(R) and np.all(np.diag(R) >= 0)
+    assert rel_diff(R, oracle.qr_reference(A, want_q=False)) <= 1e-13
+    assert backward_error(A, Q, R) <= fp64_bound(n)
+    assert orthogonality(Q) <= fp64_bound(n)
+
+
+@pytest.mark.parametrize("n", [7, 22, 38, 53, 57, 60, 63])
+def test_mixed_every_kernel_width(n):
+    torch = need_gpu()
+    from paper_0809_2407_amd import tsqr as T
+
+    m = 9000 + 5 * n
+    A, _ = synth.prescribed_sigma(m, n, seed=1100 + n, decades=6)
+    announce(f"mixed width {n}: {m}x{n}")
+    Ad = T.to_colmajor(torch.from_numpy(A))
+    with T.Plan(m, n, precision="mixed") as p:
+        R = p.factor(Ad)
+        Q = p.form_q(None)
+        torch.cuda.synchronize()
+        info = p.info()
+    R, Q = R.cpu().numpy(), Q.cpu().numpy()
+    assert info["reorth_applied"] == 1
+    assert is_upper(R) and np.all(np.diag(R) >= 0)
+    assert backward_error(A, Q, R) <= 1e-6
+    assert orthogonality(Q) <= 1e-13
+    assert rel_diff(R, oracle.qr_reference(A, want_q=False)) <= 1e-5
