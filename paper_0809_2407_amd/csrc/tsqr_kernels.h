@@ -1657,27 +1657,51 @@ __global__ void __launch_bounds__(256) k_gram_sum(const double* __restrict__ Gq,
 // One wavefront: the check ||G - I||_F, the flag, the Cholesky factor R2 of
 // G, R2^{-1}, and R = R2 R1 for the caller (R1 the sign-normalised first-pass
 // R; diag(R2) > 0 keeps diag(R) >= 0).  Below the bound: R2^{-1} = I, R = R1.
-// G and then R2 sit in LDS (column j owned by lane j); column j of R2^{-1} is
-// written by lane j straight to R2inv (NPB x NPB, zero past n).
+// Everything the serial loops touch sits in LDS (reorth_lds_doubles): G and
+// then R2, R2^{-1} and R1, each NPB x (NPB + 1) with column j owned by lane j;
+// the inputs are read and R2^{-1} (NPB x NPB, zero past n) written with
+// coalesced accesses.
+// sum over k in [k0, k1) of a[k * lda] * b[k], four partial sums (the serial
+// loops of the factorisation below are bound by the latency of one chain)
+__device__ __forceinline__ double lds_dot(const double* a, int lda, const double* b, int k0, int k1)
+{
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = k0;
+    for (; k + 3 < k1; k += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[u] = fma(a[(k + u) * lda], b[k + u], s[u]);
+    }
+    for (; k < k1; ++k) s[0] = fma(a[k * lda], b[k], s[0]);
+    return (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+template <int NP>
+__host__ __device__ constexpr int reorth_lds_doubles() { return 3 * round16(NP) * (round16(NP) + 1); }
+
 template <int NP>
 __device__ __forceinline__ void reorth_factor_body(const double* __restrict__ G, const double* __restrict__ R1,
                                                    int n, double bound, double* __restrict__ Xs,
                                                    double* __restrict__ info, double* __restrict__ R, int64_t ldr,
                                                    double* Gs, int lane)
 {
-    constexpr int NPB = round16(NP), LD = NPB + 1, XLD = NPB;
-    // symmetric G from its upper triangle; lane j owns column j
+    constexpr int NPB = round16(NP), LD = NPB + 1;
+    double* Xl = Gs + NPB * LD;  // R2^{-1}
+    double* Rl = Xl + NPB * LD;  // R1
+    // symmetric G from its upper triangle, and R1; ||G - I||_F over the n x n block
     double dev = 0.0;
-    for (int j = lane; j < NPB; j += 64)
-        for (int i = 0; i < NPB; ++i) {
-            const double g = (i <= j) ? G[i + j * NPB] : G[j + i * NPB];
+    for (int e = lane; e < NPB * NPB; e += 64) {
+        const int i = e % NPB, j = e / NPB;
+        if (i <= j) {
+            const double g = G[e];
             Gs[i + j * LD] = g;
-            if (i < n && j < n) {
+            Gs[j + i * LD] = g;
+            if (j < n) {
                 const double d = g - (i == j ? 1.0 : 0.0);
-                dev = fma(d, d, dev);
+                dev = fma((i == j ? 1.0 : 2.0) * d, d, dev);
             }
         }
-    // ||G - I||_F over the n x n block: wave sum
+    }
+    for (int e = lane; e < NP * NP; e += 64) Rl[e % NP + (e / NP) * LD] = R1[e];
     for (int off = 32; off >= 1; off >>= 1) dev += __shfl_xor(dev, off);
     const double orth = sqrt(dev);
     const bool apply = orth > bound;
@@ -1694,38 +1718,48 @@ __device__ __forceinline__ void reorth_factor_body(const double* __restrict__ G,
             __syncthreads();
             for (int j = lane; j < n; j += 64)
                 if (j > k) {
+                    // rows k + 1 .. j of column j; row k is only read, so four
+                    // updates at a time load before they store
                     const double rkj = Gs[k + j * LD];
-                    for (int i = k + 1; i <= j; ++i) Gs[i + j * LD] = fma(-Gs[k + i * LD], rkj, Gs[i + j * LD]);
+                    int i = k + 1;
+                    for (; i + 3 <= j; i += 4) {
+                        double a[4], g[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            a[u] = Gs[k + (i + u) * LD];
+                            g[u] = Gs[i + u + j * LD];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) Gs[i + u + j * LD] = fma(-a[u], rkj, g[u]);
+                    }
+                    for (; i <= j; ++i) Gs[i + j * LD] = fma(-Gs[k + i * LD], rkj, Gs[i + j * LD]);
                 }
             __syncthreads();
         }
         // column j of R2^{-1} by back substitution (the lane reads back only its own writes)
         for (int j = lane; j < NPB; j += 64) {
-            for (int i = 0; i < NPB; ++i) Xs[i + j * XLD] = 0.0;
+            for (int i = 0; i < NPB; ++i) Xl[i + j * LD] = 0.0;
             if (j < n) {
-                Xs[j + j * XLD] = 1.0 / Gs[j + j * LD];
+                Xl[j + j * LD] = 1.0 / Gs[j + j * LD];
                 for (int i = j - 1; i >= 0; --i) {
-                    double acc = 0.0;
-                    for (int k = i + 1; k <= j; ++k) acc = fma(Gs[i + k * LD], Xs[k + j * XLD], acc);
-                    Xs[i + j * XLD] = -acc / Gs[i + i * LD];
+                    const double acc = lds_dot(Gs + i, LD, Xl + j * LD, i + 1, j + 1);
+                    Xl[i + j * LD] = -acc / Gs[i + i * LD];
                 }
             }
         }
     } else {
         for (int j = lane; j < NPB; j += 64)
             for (int i = 0; i < NPB; ++i) {
-                Xs[i + j * XLD] = (i == j && j < n) ? 1.0 : 0.0;
+                Xl[i + j * LD] = (i == j && j < n) ? 1.0 : 0.0;
                 Gs[i + j * LD] = (i == j) ? 1.0 : 0.0;
             }
     }
     __syncthreads();
+    for (int e = lane; e < NPB * NPB; e += 64) Xs[e] = Xl[e % NPB + (e / NPB) * LD];
     // R = R2 R1 (upper times upper), column j by lane j
     for (int j = lane; j < n; j += 64)
         for (int i = 0; i < n; ++i) {
-            double acc = 0.0;
-            if (i <= j)
-                for (int k = i; k <= j; ++k) acc = fma(Gs[i + k * LD], R1[k + j * NP], acc);
-            R[i + j * ldr] = acc;
+            R[i + j * ldr] = i <= j ? lds_dot(Gs + i, LD, Rl + j * LD, i, j + 1) : 0.0;
         }
     if (lane == 0) {
         info[0] = orth;
@@ -1738,9 +1772,8 @@ __global__ void __launch_bounds__(64) k_reorth_factor(const double* __restrict__
                                                       int n, double bound, double* __restrict__ Xs,
                                                       double* __restrict__ info, double* __restrict__ R, int64_t ldr)
 {
-    constexpr int NPB = round16(NP);
-    __shared__ double Gs[NPB * (NPB + 1)];
-    reorth_factor_body<NP>(G, R1, n, bound, Xs, info, R, ldr, Gs, threadIdx.x);
+    extern __shared__ double smem[];  // reorth_lds_doubles<NP>()
+    reorth_factor_body<NP>(G, R1, n, bound, Xs, info, R, ldr, smem, threadIdx.x);
 }
 
 // Q = Q1 R2^{-1} in FP64 (R2^{-1} = I when the check passed), 16 rows at a
@@ -2521,8 +2554,7 @@ __global__ void __launch_bounds__(64) k_reorth_factor_batch(const BatchProblem* 
                                                             const int64_t* __restrict__ items, int64_t nitems,
                                                             double bound)
 {
-    constexpr int NPB = round16(NP);
-    __shared__ double Gs[NPB * (NPB + 1)];
+    extern __shared__ double Gs[];  // reorth_lds_doubles<NP>()
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int64_t p = items[it] >> 32;
         const BatchProblem& B = probs[p];
@@ -2530,7 +2562,7 @@ __global__ void __launch_bounds__(64) k_reorth_factor_batch(const BatchProblem* 
         double* w = ws + B.ws_off;
         reorth_factor_body<NP>(w + B.off_G, w + B.off_R1, B.n, bound, w + B.off_R2inv, w + B.off_info, X.X, X.ldx,
                                Gs, threadIdx.x);
-        __syncthreads();  // the next item rewrites Gs
+        __syncthreads();  // the next item rewrites the LDS buffers
     }
 }
 
@@ -2633,8 +2665,10 @@ hipError_t batch_factor_mixed_np(const BatchClass& C, const BatchProblem* probs,
                        probs, ws, C.root_items, C.nprob);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_reorth_factor_batch<NP>), dim3((unsigned)(C.nprob < 4096 ? C.nprob : 4096)), dim3(64), 0,
-                       s, probs, args, ws, C.root_items, C.nprob, kReorthBound);
+    const size_t rlds = (size_t)reorth_lds_doubles<NP>() * sizeof(double);
+    allow_lds(k_reorth_factor_batch<NP>, rlds);
+    hipLaunchKernelGGL((k_reorth_factor_batch<NP>), dim3((unsigned)(C.nprob < 4096 ? C.nprob : 4096)), dim3(64),
+                       rlds, s, probs, args, ws, C.root_items, C.nprob, kReorthBound);
     return hipGetLastError();
 }
 
@@ -2712,7 +2746,9 @@ hipError_t reorth_np(const Layout& L, double* ws, double* R, int64_t ldr, hipStr
                        ws + L.off_G);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_reorth_factor<NP>), dim3(1), dim3(64), 0, s, ws + L.off_G, ws + L.off_R1, (int)L.n,
+    const size_t rlds = (size_t)reorth_lds_doubles<NP>() * sizeof(double);
+    allow_lds(k_reorth_factor<NP>, rlds);
+    hipLaunchKernelGGL((k_reorth_factor<NP>), dim3(1), dim3(64), rlds, s, ws + L.off_G, ws + L.off_R1, (int)L.n,
                        kReorthBound, ws + L.off_R2inv, ws + L.off_info, R, ldr);
     return hipGetLastError();
 }
