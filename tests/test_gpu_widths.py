@@ -70,3 +70,57 @@ def test_mixed_every_kernel_width(n):
     assert backward_error(A, Q, R) <= 1e-6
     assert orthogonality(Q) <= 1e-13
     assert rel_diff(R, oracle.qr_reference(A, want_q=False)) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [57, 59, 60])
+def test_apply_qt_on_64_column_kernels(n):
+    """Q^T B for widths padded by 4-7 columns, every row against the oracle's
+    replay of the same tree."""
+    torch = need_gpu()
+    from paper_0809_2407_amd import tsqr as T
+
+    m, k = 7000 + n, 33
+    A = synth.gaussian(m, n, seed=1300 + n)
+    B = synth.gaussian(m, k, seed=1400 + n)
+    announce(f"apply_qt width {n}: {m}x{n} k={k}")
+    Ad = T.to_colmajor(torch.from_numpy(A))
+    Bd = T.to_colmajor(torch.from_numpy(B))
+    with T.Plan(m, n, tree="hybrid", flat_len=3) as p:
+        info = p.info()
+        p.factor(Ad)
+        p.apply_qt(Ad, Bd)
+        torch.cuda.synchronize()
+    X = Bd.cpu().numpy()
+    Xo = oracle.TSQR(A, info["leaf_rows"], info["tile_rows"]).apply_qt(B)
+    assert np.abs(X - Xo).max() <= 1e-13 * np.linalg.norm(B)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_widths_57_to_60_equal_single_plans(precision):
+    """A batched plan whose 64-column class holds widths 57-60 and 64 gives
+    every problem the bits of its single-problem plan."""
+    torch = need_gpu()
+    from paper_0809_2407_amd import tsqr as T
+
+    shapes = [(9000, 57), (3000, 60), (12000, 64), (5000, 58), (2500, 59)]
+    mats = [synth.gaussian(m, n, seed=1500 + i) for i, (m, n) in enumerate(shapes)]
+    announce(f"batched {precision} widths 57-60")
+    with T.BatchedPlan([m for m, _ in shapes], [n for _, n in shapes], precision=precision) as bp:
+        assert all(bp.problem_info(i)["n_padded"] == 64 for i in range(len(shapes)))
+        As = [T.to_colmajor(torch.from_numpy(A)) for A in mats]
+        Rs = bp.factor(As)
+        Qs = bp.form_q(As, [T.colmajor(m, n) for m, n in shapes])
+        torch.cuda.synchronize()
+    for i, A in enumerate(mats):
+        m, n = A.shape
+        announce(f"batched {precision} problem {i} {A.shape} against a single plan")
+        Ad = T.to_colmajor(torch.from_numpy(A))
+        with T.Plan(m, n, precision=precision) as p:
+            R1 = p.factor(Ad)
+            Q1 = p.form_q(Ad if precision == "fp64" else None, T.colmajor(m, n))
+            torch.cuda.synchronize()
+        R, Q = Rs[i].cpu().numpy(), Qs[i].cpu().numpy()
+        assert np.array_equal(R, R1.cpu().numpy()) and np.array_equal(Q, Q1.cpu().numpy())
+        bound = fp64_bound(n) if precision == "fp64" else 1e-6
+        assert backward_error(A, Q, R) <= bound
+        assert orthogonality(Q) <= (fp64_bound(n) if precision == "fp64" else 1e-13)
