@@ -1925,27 +1925,35 @@ __global__ void __launch_bounds__(256) k_apply_leaf(const double* __restrict__ V
         for (int ib = 0; ib < JB; ++ib)
 #pragma unroll
             for (int jb = 0; jb < JK; ++jb) wacc[ib][jb] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int s = 0; s < MT / 4; ++s) {
-            const int r = 4 * s + q;
-            const bool rv = r < valid;
-            double yv[JB], bv[JK];
+        // 16 rows per block: lane group q takes rows 4q .. 4q + 3 of the block, so a
+        // column's 16 rows (one 128-byte line) are requested together; the
+        // contraction over rows takes them in this order
+#pragma unroll 1
+        for (int s = 0; s < MT / 16; ++s) {
+            double yv[4][JB], bv[4][JK];
 #pragma unroll
-            for (int b = 0; b < JB; ++b) {
-                const int c = 16 * b + p;
-                double y = (rv && c < n) ? V[t0 + r + (int64_t)c * lda] : 0.0;
-                if (first) y = c < NP ? (r > c ? y : (r == c ? 1.0 : 0.0)) : 0.0;
-                yv[b] = y;
+            for (int u = 0; u < 4; ++u) {
+                const int r = 16 * s + 4 * q + u;
+                const bool rv = r < valid;
+#pragma unroll
+                for (int b = 0; b < JB; ++b) {
+                    const int c = 16 * b + p;
+                    double y = (rv && c < n) ? V[t0 + r + (int64_t)c * lda] : 0.0;
+                    if (first) y = c < NP ? (r > c ? y : (r == c ? 1.0 : 0.0)) : 0.0;
+                    yv[u][b] = y;
+                }
+#pragma unroll
+                for (int jb = 0; jb < JK; ++jb) {
+                    const int c = 16 * jb + p;
+                    bv[u][jb] = (rv && c < kc) ? B[t0 + r + (int64_t)c * ldb] : 0.0;
+                }
             }
 #pragma unroll
-            for (int jb = 0; jb < JK; ++jb) {
-                const int c = 16 * jb + p;
-                bv[jb] = (rv && c < kc) ? B[t0 + r + (int64_t)c * ldb] : 0.0;
-            }
+            for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int ib = 0; ib < JB; ++ib)
+                for (int ib = 0; ib < JB; ++ib)
 #pragma unroll
-                for (int jb = 0; jb < JK; ++jb) wacc[ib][jb] = mfma16x16x4(yv[ib], bv[jb], wacc[ib][jb]);
+                    for (int jb = 0; jb < JK; ++jb) wacc[ib][jb] = mfma16x16x4(yv[u][ib], bv[u][jb], wacc[ib][jb]);
         }
         double Dr[KS][JK], Xr[KS][JK];
 #pragma unroll
