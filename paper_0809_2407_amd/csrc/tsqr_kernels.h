@@ -2145,16 +2145,21 @@ hipError_t leaf_factor_np(const Layout& L, const double* A, int64_t lda, double*
 template <int NP>
 hipError_t build_T_np(const Layout& L, double* ws, hipStream_t s)
 {
-    constexpr int waves = 4;
-    const size_t lds = (size_t)waves * BuildTLds<NP>::WS * sizeof(double);
-    const dim3 grid(grid_for(L.ntiles, waves)), block(64 * waves);
+    // FP64 above 48 columns: single-wavefront workgroups (7 fit a CU's LDS
+    // instead of one 4-wavefront group).  The T kernel gets 1.6x faster and the
+    // tree beside it slower; the step gained about 1% at n = 64.  The FP32 slots
+    // and narrower widths measured better with 4-wavefront groups.
+    constexpr int waves = 4, waves_d = NP > 48 ? 1 : 4;
     if (L.mixed) {
+        const size_t lds = (size_t)waves * BuildTLds<NP>::WS * sizeof(double);
         allow_lds(k_build_T<NP, float>, lds);
-        hipLaunchKernelGGL((k_build_T<NP, float>), grid, block, lds, s, reinterpret_cast<float*>(ws + L.off_T32),
-                           L.ntiles);
+        hipLaunchKernelGGL((k_build_T<NP, float>), dim3(grid_for(L.ntiles, waves)), dim3(64 * waves), lds, s,
+                           reinterpret_cast<float*>(ws + L.off_T32), L.ntiles);
     } else {
+        const size_t lds = (size_t)waves_d * BuildTLds<NP>::WS * sizeof(double);
         allow_lds(k_build_T<NP, double>, lds);
-        hipLaunchKernelGGL((k_build_T<NP, double>), grid, block, lds, s, ws + L.off_T, L.ntiles);
+        hipLaunchKernelGGL((k_build_T<NP, double>), dim3(grid_for(L.ntiles, waves_d)), dim3(64 * waves_d), lds, s,
+                           ws + L.off_T, L.ntiles);
     }
     return hipGetLastError();
 }
