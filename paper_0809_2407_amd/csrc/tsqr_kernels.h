@@ -117,6 +117,13 @@ __device__ __forceinline__ void st_at(E* base, O byte_off, E v)
 {
     *reinterpret_cast<E*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
+// The same as a non-temporal store (output written once and not read again by
+// the path: the explicit Q).
+template <typename E, typename O>
+__device__ __forceinline__ void st_nt(E* base, O byte_off, E v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<E*>(reinterpret_cast<char*>(base) + byte_off));
+}
 
 // True when the byte offset of element (15, 3) of a 16 x 4 block with leading
 // dimension ld fits in 32 bits, so 32-bit per-lane offsets can be used.
@@ -1386,7 +1393,10 @@ constexpr int fq_col_blocks(int np)
 // round16(NP) columns (rows past m hold values of zero rows of V; columns past
 // n are zero).  Rows past m and columns past n of V are zeros there too, so
 // no load or store needs a mask.
-template <int NP, bool WIDE, typename E>
+// NTQ: the FP64 Q is written with non-temporal stores (a single large problem:
+// 1% off the Q kernel at n = 32; the batched plans' ragged small problems
+// measured 8% slower with them).
+template <int NP, bool WIDE, typename E, bool NTQ = false>
 __device__ __forceinline__ void form_q_leaf(const E* V, int64_t lda, int64_t m, int n, int64_t P, int64_t leaf_rows,
                                             int64_t f, const E* __restrict__ Ttile, const double* __restrict__ Sleaf,
                                             E* Q, int64_t ldq, int64_t leaf, int j0, E* Ss, int lane)
@@ -1531,7 +1541,8 @@ __device__ __forceinline__ void form_q_leaf(const E* V, int64_t lda, int64_t m, 
                         st_at(qb + (int64_t)(16 * jb + r) * ldq, lane_q, c < n ? v : E(0));
                     } else if (c < n && (full || rv)) {
                         // the window spans round16(NP) columns: those at or past n are never stored
-                        st_at(qb + (int64_t)(16 * jb + 4 * r) * ldq, lane_q, v);
+                        if constexpr (NTQ) st_nt(qb + (int64_t)(16 * jb + 4 * r) * ldq, lane_q, v);
+                        else st_at(qb + (int64_t)(16 * jb + 4 * r) * ldq, lane_q, v);
                     }
                 }
             }
@@ -1552,7 +1563,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     const int64_t leaf = gw / SPLIT;
     const int j0 = (int)(gw % SPLIT) * JW;
     if (leaf >= P) return;
-    form_q_leaf<NP, WIDE, E>(V, lda, m, n, P, leaf_rows, f, Ttile, Sleaf, Q, ldq, leaf, j0,
+    form_q_leaf<NP, WIDE, E, true>(V, lda, m, n, P, leaf_rows, f, Ttile, Sleaf, Q, ldq, leaf, j0,
                              smem + wave * NPB * 16 * JW, lane);
 }
 
