@@ -135,7 +135,9 @@ tsqr_status tsqr_factor_into(tsqr_plan p, const double* A, int64_t lda, double* 
 
 /* Explicit thin Q (m x n, ldq >= m) from the reflectors tsqr_factor left in A
  * and the plan's tree (the broadcast of Sec. 4.1).  A = Q R with Q^T Q = I.
- * Q may alias A (same pointer and same leading dimension).  On a MIXED plan
+ * Q may alias A (same pointer and same leading dimension; above 48 columns
+ * that call gives each leaf one wavefront instead of two, since both would
+ * read every reflector column of the rows whose Q they write).  On a MIXED plan
  * A_factored and lda are not used (Q may be the original A) and Q is Q1 R2^{-1}
  * from the second pass.
  * Errors: -1 p, -2 A NULL, -3 lda < m, -4 Q NULL, -5 ldq < m or aliasing with a
@@ -260,8 +262,9 @@ tsqr_status tsqr_tune_cache_store(const char* cache_path, int64_t m, int64_t n, 
  * launch: persistent kernels walk device work lists of (problem, leaf) and
  * (problem, tree node) items, one launch per phase and tree level, and the
  * whole sequence is captured once into a HIP graph that each call replays
- * (one small pointer upload and one graph launch on the plan's stream, no
- * host synchronisation).  MIXED batched plans run the mixed path the same way
+ * (one small pointer upload and one graph launch on the plan's stream; the
+ * host waits only when more than four calls of a kind are still queued, for a
+ * pinned staging buffer of the upload to come free).  MIXED batched plans run the mixed path the same way
  * (FP32 first pass, FP64 second pass per problem inside the same graphs) with
  * the results of single MIXED plans; tsqr_batched_problem_info then reports
  * each problem's check (and synchronises the plan's stream).  opts apply to
@@ -284,7 +287,10 @@ tsqr_status tsqr_batched_factor(tsqr_batched_plan p, double* const* A, const int
                                 const int64_t* ldr);
 
 /* Explicit thin Q[i] (m[i] x n[i], ldq[i] >= m[i]) of every problem from its
- * factored A[i]; Q[i] may alias A[i] with the same leading dimension.
+ * factored A[i]; Q[i] may alias A[i] with the same leading dimension (a call
+ * with some Q[i] == A[i] replays a second graph, captured on first use, that
+ * gives each leaf one wavefront: above 48 columns the other graph splits a
+ * leaf's columns over two wavefronts, which both read all of its reflectors).
  * Errors as tsqr_batched_factor (-4 Q, -5 ldq or aliasing with another
  * leading dimension); 4 when no factorisation with reflectors was done. */
 tsqr_status tsqr_batched_form_q(tsqr_batched_plan p, double* const* A, const int64_t* lda, double* const* Q,

@@ -8,9 +8,9 @@
 // precision also the (problem, row group) items of the second pass -- and the
 // persistent batched kernels walk them.  The per-problem geometry and
 // workspace offsets are uploaded once; the matrix pointers of a call go
-// through a pinned staging buffer to a small device table, so the captured
-// graphs never change and a call costs one small copy and one graph launch,
-// with no host synchronisation.
+// through a ring of pinned staging buffers to a small device table, so the
+// captured graphs never change and a call costs one small copy and one graph
+// launch; the host waits only when more than four calls of a kind are queued.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,6 +24,8 @@
 namespace tsqr {
 bool tuned_opts(int64_t m, int64_t n, tsqr_precision prec, int want_q, tsqr_opts* out);  // tsqr_tune.cpp
 }
+
+constexpr int kStageRing = 4;
 
 struct tsqr_batched_plan_s {
     int count = 0;
@@ -40,10 +42,16 @@ struct tsqr_batched_plan_s {
     int64_t* d_items = nullptr;
     tsqr::BatchArgs* d_args_f = nullptr;
     tsqr::BatchArgs* d_args_q = nullptr;
-    tsqr::BatchArgs* h_args_f = nullptr;  // pinned staging
-    tsqr::BatchArgs* h_args_q = nullptr;
-    hipEvent_t ev_f = nullptr, ev_q = nullptr;  // the staging copies have been consumed
-    hipGraphExec_t g_factor = nullptr, g_form_q = nullptr;
+    // pinned staging of the per-call pointer tables: a ring of kStageRing
+    // buffers per kind, each with an event recorded after its upload, so the
+    // host waits only when more than kStageRing calls of a kind are queued
+    tsqr::BatchArgs* h_args_f[kStageRing] = {nullptr};
+    tsqr::BatchArgs* h_args_q[kStageRing] = {nullptr};
+    hipEvent_t ev_f[kStageRing] = {nullptr}, ev_q[kStageRing] = {nullptr};
+    int next_f = 0, next_q = 0;
+    // the Q graph of calls where some Q[i] is A[i] (one wavefront per leaf,
+    // see k_form_q) and of the others
+    hipGraphExec_t g_factor = nullptr, g_form_q = nullptr, g_form_q_alias = nullptr;
     int state = 0;  // 0: nothing factored, 1: factored with reflectors, 2: R only
 };
 
@@ -60,10 +68,13 @@ void release(tsqr_batched_plan_s* p)
 {
     if (p->g_factor) hipGraphExecDestroy(p->g_factor);
     if (p->g_form_q) hipGraphExecDestroy(p->g_form_q);
-    if (p->ev_f) hipEventDestroy(p->ev_f);
-    if (p->ev_q) hipEventDestroy(p->ev_q);
-    if (p->h_args_f) hipHostFree(p->h_args_f);
-    if (p->h_args_q) hipHostFree(p->h_args_q);
+    if (p->g_form_q_alias) hipGraphExecDestroy(p->g_form_q_alias);
+    for (int r = 0; r < kStageRing; ++r) {
+        if (p->ev_f[r]) hipEventDestroy(p->ev_f[r]);
+        if (p->ev_q[r]) hipEventDestroy(p->ev_q[r]);
+        if (p->h_args_f[r]) hipHostFree(p->h_args_f[r]);
+        if (p->h_args_q[r]) hipHostFree(p->h_args_q[r]);
+    }
     if (p->d_args_f) hipFree(p->d_args_f);
     if (p->d_args_q) hipFree(p->d_args_q);
     if (p->d_items) hipFree(p->d_items);
@@ -88,11 +99,18 @@ hipError_t capture_graph(hipStream_t cap, hipGraphExec_t* exec, F&& enqueue)
     return e;
 }
 
-// Uploads the pointers of one call through the pinned staging buffer; waits
-// (host side) only for the previous upload from the same buffer.
-hipError_t stage_args(tsqr_batched_plan_s* p, tsqr::BatchArgs* h, tsqr::BatchArgs* d, hipEvent_t ev,
-                      double* const* A, const int64_t* lda, double* const* X, const int64_t* ldx)
+// Uploads the pointers of one call through the next pinned staging buffer of
+// the ring; waits (host side) only for the upload kStageRing calls back from
+// that same buffer.  The device table is overwritten in stream order, after
+// the graph replays enqueued before it have read it.
+hipError_t stage_args(tsqr_batched_plan_s* p, tsqr::BatchArgs* const* hring, tsqr::BatchArgs* d,
+                      hipEvent_t const* evring, int& next, double* const* A, const int64_t* lda, double* const* X,
+                      const int64_t* ldx)
 {
+    const int r = next;
+    next = (next + 1) % kStageRing;
+    tsqr::BatchArgs* h = hring[r];
+    hipEvent_t ev = evring[r];
     hipError_t e = hipEventSynchronize(ev);
     if (e != hipSuccess) return e;
     for (int i = 0; i < p->count; ++i) h[i] = tsqr::BatchArgs{A[i], lda[i], X[i], ldx[i]};
@@ -262,10 +280,13 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, sizeof(int64_t) * std::max<size_t>(1, all.size()));
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_args_f, sizeof(tsqr::BatchArgs) * count);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_args_q, sizeof(tsqr::BatchArgs) * count);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_args_f, sizeof(tsqr::BatchArgs) * count, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_args_q, sizeof(tsqr::BatchArgs) * count, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_f, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_q, hipEventDisableTiming);
+    for (int r = 0; r < kStageRing && e == hipSuccess; ++r) {
+        e = hipHostMalloc((void**)&p->h_args_f[r], sizeof(tsqr::BatchArgs) * count, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void**)&p->h_args_q[r], sizeof(tsqr::BatchArgs) * count, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_f[r], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_q[r], hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
     if (e == hipSuccess)
         e = hipMemcpy(p->d_probs, bp.data(), sizeof(tsqr::BatchProblem) * count, hipMemcpyHostToDevice);
@@ -312,7 +333,7 @@ tsqr_status tsqr_batched_factor(tsqr_batched_plan p, double* const* A, const int
         if (ldr[i] < p->L[i].n) return -5;
     }
     p->state = 0;
-    hipError_t e = stage_args(p, p->h_args_f, p->d_args_f, p->ev_f, A, lda, R, ldr);
+    hipError_t e = stage_args(p, p->h_args_f, p->d_args_f, p->ev_f, p->next_f, A, lda, R, ldr);
     if (e == hipSuccess && !p->g_factor) {
         e = capture_graph(p->capture, &p->g_factor, [&](hipStream_t s) {
             for (const tsqr::BatchClass& C : p->classes) {
@@ -348,20 +369,25 @@ tsqr_status tsqr_batched_form_q(tsqr_batched_plan p, double* const* A, const int
         if (Q[i] == A[i] && ldq[i] != lda[i]) return -5;
     }
     if (p->state != 1) return 4;
-    hipError_t e = stage_args(p, p->h_args_q, p->d_args_q, p->ev_q, A, lda, Q, ldq);
-    if (e == hipSuccess && !p->g_form_q) {
-        e = capture_graph(p->capture, &p->g_form_q, [&](hipStream_t s) {
+    // FP64: Q over A in any problem selects the graph with one wavefront per
+    // leaf (MIXED plans read their reflectors from the workspace)
+    bool alias = false;
+    for (int i = 0; i < p->count && p->prec != TSQR_MIXED; ++i) alias = alias || Q[i] == A[i];
+    hipGraphExec_t* g = alias ? &p->g_form_q_alias : &p->g_form_q;
+    hipError_t e = stage_args(p, p->h_args_q, p->d_args_q, p->ev_q, p->next_q, A, lda, Q, ldq);
+    if (e == hipSuccess && !*g) {
+        e = capture_graph(p->capture, g, [&](hipStream_t s) {
             for (const tsqr::BatchClass& C : p->classes) {
                 const int waves = p->waves > 0 ? p->waves : (p->want_q ? 4 : 1);
                 hipError_t el = p->prec == TSQR_MIXED
                                     ? tsqr::launch_batch_form_q_mixed(C, p->d_probs, p->d_args_q, p->ws, s)
-                                    : tsqr::launch_batch_form_q(C, p->d_probs, p->d_args_q, p->ws, waves, s);
+                                    : tsqr::launch_batch_form_q(C, p->d_probs, p->d_args_q, p->ws, waves, alias, s);
                 if (el != hipSuccess) return el;
             }
             return hipSuccess;
         });
     }
-    if (e == hipSuccess) e = hipGraphLaunch(p->g_form_q, p->stream);
+    if (e == hipSuccess) e = hipGraphLaunch(*g, p->stream);
     return hstatus(e);
 }
 

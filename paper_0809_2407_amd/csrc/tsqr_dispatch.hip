@@ -140,9 +140,9 @@ hipError_t launch_batch_factor(const BatchClass& C, const BatchProblem* probs, c
 }
 
 hipError_t launch_batch_form_q(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
-                               int waves, hipStream_t s)
+                               int waves, bool alias, hipStream_t s)
 {
-#define CALL(NP) batch_form_q_np<NP>(C, probs, args, ws, waves, s)
+#define CALL(NP) batch_form_q_np<NP>(C, probs, args, ws, waves, alias, s)
     TSQR_NP_SWITCH(C.np, CALL)
 #undef CALL
 }

@@ -166,8 +166,9 @@ hipError_t launch_reorth_q(const Layout& L, double* ws, double* Q, int64_t ldq, 
 // batched FP64: every problem of a width class in one launch per phase
 hipError_t launch_batch_factor(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
                                bool want_q, int waves, hipStream_t s);
+// alias: some problem's Q is its A (the graph then takes one wavefront per leaf)
 hipError_t launch_batch_form_q(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
-                               int waves, hipStream_t s);
+                               int waves, bool alias, hipStream_t s);
 hipError_t launch_batch_factor_mixed(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args,
                                      double* ws, bool want_q, int waves, hipStream_t s);
 hipError_t launch_batch_form_q_mixed(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args,
@@ -206,7 +207,7 @@ hipError_t batch_factor_np(const BatchClass& C, const BatchProblem* probs, const
                            bool want_q, int waves, hipStream_t s);
 template <int NP>
 hipError_t batch_form_q_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
-                           int waves, hipStream_t s);
+                           int waves, bool alias, hipStream_t s);
 template <int NP>
 hipError_t batch_factor_mixed_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
                                  bool want_q, int waves, hipStream_t s);

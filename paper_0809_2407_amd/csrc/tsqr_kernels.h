@@ -1396,7 +1396,58 @@ constexpr int fq_col_blocks(int np)
 // NTQ: the FP64 Q is written with non-temporal stores (a single large problem:
 // 1% off the Q kernel at n = 32; the batched plans' ragged small problems
 // measured 8% slower with them).
-template <int NP, bool WIDE, typename E, bool NTQ = false>
+// One step of a leaf's seed windows jofs .. jofs + JN - 1 (16 columns each,
+// held in LDS at Ss in the register layout of the products): for a chained
+// tile (first == false) Z = T S and the window becomes S - Z (the seed of the
+// tile above); for the chain's first tile, Z = T (V_top^T S_0) with V_top the
+// unit lower triangle of the tile's top rows, and S_0 stays (the [S_0; 0]
+// term of the expansion).
+template <int NP, int JN, typename E>
+__device__ __forceinline__ void seed_windows(const E* __restrict__ T, const E* V, int64_t t0, int64_t lda,
+                                             int64_t valid, int n, bool first, E* Ss, int jofs,
+                                             E (&Zr)[round16(NP) / 4][JN], int lane)
+{
+    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
+    typedef Mfma<E> MM;
+    const int cg = lane >> 4, rg = lane & 15;
+    E Sr[KS][JN];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int jb = 0; jb < JN; ++jb) Sr[s][jb] = Ss[krow<E>(s, cg) + (16 * (jofs + jb) + rg) * NPB];
+    if (!first) {
+        tri_times_regs<NP, JN, E>(T, Sr, Zr, lane);
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int jb = 0; jb < JN; ++jb) Ss[krow<E>(s, cg) + (16 * (jofs + jb) + rg) * NPB] = Sr[s][jb] - Zr[s][jb];
+    } else {
+        E Wr[KS][JN];
+#pragma unroll
+        for (int ib = 0; ib < JB; ++ib) {
+            // V_top(r, 16 ib + p) vanishes for r < 16 ib
+            E vt[KS];
+#pragma unroll
+            for (int s = 4 * ib; s < KS; ++s) {
+                const int r = krow<E>(s, cg), c = 16 * ib + rg;  // V_top(r, c)
+                const bool ok = r > c && r < valid && c < n;
+                const E v = V[t0 + (ok ? r + (int64_t)c * lda : 0)];
+                vt[s] = ok ? v : (r == c && r < NP ? E(1) : E(0));
+            }
+#pragma unroll
+            for (int jb = 0; jb < JN; ++jb) {
+                typename MM::acc_t acc = MM::zero();
+#pragma unroll
+                for (int s = 4 * ib; s < KS; ++s) acc = MM::mma(vt[s], Sr[s][jb], acc);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Wr[4 * ib + r][jb] = acc[r];
+            }
+        }
+        tri_times_regs<NP, JN, E>(T, Wr, Zr, lane);
+    }
+}
+
+template <int NP, bool WIDE, typename E, bool NTQ = false, int JWT = fq_col_blocks<E>(NP)>
 __device__ __forceinline__ void form_q_leaf(const E* V, int64_t lda, int64_t m, int n, int64_t P, int64_t leaf_rows,
                                             int64_t f, const E* __restrict__ Ttile, const double* __restrict__ Sleaf,
                                             E* Q, int64_t ldq, int64_t leaf, int j0, E* Ss, int lane)
@@ -1407,8 +1458,11 @@ __device__ __forceinline__ void form_q_leaf(const E* V, int64_t lda, int64_t m, 
     // k-steps of the expansion: the FP32 permutation of k mixes the columns of
     // a 16-block, so whole blocks are contracted (their padding is zero)
     constexpr int KX = MIXED ? KS : KC;
-    constexpr int JW = fq_col_blocks<E>(NP), SPLIT = JB / JW;
+    constexpr int JW = JWT;
     constexpr int FQU = NP > 48 ? 1 : 2;  // row blocks in flight; more spills at the widest tiles
+    // FP64 with more than two windows per wavefront: the seed step runs one
+    // window at a time (a seed and its product for all four would not fit the registers)
+    constexpr bool PERW = !MIXED && JW > 2;
     static_assert(JB % JW == 0, "column window must divide the padded width");
     typedef Mfma<E> MM;
     const int cg = lane >> 4, rg = lane & 15;
@@ -1448,45 +1502,19 @@ __device__ __forceinline__ void form_q_leaf(const E* V, int64_t lda, int64_t m, 
         const int64_t t0 = row0 + t * MT;
         const int64_t valid = MIXED ? MT : ((rows - t * MT) < MT ? (rows - t * MT) : MT);
         E Zr[KS][JW];
-        {
-            E Sr[KS][JW];
+        if constexpr (PERW) {
+            // one window at a time: the seed and its product never share the registers
 #pragma unroll
-            for (int s = 0; s < KS; ++s)
+            for (int jb = 0; jb < JW; ++jb) {
+                E Z1[KS][1];
+                seed_windows<NP, 1, E>(T, V, t0, lda, valid, n, t == 0, Ss, jb, Z1, lane);
 #pragma unroll
-                for (int jb = 0; jb < JW; ++jb) Sr[s][jb] = Ss[krow<E>(s, cg) + (16 * jb + rg) * NPB];
-            if (t > 0) {
-                tri_times_regs<NP, JW, E>(T, Sr, Zr, lane);
-#pragma unroll
-                for (int s = 0; s < KS; ++s)
-#pragma unroll
-                    for (int jb = 0; jb < JW; ++jb) Ss[krow<E>(s, cg) + (16 * jb + rg) * NPB] = Sr[s][jb] - Zr[s][jb];
-            } else {
-                // W = V_top^T S_0 with V_top the unit lower triangle of the tile's top rows
-                E Wr[KS][JW];
-#pragma unroll
-                for (int ib = 0; ib < JB; ++ib) {
-                    // V_top(r, 16 ib + p) vanishes for r < 16 ib
-                    E vt[KS];
-#pragma unroll
-                    for (int s = 4 * ib; s < KS; ++s) {
-                        const int r = krow<E>(s, cg), c = 16 * ib + rg;  // V_top(r, c)
-                        const bool ok = r > c && r < valid && c < n;
-                        const E v = V[t0 + (ok ? r + (int64_t)c * lda : 0)];
-                        vt[s] = ok ? v : (r == c && r < NP ? E(1) : E(0));
-                    }
-#pragma unroll
-                    for (int jb = 0; jb < JW; ++jb) {
-                        typename MM::acc_t acc = MM::zero();
-#pragma unroll
-                        for (int s = 4 * ib; s < KS; ++s) acc = MM::mma(vt[s], Sr[s][jb], acc);
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) Wr[4 * ib + r][jb] = acc[r];
-                    }
-                }
-                tri_times_regs<NP, JW, E>(T, Wr, Zr, lane);
-                __builtin_amdgcn_wave_barrier();  // S_0 is read across lanes below
+                for (int s = 0; s < KS; ++s) Zr[s][jb] = Z1[s][0];
             }
+        } else {
+            seed_windows<NP, JW, E>(T, V, t0, lda, valid, n, t == 0, Ss, 0, Zr, lane);
         }
+        if (t == 0) __builtin_amdgcn_wave_barrier();  // S_0 is read across lanes below
         // expansion Q_t = [S_0; 0] (t == 0 only) - V_t Z, 16 rows at a time
         const bool full = valid == MT;  // every row of the tile exists
 #pragma unroll FQU
@@ -1550,12 +1578,17 @@ __device__ __forceinline__ void form_q_leaf(const E* V, int64_t lda, int64_t m, 
     }
 }
 
-template <int NP, bool WIDE, typename E = double>
+// JWT: 16-column windows per wavefront.  A leaf split over several
+// wavefronts (JWT < round16(NP) / 16) must not have Q alias V: every
+// wavefront reads all of V's columns for the rows whose Q window it writes, so
+// one wavefront's stores could overwrite reflectors another has yet to read.
+// Aliased calls take JWT = round16(NP) / 16 (one wavefront per leaf).
+template <int NP, bool WIDE, typename E = double, int JWT = fq_col_blocks<E>(NP)>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_form_q(const E* V, int64_t lda, int64_t m, int n, int64_t P,
                                                 int64_t leaf_rows, int64_t f, const E* __restrict__ Ttile,
                                                 const double* __restrict__ Sleaf, E* Q, int64_t ldq)
 {
-    constexpr int NPB = round16(NP), JW = fq_col_blocks<E>(NP), SPLIT = NPB / 16 / JW;
+    constexpr int NPB = round16(NP), JW = JWT, SPLIT = NPB / 16 / JW;
     extern __shared__ double smem_d[];
     E* smem = reinterpret_cast<E*>(smem_d);
     const int wave = wave_index(), lane = threadIdx.x & 63;
@@ -1563,8 +1596,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     const int64_t leaf = gw / SPLIT;
     const int j0 = (int)(gw % SPLIT) * JW;
     if (leaf >= P) return;
-    form_q_leaf<NP, WIDE, E, true>(V, lda, m, n, P, leaf_rows, f, Ttile, Sleaf, Q, ldq, leaf, j0,
-                             smem + wave * NPB * 16 * JW, lane);
+    form_q_leaf<NP, WIDE, E, true, JW>(V, lda, m, n, P, leaf_rows, f, Ttile, Sleaf, Q, ldq, leaf, j0,
+                                       smem + wave * NPB * 16 * JW, lane);
 }
 
 // --------------------------------------------------------------------------
@@ -2220,23 +2253,33 @@ hipError_t seeds_np(const Layout& L, double* ws, hipStream_t s)
     return hipSuccess;
 }
 
+template <int NP, int JW>
+hipError_t form_q_launch(const Layout& L, const double* A, int64_t lda, double* ws, double* Q, int64_t ldq,
+                         hipStream_t s)
+{
+    constexpr int NPB = round16(NP), SPLIT = NPB / 16 / JW;
+    const size_t lds = (size_t)L.waves * NPB * 16 * JW * sizeof(double);
+    const dim3 grid(grid_for(L.P * SPLIT, L.waves)), block(64 * L.waves);
+    if (lane_offsets_fit_32(lda) && lane_offsets_fit_32(ldq)) {
+        allow_lds(k_form_q<NP, false, double, JW>, lds);
+        hipLaunchKernelGGL((k_form_q<NP, false, double, JW>), grid, block, lds, s, A, lda, L.m, (int)L.n, L.P,
+                           L.leaf_rows, L.f, ws + L.off_T, ws + L.off_S[0], Q, ldq);
+    } else {
+        allow_lds(k_form_q<NP, true, double, JW>, lds);
+        hipLaunchKernelGGL((k_form_q<NP, true, double, JW>), grid, block, lds, s, A, lda, L.m, (int)L.n, L.P,
+                           L.leaf_rows, L.f, ws + L.off_T, ws + L.off_S[0], Q, ldq);
+    }
+    return hipGetLastError();
+}
+
 template <int NP>
 hipError_t form_q_np(const Layout& L, const double* A, int64_t lda, double* ws, double* Q, int64_t ldq,
                      hipStream_t s)
 {
-    constexpr int NPB = round16(NP), JW = fq_col_blocks<double>(NP), SPLIT = NPB / 16 / JW;
-    const size_t lds = (size_t)L.waves * NPB * 16 * JW * sizeof(double);
-    const dim3 grid(grid_for(L.P * SPLIT, L.waves)), block(64 * L.waves);
-    if (lane_offsets_fit_32(lda) && lane_offsets_fit_32(ldq)) {
-        allow_lds(k_form_q<NP, false, double>, lds);
-        hipLaunchKernelGGL((k_form_q<NP, false, double>), grid, block, lds, s, A, lda, L.m, (int)L.n, L.P,
-                           L.leaf_rows, L.f, ws + L.off_T, ws + L.off_S[0], Q, ldq);
-    } else {
-        allow_lds(k_form_q<NP, true, double>, lds);
-        hipLaunchKernelGGL((k_form_q<NP, true, double>), grid, block, lds, s, A, lda, L.m, (int)L.n, L.P,
-                           L.leaf_rows, L.f, ws + L.off_T, ws + L.off_S[0], Q, ldq);
-    }
-    return hipGetLastError();
+    constexpr int NPB = round16(NP), JB = NPB / 16, JW = fq_col_blocks<double>(NP);
+    // Q over V: one wavefront per leaf (see k_form_q)
+    if ((const double*)Q == A && JW < JB) return form_q_launch<NP, JB>(L, A, lda, ws, Q, ldq, s);
+    return form_q_launch<NP, JW>(L, A, lda, ws, Q, ldq, s);
 }
 
 template <int NP>
@@ -2370,12 +2413,14 @@ __global__ void __launch_bounds__(256) k_seed_batch(const BatchProblem* __restri
     }
 }
 
-template <int NP>
+// JWT as for k_form_q: the graph of calls with some Q[i] aliasing A[i] takes
+// one wavefront per leaf.
+template <int NP, int JWT = fq_col_blocks<double>(NP)>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_form_q_batch(const BatchProblem* __restrict__ probs,
                                                     const BatchArgs* __restrict__ args, double* ws,
                                                     const int64_t* __restrict__ items, int64_t nitems)
 {
-    constexpr int NPB = round16(NP), JW = fq_col_blocks<double>(NP), SPLIT = NPB / 16 / JW;
+    constexpr int NPB = round16(NP), JW = JWT, SPLIT = NPB / 16 / JW;
     extern __shared__ double smem[];
     const int wave = wave_index(), lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -2386,8 +2431,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         const BatchProblem& B = probs[p];
         const BatchArgs X = args[p];
         double* w = ws + B.ws_off;
-        form_q_leaf<NP, true, double>(X.A, X.lda, B.m, B.n, B.P, B.leaf_rows, B.f, w + B.off_T, w + B.off_S[0],
-                                      X.X, X.ldx, leaf, j0, smem + wave * NPB * 16 * JW, lane);
+        form_q_leaf<NP, true, double, false, JW>(X.A, X.lda, B.m, B.n, B.P, B.leaf_rows, B.f, w + B.off_T,
+                                                 w + B.off_S[0], X.X, X.ldx, leaf, j0, smem + wave * NPB * 16 * JW,
+                                                 lane);
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -2444,9 +2490,21 @@ hipError_t batch_factor_np(const BatchClass& C, const BatchProblem* probs, const
     return hipGetLastError();
 }
 
+template <int NP, int JW>
+hipError_t batch_form_q_launch(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
+                               int waves, hipStream_t s)
+{
+    constexpr int NPB = round16(NP), SPLIT = NPB / 16 / JW;
+    const size_t lds = (size_t)waves * NPB * 16 * JW * sizeof(double);
+    allow_lds(k_form_q_batch<NP, JW>, lds);
+    hipLaunchKernelGGL((k_form_q_batch<NP, JW>), dim3(batch_grid(C.n_leaf * SPLIT, waves)), dim3(64 * waves), lds,
+                       s, probs, args, ws, C.leaf_items, C.n_leaf);
+    return hipGetLastError();
+}
+
 template <int NP>
 hipError_t batch_form_q_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
-                           int waves, hipStream_t s)
+                           int waves, bool alias, hipStream_t s)
 {
     for (int l = C.max_levels; l >= 1; --l) {
         hipLaunchKernelGGL((k_seed_batch<NP>), dim3(batch_grid(C.n_level[l], 4)), dim3(256), 0, s, probs, ws,
@@ -2454,12 +2512,10 @@ hipError_t batch_form_q_np(const BatchClass& C, const BatchProblem* probs, const
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    constexpr int NPB = round16(NP), JW = fq_col_blocks<double>(NP), SPLIT = NPB / 16 / JW;
-    const size_t lds = (size_t)waves * NPB * 16 * JW * sizeof(double);
-    allow_lds(k_form_q_batch<NP>, lds);
-    hipLaunchKernelGGL((k_form_q_batch<NP>), dim3(batch_grid(C.n_leaf * SPLIT, waves)), dim3(64 * waves), lds, s,
-                       probs, args, ws, C.leaf_items, C.n_leaf);
-    return hipGetLastError();
+    constexpr int NPB = round16(NP), JB = NPB / 16, JWD = fq_col_blocks<double>(NP);
+    // Q over A in some problem: one wavefront per leaf (see k_form_q)
+    if (alias && JWD < JB) return batch_form_q_launch<NP, JB>(C, probs, args, ws, waves, s);
+    return batch_form_q_launch<NP, JWD>(C, probs, args, ws, waves, s);
 }
 
 // ---- batched mixed precision ------------------------------------------------
@@ -2891,9 +2947,9 @@ hipError_t batch_factor_np(const BatchClass& C, const BatchProblem* probs, const
 }
 template <int NP>
 hipError_t batch_form_q_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
-                           int waves, hipStream_t s)
+                           int waves, bool alias, hipStream_t s)
 {
-    return detail::batch_form_q_np<NP>(C, probs, args, ws, waves, s);
+    return detail::batch_form_q_np<NP>(C, probs, args, ws, waves, alias, s);
 }
 template <int NP>
 hipError_t batch_factor_mixed_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
@@ -2928,7 +2984,7 @@ hipError_t batch_form_q_mixed_np(const BatchClass& C, const BatchProblem* probs,
     template hipError_t batch_factor_np<NP>(const BatchClass&, const BatchProblem*, const BatchArgs*, double*,  \
                                             bool, int, hipStream_t);                                          \
     template hipError_t batch_form_q_np<NP>(const BatchClass&, const BatchProblem*, const BatchArgs*, double*,  \
-                                            int, hipStream_t);                                                \
+                                            int, bool, hipStream_t);                                          \
     template hipError_t batch_factor_mixed_np<NP>(const BatchClass&, const BatchProblem*, const BatchArgs*,    \
                                                   double*, bool, int, hipStream_t);                           \
     template hipError_t batch_form_q_mixed_np<NP>(const BatchClass&, const BatchProblem*, const BatchArgs*,    \
