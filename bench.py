@@ -9,6 +9,18 @@ factors, the root sign normalisation, the top-down seed descent and the Q
 expansion (tsqr_factor_into + tsqr_form_q; A is only read, so every step sees
 the same input).  Prints ONE JSON line.
 
+The default line also carries, unless --no-extras:
+  accuracy.R_vs_oracle   ||R - R_oracle||_F / ||R_oracle||_F on the whole matrix
+                         (the oracle of the cpu_baseline leg, signs normalised);
+  mixed_vs_fp64          m = 2^24, n = 64, sigma 1 .. 1e-6: the FP64 path and
+                         the mixed path on the same matrix, both times, each
+                         path's accuracy against its own stated bounds and the
+                         R of each against the FP64 oracle;
+  batched                2048 problems (m_i uniform on 1000..200000, n_i on
+                         {8, 16, 32, 64}): one batched plan per call against the
+                         loop of single calls on the same stream (FP64), and
+                         the mixed batched plan on the same problems.
+
 Flop convention (nominal): R + Q = 4mn^2 - 4n^3/3, R only = 2mn^2 - 2n^3/3.
 Byte convention (algorithmic HBM traffic): factor with reflectors 16mn (read A,
 write V), Q expansion 16mn (read V, write Q).
@@ -129,9 +141,21 @@ def measured_traffic(m: int, n: int, kernel: str):
     return None
 
 
-def cpu_baseline(A_dev, info: dict, sample_rows: int, mode: str):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A_dev, info: dict, sample_rows: int, mode: str, one_thread_rows: int = 1 << 20):
     """The oracle as it stands, on the first sample_rows rows of the same input,
-    on the host cores (tree of the same shape: same leaf and tile rows)."""
+    on the host cores (tree of the same shape: same leaf and tile rows), and
+    on one core over the first one_thread_rows rows.  Returns the record and
+    the oracle's R of the sample."""
     import numpy as np
 
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
@@ -141,49 +165,119 @@ def cpu_baseline(A_dev, info: dict, sample_rows: int, mode: str):
     ms = min(m, sample_rows)
     As = np.asfortranarray(A_dev[:ms].cpu().numpy())
     threads = oracle.num_threads()
-    t0 = time.perf_counter()
-    t = oracle.TSQR(As, info["leaf_rows"], info["tile_rows"])
-    if mode == "rq":
-        t.form_q()
-    t.R()
-    dt = time.perf_counter() - t0
+
+    def run(X):
+        t0 = time.perf_counter()
+        t = oracle.TSQR(X, info["leaf_rows"], info["tile_rows"])
+        if mode == "rq":
+            t.form_q()
+        R = t.R()
+        return R, time.perf_counter() - t0
+
+    Ro, dt = run(As)
     fl = flops_rq(ms, n) if mode == "rq" else flops_r(ms, n)
-    return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {ms} of {m} rows (x{n}), same leaf/tile rows, "
-                      f"{'R + explicit Q' if mode == 'rq' else 'R only'}, {dt:.2f} s"}
+    m1 = min(ms, one_thread_rows)
+    oracle.set_num_threads(1)
+    try:
+        _, dt1 = run(np.asfortranarray(As[:m1]))
+    finally:
+        oracle.set_num_threads(threads)
+    fl1 = flops_rq(m1, n) if mode == "rq" else flops_r(m1, n)
+    what = "R + explicit Q" if mode == "rq" else "R only"
+    rec = {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {ms} of {m} rows (x{n}), same leaf/tile rows, {what}, {dt:.2f} s",
+           "one_thread": {"value": fl1 / dt1 / 1e9, "unit": "GFLOP/s", "cores": 1,
+                          "sample": f"first {m1} rows, {what}, {dt1:.2f} s"},
+           "host": {"nproc": os.cpu_count(), "model": cpu_model()}}
+    return rec, Ro
 
 
-def main(argv=None) -> int:
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(BATCHED))
-    ap.add_argument("--seed", type=int, default=2024)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 24)
-    ap.add_argument("--no-check", action="store_true", help="skip the accuracy check after timing")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="before warm-up, run one plain device copy of m x n doubles (8mn bytes read, "
-                         "8mn written) so that hardware byte counters can be scaled against it")
-    args = ap.parse_args(argv)
+def r_vs_oracle(R_dev, Ro) -> float:
+    """||R - R_oracle||_F / ||R_oracle||_F; both are sign-normalised (diag >= 0)."""
+    import numpy as np
 
-    if args.gpus != 1:
-        print(json.dumps({"error": "this TSQR build runs on one GPU; the multi-GPU path (one all-gather "
-                                   "of the R factors) is a design, not a build: use --gpus 1"}))
-        return 2
+    R = R_dev.cpu().numpy()
+    return float(np.linalg.norm(R - Ro) / np.linalg.norm(Ro))
 
+
+def fp64_bounds(n: int) -> dict:
+    b = 20 * n * 2.0 ** -53
+    return {"backward_error": b, "orthogonality": b, "R_vs_oracle": 1e-13}
+
+
+# the mixed path's stated bounds: backward error and orthogonality after the
+# second pass; its R against the FP64 oracle is reported (the FP32 first pass
+# limits it to about 1e-7)
+MIXED_BOUNDS = {"backward_error": 1e-6, "orthogonality": 1e-13, "R_vs_oracle": 1e-5}
+
+
+def accuracy_of(A, Q, R) -> dict:
+    """Backward error and orthogonality on the device, in FP64."""
+    import torch
+
+    m, n = A.shape
+    with torch.no_grad():
+        nA = torch.linalg.norm(A)
+        E = torch.addmm(A, Q, R, alpha=-1.0)
+        bwd = float(torch.linalg.norm(E) / nA)
+        del E
+        # Q^T Q as a sum over row blocks: one GEMM with k = m accumulates
+        # an error near sqrt(m) eps, above the orthogonality being measured
+        nb = 4096
+        while m % nb:
+            nb //= 2
+        Qb = Q.t().reshape(n, nb, m // nb).permute(1, 0, 2).contiguous()
+        G = torch.bmm(Qb, Qb.transpose(1, 2).contiguous()).sum(dim=0)
+        del Qb
+        orth = float(torch.linalg.norm(G - torch.eye(n, dtype=G.dtype, device=G.device)))
+    return {"backward_error": bwd, "orthogonality": orth}
+
+
+def oracle_r_only(A_dev, leaf_rows: int, tile_rows: int):
+    """The FP64 oracle's R of the whole matrix (host cores)."""
+    import numpy as np
+
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import oracle
+
+    As = np.asfortranarray(A_dev.cpu().numpy())
+    t0 = time.perf_counter()
+    R = oracle.TSQR(As, leaf_rows, tile_rows).R()
+    return R, time.perf_counter() - t0
+
+
+def time_steps(step, plan, steps: int, warmup: int):
+    """W untimed steps, then K timed ones bracketed by device synchronisation;
+    per-phase device times from the plan's HIP events over the timed steps."""
+    import torch
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ph = plan.timings()
+    plan.profile(False)
+    return (t1 - t0) * 1e3 / steps, ph
+
+
+def phase_means(ph: dict) -> dict:
+    return {k: (v[0] / v[1] if v[1] else 0.0) for k, v in ph.items()}
+
+
+def run_single(args, wname: str, cpu: bool, check: bool):
+    """One workload of WORKLOADS: the result record (the JSON line's fields)."""
     import torch
     from paper_0809_2407_amd import tsqr as T
 
-    if not torch.cuda.is_available():
-        print(json.dumps({"error": "no GPU"}))
-        return 1
-    if args.workload in BATCHED:
-        return run_batched(args)
-    w = dict(WORKLOADS[args.workload])
+    w = dict(WORKLOADS[wname])
     m, n, mode = w["m"], w["n"], w["mode"]
-    log(f"workload {args.workload}: generating input")
+    log(f"workload {wname}: generating input")
     A, sig = make_input(w, args.seed)
     mixed = w.get("precision", "fp64") == "mixed"
     plan = T.Plan(m, n, precision="mixed" if mixed else "fp64", leaf_rows=w.get("leaf_rows", 0),
@@ -214,20 +308,7 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         del Cdst
         log(f"calibration copy: {8 * m * n} bytes read, {8 * m * n} bytes written")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps)")
-    plan.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ph = plan.timings()
-    plan.profile(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_step, ph = time_steps(step, plan, args.steps, args.warmup)
     log(f"timed {args.steps} steps: {ms_step:.4f} ms/step; phases {ph}")
 
     fl = flops_rq(m, n) if mode == "rq" else flops_r(m, n)
@@ -245,9 +326,11 @@ def main(argv=None) -> int:
     dom_ms = ph[dom][0] / max(1, ph[dom][1])
     achieved = phase_bytes[dom] / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(m, n, dom) if mode == "rq" and not mixed else None,
-                "kernel": dom,
-                "kernel_ms": dom_ms, "bytes_per_launch": phase_bytes[dom]}
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(m, n, dom) if mode == "rq" and not mixed else None,
+                "kernel": dom, "kernel_ms": dom_ms, "bytes_per_launch": phase_bytes[dom],
+                "timing": "HIP events on the plan's stream around each launch of the kernel, "
+                          "mean over the timed steps"}
     path_bytes = (32.0 if mode == "rq" else 8.0) * m * n + (8.0 * m * n + 16.0 * m * k_rhs if k_rhs else 0.0)
     if mixed and mode == "rq":
         path_bytes = 36.0 * m * n  # the byte model of the mixed path with its Gram pass unfused
@@ -258,7 +341,7 @@ def main(argv=None) -> int:
         "value": value, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64", "data": "synthetic",
-        "config": {"workload": args.workload, "m": m, "n": n, "mode": mode,
+        "config": {"workload": wname, "m": m, "n": n, "mode": mode,
                    "sigma": None if sig is None else f"logspace(0,-{w['decades']:g},{n})",
                    "seed": args.seed, "tree": {1: "binary", 2: "flat", 3: "hybrid"}.get(info["tree"], "auto"),
                    "tile_rows": info["tile_rows"], "leaf_rows": info["leaf_rows"],
@@ -267,57 +350,108 @@ def main(argv=None) -> int:
         "roofline": roofline,
         "path_roofline": {"t_roof_ms": t_roof * 1e3, "frac": t_roof * 1e3 / ms_step,
                           "bytes": path_bytes, "flops": fl},
-        "phases_ms": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in ph.items()},
+        "phases_ms": phase_means(ph),
     }
-
-    if not args.no_check and mode == "rq":
-        with torch.no_grad():
-            nA = torch.linalg.norm(A)
-            E = torch.addmm(A, Q, R, alpha=-1.0)
-            bwd = float(torch.linalg.norm(E) / nA)
-            del E
-            # Q^T Q as a sum over row blocks: one GEMM with k = m accumulates
-            # an error near sqrt(m) eps, above the orthogonality being measured
-            nb = 4096
-            while m % nb:
-                nb //= 2
-            Qb = Q.t().reshape(n, nb, m // nb).permute(1, 0, 2).contiguous()
-            G = torch.bmm(Qb, Qb.transpose(1, 2).contiguous()).sum(dim=0)
-            del Qb
-            orth = float(torch.linalg.norm(G - torch.eye(n, dtype=G.dtype, device=G.device)))
-        result["accuracy"] = {"backward_error": bwd, "orthogonality": orth, "bound": 20 * n * 2.0 ** -53}
-        log(f"accuracy {result['accuracy']}")
-
-    if not args.no_cpu_baseline:
+    if check and mode == "rq":
+        acc = accuracy_of(A, Q, R)
+        acc["bounds"] = MIXED_BOUNDS if mixed else fp64_bounds(n)
+        result["accuracy"] = acc
+        log(f"accuracy {acc}")
+    result["cpu_baseline"] = None
+    if cpu:
         log("cpu baseline (oracle on host cores)")
-        result["cpu_baseline"] = cpu_baseline(A, info, args.cpu_sample_rows, mode)
-    else:
-        result["cpu_baseline"] = None
-
+        rec, Ro = cpu_baseline(A, info, args.cpu_sample_rows, mode)
+        result["cpu_baseline"] = rec
+        if Ro.shape[0] == n and args.cpu_sample_rows >= m:
+            result.setdefault("accuracy", {})["R_vs_oracle"] = r_vs_oracle(R, Ro)
+            log(f"R vs oracle {result['accuracy']['R_vs_oracle']:.3e}")
     plan.close()
-    print(json.dumps(result), flush=True)
-    return 0
+    del A, V, Q, R
+    torch.cuda.empty_cache()
+    return result
 
 
-def run_batched(args) -> int:
-    """One step = R and explicit Q of every problem of the batch: one replay of
-    the batched plan's factor graph and one of its Q graph.  The loop of single
-    calls does the same problems one plan at a time.  A is regenerated before
-    every step (outside the timed events: the factorisation overwrites it)."""
+def mixed_vs_fp64(args, steps: int, warmup: int) -> dict:
+    """The FP64 path and the mixed path (FP32 first pass, FP64 second pass) on
+    the same m = 2^24, n = 64 matrix (sigma 1 .. 1e-6): both times, each path's
+    accuracy against its stated bounds and R against the FP64 oracle."""
+    import torch
+    from paper_0809_2407_amd import tsqr as T
+
+    m, n, dec = 1 << 24, 64, 6.0
+    log(f"mixed vs FP64: m = {m}, n = {n}, generating input")
+    A, _ = make_input(dict(m=m, n=n, decades=dec), args.seed)
+    Q = T.colmajor(m, n)
+    out = {"workload": f"tsqr_rq_m{m}_n{n}_kappa1e6", "m": m, "n": n, "sigma": f"logspace(0,-{dec:g},{n})",
+           "seed": args.seed, "steps": steps, "warmup": warmup, "flops_credited": flops_rq(m, n)}
+    Rs = {}
+    fp64_geom = None
+    for prec in ("fp64", "mixed"):
+        plan = T.Plan(m, n, precision=prec)
+        info = plan.info()
+        V = T.colmajor(m, n) if prec == "fp64" else None
+        R = T.colmajor(n, n)
+
+        def step():
+            plan.factor_into(A, V, R)
+            plan.form_q(V, Q)
+
+        ms_step, ph = time_steps(step, plan, steps, warmup)
+        acc = accuracy_of(A, Q, R)
+        rec = {"ms_per_step": ms_step, "value": flops_rq(m, n) / (ms_step * 1e-3) / 1e9, "unit": "GFLOP/s",
+               "phases_ms": phase_means(ph), "accuracy": acc,
+               "bounds": MIXED_BOUNDS if prec == "mixed" else fp64_bounds(n),
+               "leaf_rows": info["leaf_rows"], "tile_rows": info["tile_rows"]}
+        if prec == "mixed":
+            i2 = plan.info()
+            rec["second_pass"] = {"orth_estimate": i2["orth_estimate"], "applied": bool(i2["reorth_applied"])}
+        log(f"{prec}: {ms_step:.3f} ms/step, accuracy {acc}")
+        out[prec] = rec
+        Rs[prec] = R
+        if prec == "fp64":
+            fp64_geom = (info["leaf_rows"], info["tile_rows"])
+        plan.close()
+        del V
+    if args.no_cpu_baseline:
+        out["oracle"] = None
+    else:
+        log("mixed vs FP64: the FP64 oracle's R of the whole matrix (host cores)")
+        Ro, dt = oracle_r_only(A, *fp64_geom)
+        for prec in ("fp64", "mixed"):
+            out[prec]["accuracy"]["R_vs_oracle"] = r_vs_oracle(Rs[prec], Ro)
+        out["oracle"] = {"seconds": dt, "what": "R of the whole matrix, FP64 oracle (same leaf and tile rows "
+                                                "as the FP64 plan)"}
+    out["mixed_speedup"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    for prec in ("fp64", "mixed"):
+        a, b = out[prec]["accuracy"], out[prec]["bounds"]
+        out[prec]["within_bounds"] = all(a[k] <= b[k] for k in b if k in a)
+    del A, Q, Rs
+    torch.cuda.empty_cache()
+    return out
+
+
+def batched_record(args, count: int, m_lo: int, m_hi: int, ns, precision: str, steps: int, warmup: int,
+                   loop_steps: int, sample_oracle: bool, state=None) -> dict:
+    """One batched plan (captured graph) over `count` problems, R and explicit
+    Q per step, against a loop of single calls on the same stream (loop_steps
+    > 0).  A is regenerated before every step, outside the timed events (the
+    factorisation overwrites it).  `state` carries the problems' buffers from
+    one call to the next (same problems, another precision)."""
     import numpy as np
     import torch
     from paper_0809_2407_amd import tsqr as T
 
-    w = BATCHED[args.workload]
-    rng = np.random.default_rng(args.seed)
-    ms = [int(x) for x in rng.integers(w["m_lo"], w["m_hi"] + 1, size=w["count"])]
-    ns = [int(x) for x in rng.choice(w["ns"], size=w["count"])]
-    fl = sum(flops_rq(m, n) for m, n in zip(ms, ns))
-    entries = sum(m * n for m, n in zip(ms, ns))
-    log(f"batched workload {args.workload}: {w['count']} problems, {entries * 8 / 1e9:.1f} GB per matrix set")
-    g = torch.Generator(device="cuda")
-    As = [T.colmajor(m, n) for m, n in zip(ms, ns)]
-    Qs = [T.colmajor(m, n) for m, n in zip(ms, ns)]
+    if state is None:
+        rng = np.random.default_rng(args.seed)
+        ms = [int(x) for x in rng.integers(m_lo, m_hi + 1, size=count)]
+        nn = [int(x) for x in rng.choice(ns, size=count)]
+        state = {"ms": ms, "ns": nn, "As": [T.colmajor(m, n) for m, n in zip(ms, nn)],
+                 "Qs": [T.colmajor(m, n) for m, n in zip(ms, nn)], "g": torch.Generator(device="cuda")}
+    ms, nn, As, Qs, g = state["ms"], state["ns"], state["As"], state["Qs"], state["g"]
+    fl = sum(flops_rq(m, n) for m, n in zip(ms, nn))
+    entries = sum(m * n for m, n in zip(ms, nn))
+    mixed = precision == "mixed"
+    log(f"batched {precision}: {count} problems, {entries * 8 / 1e9:.1f} GB per matrix set")
 
     def fill(A, step, i):
         g.manual_seed((args.seed * 1000 + step) * 8192 + i)
@@ -327,100 +461,161 @@ def run_batched(args) -> int:
         for i, A in enumerate(As):
             fill(A, step, i)
 
-    prec = w.get("precision", "fp64")
-    mixed = prec == "mixed"
-    bp = T.BatchedPlan(ms, ns, precision=prec)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    bp = T.BatchedPlan(ms, nn, precision=precision)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
 
     def batched_step():
         bp.factor(As)
         bp.form_q(As, Qs)
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         regenerate(i)
         batched_step()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         regenerate(100 + i)
         ev[i][0].record()
         batched_step()
         ev[i][1].record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    b_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
-    log(f"batched: {b_ms:.3f} ms/step (events), wall {wall * 1e3 / args.steps:.1f} ms/step with regeneration")
+    b_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    log(f"batched {precision}: {b_ms:.3f} ms/step (events)")
 
-    # accuracy on a sample of problems of the last step (against the regenerated input)
-    regen_check = {}
-    sample = list(range(0, w["count"], max(1, w["count"] // 16)))
-    worst_b = worst_o = 0.0
-    if not args.no_check:
-        # the sampled problems' inputs again, into fresh buffers, for the residuals
-        last = 100 + args.steps - 1
-        A0 = {}
-        for i in sample:
-            A0[i] = torch.empty_like(As[i])
-            fill(A0[i], last, i)
-        regenerate(last)
-        Rs = bp.factor(As)
-        bp.form_q(As, Qs)
-        torch.cuda.synchronize()
-        for i in sample:
-            A, Q, R = A0[i], Qs[i], Rs[i]
-            bwd = float(torch.linalg.norm(torch.addmm(A, Q, R, alpha=-1.0)) / torch.linalg.norm(A))
-            G = sum(Q[r:r + 4096].t() @ Q[r:r + 4096] for r in range(0, ms[i], 4096))  # blocked Gram
-            orth = float(torch.linalg.norm(G - torch.eye(ns[i], dtype=G.dtype, device=G.device)))
-            bb = 1e-6 if mixed else 20 * ns[i] * 2.0 ** -53  # the stated bounds of each path
-            ob = 1e-13 if mixed else 20 * ns[i] * 2.0 ** -53
-            worst_b, worst_o = max(worst_b, bwd / bb), max(worst_o, orth / ob)
-        regen_check = {"sampled_problems": len(sample), "max_backward_over_bound": worst_b,
-                       "max_orthogonality_over_bound": worst_o}
-        log(f"accuracy {regen_check}")
-        del A0
-
-    # the loop of single calls on the same problems
-    plans = [T.Plan(m, n, precision=prec) for m, n in zip(ms, ns)]
-
-    def loop_step():
-        for p, A, Q in zip(plans, As, Qs):
-            p.factor(A)
-            p.form_q(A, Q)
-
-    regenerate(0)
-    loop_step()
+    # accuracy on a sample of problems: regenerate the last step's input, keep
+    # copies of the sampled ones, factor again and check the residuals
+    sample = list(range(0, count, max(1, count // 16)))
+    last = 100 + steps - 1
+    A0 = {}
+    for i in sample:
+        A0[i] = torch.empty_like(As[i])
+        fill(A0[i], last, i)
+    regenerate(last)
+    Rs = bp.factor(As)
+    bp.form_q(As, Qs)
     torch.cuda.synchronize()
-    lev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    for i in range(args.steps):
-        regenerate(100 + i)
-        lev[i][0].record()
+    worst = {"backward_error": 0.0, "orthogonality": 0.0, "R_vs_oracle": 0.0}
+    for i in sample:
+        A, Q, R = A0[i], Qs[i], Rs[i]
+        bwd = float(torch.linalg.norm(torch.addmm(A, Q, R, alpha=-1.0)) / torch.linalg.norm(A))
+        G = sum(Q[r:r + 4096].t() @ Q[r:r + 4096] for r in range(0, ms[i], 4096))  # blocked Gram
+        orth = float(torch.linalg.norm(G - torch.eye(nn[i], dtype=G.dtype, device=G.device)))
+        b = MIXED_BOUNDS if mixed else fp64_bounds(nn[i])
+        worst["backward_error"] = max(worst["backward_error"], bwd / b["backward_error"])
+        worst["orthogonality"] = max(worst["orthogonality"], orth / b["orthogonality"])
+        if sample_oracle:
+            sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+            import oracle
+
+            Ro = oracle.qr_reference(np.asfortranarray(A.cpu().numpy()), want_q=False)
+            worst["R_vs_oracle"] = max(worst["R_vs_oracle"], r_vs_oracle(R, Ro) / b["R_vs_oracle"])
+    del A0, Rs
+    acc = {"sampled_problems": len(sample), "max_over_bound": worst,
+           "bounds": MIXED_BOUNDS if mixed else {"backward_error": "20 n 2^-53", "orthogonality": "20 n 2^-53",
+                                                 "R_vs_oracle": 1e-13}}
+    log(f"batched {precision} accuracy {acc}")
+    bp.close()
+
+    rec = {"problems": count, "precision": precision, "m_range": [m_lo, m_hi], "n_choices": list(ns),
+           "seed": args.seed, "sum_mn": entries, "flops": fl, "steps": steps, "warmup": warmup,
+           "ms_per_step": b_ms, "value": fl / (b_ms * 1e-3) / 1e9, "unit": "GFLOP/s", "accuracy": acc}
+    bytes_ = (36.0 if mixed else 32.0) * entries
+    t_roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), bytes_ / (HBM_PEAK_GBS * 1e9))
+    rec["path_roofline"] = {"t_roof_ms": t_roof * 1e3, "frac": t_roof * 1e3 / b_ms, "bytes": bytes_, "flops": fl}
+
+    if loop_steps > 0:
+        plans = [T.Plan(m, n, precision=precision) for m, n in zip(ms, nn)]
+
+        def loop_step():
+            for p, A, Q in zip(plans, As, Qs):
+                p.factor(A)
+                p.form_q(A, Q)
+
+        regenerate(0)
         loop_step()
-        lev[i][1].record()
-    torch.cuda.synchronize()
-    l_ms = sum(a.elapsed_time(b) for a, b in lev) / args.steps
-    log(f"loop of single calls: {l_ms:.3f} ms/step")
-    for p in plans:
-        p.close()
+        torch.cuda.synchronize()
+        lev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(loop_steps)]
+        for i in range(loop_steps):
+            regenerate(100 + i)
+            lev[i][0].record()
+            loop_step()
+            lev[i][1].record()
+        torch.cuda.synchronize()
+        l_ms = sum(a.elapsed_time(b) for a, b in lev) / loop_steps
+        log(f"loop of single {precision} calls: {l_ms:.3f} ms/step")
+        for p in plans:
+            p.close()
+        del plans
+        rec["loop_of_single_calls"] = {"ms_per_step": l_ms, "value": fl / (l_ms * 1e-3) / 1e9,
+                                       "steps": loop_steps, "batched_speedup": l_ms / b_ms}
+    torch.cuda.empty_cache()
+    return rec, state
 
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(BATCHED))
+    ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 24)
+    ap.add_argument("--no-check", action="store_true", help="skip the accuracy check after timing")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="the default workload only (no mixed-vs-FP64 or batched records)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="before warm-up, run one plain device copy of m x n doubles (8mn bytes read, "
+                         "8mn written) so that hardware byte counters can be scaled against it")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this TSQR build runs on one GPU; the multi-GPU path (one all-gather "
+                                   "of the R factors) is a design, not a build: use --gpus 1"}))
+        return 2
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        return 1
+    if args.workload in BATCHED:
+        return run_batched(args)
+    result = run_single(args, args.workload, cpu=not args.no_cpu_baseline, check=not args.no_check)
+    if args.workload == DEFAULT and not args.no_extras:
+        result["mixed_vs_fp64"] = mixed_vs_fp64(args, steps=min(args.steps, 10), warmup=2)
+        w = BATCHED["tsqr_batched_fp64_rq_p2048_m1000_200000_n8_64"]
+        fp64, state = batched_record(args, w["count"], w["m_lo"], w["m_hi"], w["ns"], "fp64", steps=3, warmup=1,
+                                     loop_steps=2, sample_oracle=not args.no_cpu_baseline)
+        mx, state = batched_record(args, w["count"], w["m_lo"], w["m_hi"], w["ns"], "mixed", steps=3, warmup=1,
+                                   loop_steps=0, sample_oracle=not args.no_cpu_baseline, state=state)
+        del state
+        result["batched"] = {"workload": "tsqr_batched_rq_p2048_m1000_200000_n8_64", "fp64": fp64, "mixed": mx,
+                             "mixed_vs_fp64_batched": fp64["ms_per_step"] / mx["ms_per_step"]}
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def run_batched(args) -> int:
+    """A batched workload alone: its record as the JSON line."""
+    w = BATCHED[args.workload]
+    prec = w.get("precision", "fp64")
+    rec, _ = batched_record(args, w["count"], w["m_lo"], w["m_hi"], w["ns"], prec, steps=args.steps,
+                            warmup=args.warmup, loop_steps=args.steps, sample_oracle=not args.no_cpu_baseline)
     result = {
         "metric": "TSQR R+Q GFLOP/s & % roofline; mixed/batched vs FP64 at stated backward error",
-        "value": fl / (b_ms * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": b_ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64" if mixed else "f64", "data": "synthetic",
-        "config": {"workload": args.workload, "problems": w["count"], "precision": prec, "m_range": [w["m_lo"], w["m_hi"]],
-                   "n_choices": list(w["ns"]), "seed": args.seed, "sum_mn": entries, "flops": fl,
-                   "parallelism": "single GPU"},
-        "loop_of_single_calls": {"ms_per_step": l_ms, "value": fl / (l_ms * 1e-3) / 1e9,
-                                 "batched_speedup": l_ms / b_ms},
-        "path_roofline": {"t_roof_ms": max(fl / (FP64_PEAK_TFLOPS * 1e12),
-                                           (36.0 if mixed else 32.0) * entries / (HBM_PEAK_GBS * 1e9)) * 1e3,
-                          "bytes": (36.0 if mixed else 32.0) * entries, "flops": fl},
-        "accuracy": regen_check or None,
+        "value": rec["value"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": rec["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64" if prec == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "problems": w["count"], "precision": prec,
+                   "m_range": [w["m_lo"], w["m_hi"]], "n_choices": list(w["ns"]), "seed": args.seed,
+                   "sum_mn": rec["sum_mn"], "flops": rec["flops"], "parallelism": "single GPU"},
+        "loop_of_single_calls": rec.get("loop_of_single_calls"),
+        "path_roofline": rec["path_roofline"],
+        "accuracy": rec["accuracy"],
         "roofline": None,
         "cpu_baseline": None,
     }
-    result["path_roofline"]["frac"] = result["path_roofline"]["t_roof_ms"] / b_ms
-    bp.close()
     print(json.dumps(result), flush=True)
     return 0
 

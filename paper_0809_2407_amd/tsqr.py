@@ -37,13 +37,21 @@ def to_colmajor(X: torch.Tensor, device="cuda") -> torch.Tensor:
 def _ld(X: torch.Tensor, rows: int, name: str, dtype=torch.float64) -> int:
     if X.dim() != 2 or X.dtype != dtype:
         raise ValueError(f"{name}: a 2-D {dtype} tensor is required")
-    if not X.is_cuda:
-        raise ValueError(f"{name}: a device tensor is required")
     if X.shape[0] != rows:
         raise ValueError(f"{name}: expected {rows} rows, got {X.shape[0]}")
     if X.stride(0) != 1 and X.shape[0] > 1:
         raise ValueError(f"{name}: must be column-major (stride (1, ld))")
-    return max(X.stride(1), rows) if X.shape[1] > 1 else max(rows, 1)
+    cols = X.shape[1]
+    if cols > 1 and X.stride(1) < rows:
+        # an expanded or overlapping view: the kernels would run past its storage
+        raise ValueError(f"{name}: column stride {X.stride(1)} is below the row count {rows}")
+    ld = X.stride(1) if cols > 1 else max(rows, 1)
+    need = X.storage_offset() + (cols - 1) * ld + rows if cols > 0 and rows > 0 else 0
+    if X.untyped_storage().nbytes() // X.element_size() < need:
+        raise ValueError(f"{name}: its storage holds fewer than (n-1)*ld + m elements")
+    if not X.is_cuda:
+        raise ValueError(f"{name}: a device tensor is required")
+    return ld
 
 
 def _stream_handle(stream) -> int:

@@ -177,3 +177,22 @@ def test_mixed_plan_geometry():
     # R only: no FP32 cap needed for accuracy of Q, still FP32 tiles
     r_only = T.plan_query(1 << 20, 16, precision="mixed", want_q=False)
     assert r_only["precision"] == 1
+
+
+def test_binding_rejects_views_the_kernels_would_overrun():
+    """Leading dimensions come from the tensor's strides: an expanded or
+    overlapping view (column stride below the row count) is refused before
+    any launch."""
+    import torch
+
+    from paper_0809_2407_amd.tsqr import _ld
+
+    base = torch.zeros(10, 1, dtype=torch.float64)
+    with pytest.raises(ValueError, match="column stride"):
+        _ld(base.expand(10, 3), 10, "A")
+    over = torch.zeros(40, dtype=torch.float64).as_strided((10, 3), (1, 5))
+    with pytest.raises(ValueError, match="column stride"):
+        _ld(over, 10, "A")
+    ok = torch.zeros(3, 12, dtype=torch.float64).t()[:10]  # ld 12, the last column ends at 34 < 36
+    with pytest.raises(ValueError, match="device tensor"):
+        _ld(ok, 10, "A")
