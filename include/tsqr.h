@@ -22,7 +22,7 @@
  *     prototype) is invalid (LAPACK "info" style); 1 = HIP runtime error,
  *     2 = device memory exhausted, 3 = unsupported case, 4 = call out of order
  *     (e.g. tsqr_form_q before tsqr_factor), 5 = class not in the autotune
- *     cache.
+ *     cache, 6 = size beyond the fixed scratch of tsqr_factor_r_noalloc.
  *   - NaN or Inf entries propagate; nothing checks for them.
  *   - A plan is not thread-safe.  Different plans are independent.
  *   - Householder conventions: H_j = I - tau_j v_j v_j^T with v_j(j) = 1,
@@ -302,6 +302,29 @@ tsqr_status tsqr_batched_problem_info(tsqr_batched_plan p, int index, tsqr_info*
 /* Free the batched plan (synchronises its stream first).  Freed whatever the
  * status, as for tsqr_plan_destroy.  Errors: -1 p; 1 HIP. */
 tsqr_status tsqr_batched_plan_destroy(tsqr_batched_plan p);
+
+/* ---- Allocation-free entry point ------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The FP64
+ * R-only factorisation of tsqr_factor with want_q = 0 (leaf chains, binary
+ * tree over the leaves, sign normalisation; the same kernels) without a plan:
+ * its workspace (the R factors of every tree level, the signs) lives in a
+ * fixed 64 MiB device array of the library, of which each GPU holds one copy
+ * until the process ends.  The call allocates nothing and needs no set-up;
+ * its first call on a device looks the array's address up.
+ *   m x n A (lda >= m, device) is only read; R (n x n, ldr >= n, device)
+ *   receives the sign-normalised upper-triangular factor (strictly lower part
+ *   zero).  Asynchronous on hip_stream, which must belong to the current
+ *   device.  info (host, may be NULL) receives the geometry chosen.
+ * Geometry: 16384 leaves (as R-only plans) or fewer, longer chains when their
+ * R factors would not fit the array; chains of more than 256 tiles are
+ * refused with status 6 (at 64 columns that is m above about 2^24 rows, at
+ * 32 columns about 2^27).  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other host threads) race.
+ * Errors: -1 m < 1 or m < n, -2 n < 1 (3 for n > 64), -3 A NULL, -4 lda < m,
+ * -5 R NULL, -6 ldr < n; 6 beyond the array; 1 HIP error. */
+tsqr_status tsqr_factor_r_noalloc(int64_t m, int64_t n, const double* A, int64_t lda, double* R, int64_t ldr,
+                                  void* hip_stream, tsqr_info* info);
 
 /* Static, human-readable text for a status code. */
 const char* tsqr_status_string(tsqr_status s);

@@ -48,6 +48,7 @@ EXPORTED = [
     "tsqr_version", "tsqr_mixed_q1",
     "tsqr_batched_plan_create", "tsqr_batched_factor", "tsqr_batched_form_q", "tsqr_batched_problem_info",
     "tsqr_batched_plan_destroy", "tsqr_autotune", "tsqr_tune_cache_lookup", "tsqr_tune_cache_store",
+    "tsqr_factor_r_noalloc",
 ]
 
 _lib = None
@@ -124,6 +125,8 @@ def load(path: str = LIB_PATH):
     lib.tsqr_tune_cache_store.argtypes = [ctypes.c_char_p, i64, i64, ctypes.c_int, ctypes.POINTER(TsqrOpts),
                                           ctypes.c_double]
     lib.tsqr_tune_cache_store.restype = ctypes.c_int
+    lib.tsqr_factor_r_noalloc.argtypes = [i64, i64, dp, i64, dp, i64, P, ctypes.POINTER(TsqrInfo)]
+    lib.tsqr_factor_r_noalloc.restype = ctypes.c_int
     _lib = lib
     return lib
 

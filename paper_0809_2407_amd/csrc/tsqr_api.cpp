@@ -116,6 +116,29 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
     return true;
 }
 
+bool make_layout_r_compact(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req)
+{
+    if (!make_layout(L, m, n, leaf_rows_req, 0, TSQR_TREE_AUTO, 0, false, false)) return false;
+    // the same geometry; a workspace with only what R needs: the R of every
+    // entry of every level, the signs and the root seed the root kernel writes
+    const int64_t np2 = (int64_t)L.np * L.np;
+    int64_t off = 0;
+    auto take = [&](int64_t doubles) {
+        int64_t o = off;
+        off += (doubles + 31) / 32 * 32;  // 256-byte alignment
+        return o;
+    };
+    L.off_T = 0;  // no tile factors (the R-only leaf kernel writes none)
+    for (int l = 0; l <= L.levels; ++l) {
+        L.off_R[l] = take(L.count[l] * np2);
+        L.off_S[l] = L.off_Y[l] = L.off_TN[l] = 0;  // no node factors or seeds below the root
+    }
+    L.off_S[L.levels] = take(np2);
+    L.off_D = take(L.np);
+    L.total = off;
+    return true;
+}
+
 }  // namespace tsqr
 
 struct PhaseEvent {
@@ -262,6 +285,7 @@ const char* tsqr_status_string(tsqr_status s)
     case 3: return "unsupported case";
     case 4: return "call out of order (no factorisation with reflectors in the plan)";
     case 5: return "class not in the autotune cache";
+    case 6: return "size beyond the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
     }
 }

@@ -139,6 +139,10 @@ struct BatchClass {
 // Fills the geometry.  Returns false for an unsupported shape.
 bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves,
                  bool mixed, bool want_q);
+// The geometry of an FP64 R-only factorisation with leaves of leaf_rows_req
+// rows and a workspace holding only the R factors of every tree level, the
+// signs and the root seed (L.total doubles).
+bool make_layout_r_compact(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req);
 
 // Kernel launchers (tsqr_kernels.hip).  All enqueue on `s` and return the
 // launch status.

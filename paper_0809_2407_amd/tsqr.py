@@ -290,6 +290,23 @@ def tune_cache_store(path: str, m: int, n: int, opts: dict, ms: float, precision
                                                              ctypes.byref(o), float(ms)))
 
 
+def factor_r_noalloc(A: torch.Tensor, R: Optional[torch.Tensor] = None, stream=None):
+    """tsqr_factor_r_noalloc: the FP64 R of A (only read) with no device
+    allocation by the library (its workspace is a fixed per-GPU array).
+    Returns (R, geometry dict)."""
+    lib = _lib.load()
+    m, n = A.shape
+    lda = _ld(A, m, "A")
+    if R is None:
+        R = colmajor(n, n, device=A.device)
+    ldr = _ld(R, n, "R")
+    out = TsqrInfo()
+    h = _stream_handle(stream)
+    check("tsqr_factor_r_noalloc", lib.tsqr_factor_r_noalloc(m, n, A.data_ptr(), lda, R.data_ptr(), ldr, h,
+                                                             ctypes.byref(out)))
+    return R, {f: getattr(out, f) for f, _ in TsqrInfo._fields_}
+
+
 def qr(A: torch.Tensor, **plan_kw):
     """Thin QR of a column-major device matrix: returns (Q, R); A is overwritten
     by the reflectors."""
