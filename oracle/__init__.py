@@ -24,6 +24,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tsqr_oracle.c")
+# the comparison methods of Sec. 5 (CholeskyQR, CGS, MGS) live beside it
+_SRCS = [_SRC, os.path.join(_HERE, "cmp_oracle.c")]
 _LIB = os.path.join(_HERE, "libtsqr_oracle.so")
 
 _lib = None
@@ -31,10 +33,10 @@ _lib = None
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
-               _SRC, "-o", tmp, "-lm"]
+               *_SRCS, "-o", tmp, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
     return _LIB
@@ -74,6 +76,9 @@ def _load():
     lib.orc_tree_levels.argtypes = [i64, ctypes.POINTER(i64), ctypes.c_int]
     lib.orc_tree_levels.restype = ctypes.c_int
     lib.orc_set_mutation.argtypes = [ctypes.c_int]
+    for f in ("orc_cholqr", "orc_cholqr2", "orc_cgs", "orc_mgs"):
+        getattr(lib, f).argtypes = [i64, i64, dp, i64, dp, i64, dp, i64]
+        getattr(lib, f).restype = ctypes.c_int
     lib.orc_num_threads.restype = ctypes.c_int
     lib.orc_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -240,3 +245,34 @@ class TSQR:
         Va = np.ctypeslib.as_array(V, shape=(self.n * rows,)).reshape((self.n, rows)).T.copy()
         ta = np.ctypeslib.as_array(t, shape=(self.n,)).copy()
         return Va, ta
+
+
+# ---------------------------------------------------------------- Sec. 5 competitors
+def _cmp(fn: str, A: np.ndarray):
+    A = _f64(A)
+    m, n = A.shape
+    Q = np.zeros((m, n), order="F")
+    R = np.zeros((n, n), order="F")
+    info = getattr(_load(), fn)(m, n, _p(A), _ld(A), _p(Q), m, _p(R), n)
+    return Q, R, int(info)
+
+
+def cholqr(A: np.ndarray):
+    """CholeskyQR (Sec. 5): G = A^T A = R^T R, Q = A R^{-1}.  Returns (Q, R,
+    info); info = j + 1 when the j-th Cholesky pivot is not positive."""
+    return _cmp("orc_cholqr", A)
+
+
+def cholqr2(A: np.ndarray):
+    """CholeskyQR applied to A, then to its Q; R = R2 R1.  (Q, R, info)."""
+    return _cmp("orc_cholqr2", A)
+
+
+def cgs(A: np.ndarray):
+    """Classical Gram-Schmidt (Sec. 5).  (Q, R, info); info = j + 1 on a zero norm."""
+    return _cmp("orc_cgs", A)
+
+
+def mgs(A: np.ndarray):
+    """Modified Gram-Schmidt (Sec. 5).  (Q, R, info); info = j + 1 on a zero norm."""
+    return _cmp("orc_mgs", A)

@@ -1,6 +1,8 @@
 """Pins for the CPU oracle: each test checks it against something other than
 itself -- exact rational arithmetic, closed forms, invariants the paper states,
 special inputs whose answer is known, and a library SVD for the spectrum."""
+import os
+
 import numpy as np
 import pytest
 
@@ -187,6 +189,13 @@ def test_tree_indices_worked_example():
             a, b = t.node_homes(k - 1, lev)
             assert (a, b) == (first, target)
     assert t.node_homes(1, 1) == (4, 6)
+    # the rows of the worked example as the paper prints them (golden fixture)
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tree_index_p8.txt")
+    rows = [list(map(int, ln.split())) for ln in open(golden) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 4
+    for P, k, i, first, target in rows:
+        assert P == t.num_leaves
+        assert t.node_homes(k - 1, i // 2 ** k) == (first, target)
 
 
 def test_odd_leaf_count_passes_up():
