@@ -86,12 +86,19 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
         return o;
     };
     L.off_T = take(mixed ? 0 : L.ntiles * L.nt);
+    // the T slots of every tree node, level after level in one run, so that
+    // one T-kernel launch covers them all (off_TN[1] .. + tree_nodes * nt)
+    L.tree_nodes = 0;
+    for (int l = 1; l <= L.levels; ++l) L.tree_nodes += L.count[l];
+    const int64_t tn0 = take(L.tree_nodes * L.nt);
+    int64_t node = 0;
     for (int l = 0; l <= L.levels; ++l) {
         L.off_R[l] = take(L.count[l] * np2);
         L.off_S[l] = take(L.count[l] * np2);
         if (l >= 1) {
             L.off_Y[l] = take(L.count[l] * np2);
-            L.off_TN[l] = take(L.count[l] * L.nt);
+            L.off_TN[l] = tn0 + node * L.nt;
+            node += L.count[l];
         }
     }
     L.off_D = take(L.np);

@@ -67,7 +67,8 @@ struct Layout {
     int64_t off_R[kMaxLevels + 1] = {0};    // R of every entry of a level, count[l] * np*np
     int64_t off_S[kMaxLevels + 1] = {0};    // seeds of every entry of a level, count[l] * np*np
     int64_t off_Y[kMaxLevels + 1] = {0};    // node reflectors Y1 (np x np), level >= 1
-    int64_t off_TN[kMaxLevels + 1] = {0};   // node T (packed), level >= 1
+    int64_t off_TN[kMaxLevels + 1] = {0};   // node T (packed), level >= 1; one contiguous run over the levels
+    int64_t tree_nodes = 0;                 // nodes of levels >= 1 (T slots from off_TN[1])
     int64_t off_D = 0;                      // signs, np
 
     // mixed precision (FP32 first pass, FP64 second pass)

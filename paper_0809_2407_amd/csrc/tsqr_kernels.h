@@ -161,9 +161,6 @@ __host__ __device__ constexpr int round16(int np) { return (np + 15) / 16 * 16; 
 template <int NP>
 __host__ __device__ constexpr int rpk(int r, int c) { return r * NP - r * (r + 1) / 2 + c; }
 __host__ __device__ constexpr int r_area(int np) { return (np * (np + 1) / 2 + 1) / 2 * 2; }
-// The strictly upper Gram entries G(k, j), k < j, packed by columns at
-// j(j-1)/2 + k.
-__host__ __device__ constexpr int gpk(int k, int j) { return j * (j - 1) / 2 + k; }
 // Stride (doubles) between the per-lane segments of the reflector broadcast
 // buffer: s = 2 mod 4, so that 8 or 16 segments read 16 bytes at a time hit
 // disjoint banks, and 16-byte aligned.
@@ -175,22 +172,16 @@ __host__ __device__ constexpr int vb_stride_e(int rl) { return sizeof(E) == 8 ? 
 __host__ __device__ constexpr int packed_size(int np) { return np * (np + 1) / 2; }
 // Column groups of the factor layout: 8 when NP is a multiple of 8, else 4.
 __host__ __device__ constexpr int col_groups(int np) { return np % 8 == 0 && np > 16 ? 8 : 4; }
-// The Gram area of the factor kernels (packed strictly upper G) also serves as
-// the 16-row chunk buffer of gram_mfma (16 x (np+1) doubles); R-only kernels
-// have none.
-__host__ __device__ constexpr int gram_area(int np)
-{
-    return ((np * (np - 1) / 2 > 16 * (np + 1) ? np * (np - 1) / 2 : 16 * (np + 1)) + 1) / 2 * 2;
-}
-// LDS of the blocked construction of T for 16 < np <= 32 (doubles), after the tau array
-__host__ __device__ constexpr int tb_area(int np) { return np > 16 && np <= 32 ? 32 * 33 : 0; }
-// per-wave LDS of the factor kernels: R, Gram entries (with Q), reflector broadcast, tau, T blocks
+// The Gram chunk buffer of the tree kernels with Q: 16 rows of np + 1 doubles
+// (gram_out); R-only kernels have none.
+__host__ __device__ constexpr int gram_area(int np) { return (16 * (np + 1) + 1) / 2 * 2; }
+// per-wave LDS of the tree kernels: R, Gram chunk buffer (with Q), reflector broadcast, tau
 template <typename E = double>
 __host__ __device__ constexpr int factor_lds_doubles(int np, int tile_rows, bool want_q)
 {
     return r_area(np) + (want_q ? gram_area(np) : 0) +
            ((64 / col_groups(np)) * vb_stride_e<E>(tile_rows / (64 / col_groups(np))) * (int)sizeof(E) + 7) / 8 +
-           np + (want_q ? tb_area(np) : 0);
+           np;
 }
 // Widths whose FP64 leaf factors chained tiles in 16-column panels with the
 // trailing update on the matrix cores (factor_tile_blocked), one bit per width
@@ -245,8 +236,8 @@ __host__ __device__ constexpr int tile_rows_e(int np) { return sizeof(E) == 8 ? 
 //         at Rs, column-major NP x NP): the QR of [R; A_k] with reflectors
 //         [e_j; y_j] (Alg. 2; triangle on a rectangle, Sec. 3.1).  R is updated
 //         in place, the tile is overwritten by the y_j.
-// tau_j is recorded in taus for the compact-WY factor T (see gram_mfma and
-// build_T).
+// tau_j is recorded in taus for the compact-WY factor T (see gram_out and
+// k_build_T).
 //
 // A reflector column is left unscaled in the registers while the tile is
 // factored (y = x * sc, sc[k] holds the scale of the lane's column k, 1 for a
@@ -256,7 +247,12 @@ __host__ __device__ constexpr int tile_rows_e(int np) { return sizeof(E) == 8 ? 
 // --------------------------------------------------------------------------
 // KLO, KHI: factor only the columns held in slots [KLO, KHI) and update only
 // those (a panel of the blocked factorization below); the default is the tile.
-template <int NP, int RL, int LC, bool FIRST, typename E = double, int KLO = 0, int KHI = NP / LC>
+// TRI: the tile is upper triangular (the R_b of a tree node, Sec. 3.1): rows
+// past a column are zero and stay zero, so reflector j = [e_j; y_j] has y_j
+// nonzero in rows 0 .. j only, and the column steps of block kb skip the
+// register slots of rows past its last column (eq. fact_2rs: the structured
+// QR of two stacked triangles).
+template <int NP, int RL, int LC, bool FIRST, typename E = double, int KLO = 0, int KHI = NP / LC, bool TRI = false>
 __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC], double* Rs, E* vb,
                                             double* taus, int lane)
 {
@@ -269,6 +265,8 @@ __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC
     for (int kb = KLO; kb < KHI; ++kb) {
         const int ij = (LC * kb) / LR;   // register slot of the pivot rows of this block
         const int rg0 = (LC * kb) % LR;  // lane (within a group) of the block's first pivot row
+        // TRI: the last register slot holding a row at or above this block's last column
+        const int imax = TRI ? (LC * kb + LC - 1) / LR : RL - 1;
 #pragma unroll 1
         for (int cgj = 0; cgj < LC; ++cgj) {
             const int j = LC * kb + cgj;
@@ -296,6 +294,7 @@ __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC
             double sp0 = 0.0, sp1 = 0.0;
 #pragma unroll
             for (int i = 0; i < RL; ++i) {
+                if (i > imax) continue;
                 double x = (double)a[i][kb];
                 if (FIRST && LR * i + rg <= j) x = 0.0;
                 if (i & 1) sp1 = fma(x, x, sp1);
@@ -350,6 +349,7 @@ __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC
                 E acc0 = E(0), acc1 = E(0);
 #pragma unroll
                 for (int i = 0; i < RL; ++i) {
+                    if (i > imax) continue;
                     if (i & 1) acc1 = fma(vr[i], a[i][k], acc1);
                     else acc0 = fma(vr[i], a[i][k], acc0);
                 }
@@ -369,7 +369,8 @@ __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC
                 }
                 const double tw = trailing ? tau * w : 0.0;
 #pragma unroll
-                for (int i = 0; i < RL; ++i) a[i][k] = fma(-(E)tw, vr[i], a[i][k]);
+                for (int i = 0; i < RL; ++i)
+                    if (i <= imax) a[i][k] = fma(-(E)tw, vr[i], a[i][k]);
                 if (!FIRST && rg == 0 && trailing) Rs[rpk<NP>(j, c)] = rjc - tw;
             }
             if (FIRST) {
@@ -572,38 +573,8 @@ __device__ __forceinline__ void gram_accumulate(const E (&a)[RL][NP / LC], doubl
     }
 }
 
-template <int NP, int RL, int LC, bool FIRST, typename E = double>
-__device__ __forceinline__ void gram_mfma(const E (&a)[RL][NP / LC], double* cb, double* Gs, int lane)
-{
-    constexpr int JB = round16(NP) / 16;
-    const int q = lane >> 4, p = lane & 15;
-    dbl4 acc[JB][JB];
-    gram_accumulate<NP, RL, LC, FIRST, 16, E>(a, cb, acc, lane);
-#pragma unroll
-    for (int ib = 0; ib < JB; ++ib)
-#pragma unroll
-        for (int jb = ib; jb < JB; ++jb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = 16 * ib + q + 4 * r, col = 16 * jb + p;
-                if (row < col && col < NP) Gs[gpk(row, col)] = acc[ib][jb][r];
-            }
-    __builtin_amdgcn_wave_barrier();
-}
-
 // Position of G(k, j), k < j, in the strictly upper Gram packed by rows.
 __host__ __device__ constexpr int grow(int np, int k, int j) { return k * (np - 1) - k * (k - 1) / 2 + (j - k - 1); }
-// G(k, j) in either packing (ROWS: by rows, as the leaf kernel leaves it in a
-// T slot; else by columns).
-template <int NP, bool ROWS>
-__host__ __device__ constexpr int gidx(int k, int j) { return ROWS ? grow(NP, k, j) : gpk(k, j); }
-// The column j of the e-th strictly upper entry in column order (j(j-1)/2 <= e).
-__host__ __device__ constexpr int gcol(int e)
-{
-    int j = 1;
-    while ((j + 1) * j / 2 <= e) ++j;
-    return j;
-}
 
 // The factors of a tile's T for a later construction (k_build_T): the tile's
 // T slot of np(np+1)/2 entries receives tau (np entries) followed by the
@@ -634,166 +605,6 @@ __device__ __forceinline__ void gram_out(const E (&a)[RL][NP / LC], double* cb, 
             }
 }
 
-// T of H_0 ... H_{NP-1} = I - V T V^T from the Gram entries G(c, j) = v_c^T v_j
-// (c < j) and tau: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).
-// Lane t < NP builds row t; T is written packed (column j at j(j+1)/2).
-// The recurrence with the Gram column of each step loaded in chunks of 16.
-template <int NP, typename E = double, bool ROWS = false>
-__device__ __forceinline__ void build_T_cols(const double* Gs, const double* taus, E* __restrict__ Tout, int lane)
-{
-    double tr[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) tr[j] = 0.0;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const double tj = taus[j];
-        double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll
-        for (int k = 0; k < j; ++k) {
-            if (k & 1) acc1 = fma(tr[k], Gs[gidx<NP, ROWS>(k, j)], acc1);
-            else acc0 = fma(tr[k], Gs[gidx<NP, ROWS>(k, j)], acc0);
-            // at most 16 loads of G in flight
-            if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
-        }
-        const double acc = acc0 + acc1;
-        const double v = (lane < j) ? -tj * acc : (lane == j ? tj : 0.0);
-        tr[j] = v;
-        if (lane <= j) Tout[j * (j + 1) / 2 + lane] = (E)v;
-        // keep the loads of later columns from being hoisted all at once
-        __builtin_amdgcn_sched_barrier(0);
-    }
-}
-
-template <int NP, typename E = double, bool ROWS = false>
-__device__ __forceinline__ void build_T(const double* Gs, const double* taus, E* __restrict__ Tout, int lane)
-{
-    // The packed strictly upper Gram entries lie column after column, in the
-    // order the recurrence reads them (G(0:j, j) is Gs[j(j-1)/2 ...]), so they
-    // stream in as one sequence: loaded DIST entries ahead of their use, across
-    // column boundaries, in groups of R between scheduling barriers; four
-    // accumulation chains per column.  (With ROWS the sequence is gathered from
-    // the row packing; every position is a compile-time constant.)
-    constexpr int NN = NP * (NP - 1) / 2, R = 8, DIST = 16, RING = 32;
-    auto at = [&](int e) {
-        const int j = gcol(e);
-        return Gs[gidx<NP, ROWS>(e - j * (j - 1) / 2, j)];
-    };
-    __builtin_amdgcn_sched_barrier(0);  // nothing of the recurrence mixes with the code before it
-    double tr[NP];
-    double ring[RING];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) tr[j] = 0.0;
-#pragma unroll
-    for (int e = 0; e < DIST; ++e)
-        if (e < NN) ring[e % RING] = at(e);
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < j; ++k) {
-            const int e = j * (j - 1) / 2 + k;  // position in the stream
-            if (e + DIST < NN) ring[(e + DIST) % RING] = at(e + DIST);
-            acc[k & 3] = fma(tr[k], ring[e % RING], acc[k & 3]);
-            if ((e % R) == R - 1) __builtin_amdgcn_sched_barrier(0);
-        }
-        const double tj = taus[j];
-        const double sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-        const double v = (lane < j) ? -tj * sum : (lane == j ? tj : 0.0);
-        tr[j] = v;
-        if (lane <= j) Tout[j * (j + 1) / 2 + lane] = (E)v;
-    }
-}
-
-// The same T for 16 < NP <= 32 in two 16-column blocks, T = [T11 T12; 0 T22]:
-// the diagonal blocks by the recurrence above, concurrently (lanes 0-15 build
-// the rows of T11, lanes 16-31 those of T22; chains of at most 15 steps), then
-// T12 = -T11 G12 T22 on the matrix cores (two 16x16x16 products).  Scratch
-// Tb (LDS, 1056 doubles): the diagonal Gram blocks restaged so that a lane's
-// addresses are its block's base plus constants (Gd, 2 x 256), and T11, T22
-// (stride 17, 2 x 272) for the operand layout; the f64 output layout of the
-// first product is the B operand of the second as it stands.
-template <int NP, typename E = double, bool ROWS = false>
-__device__ __forceinline__ void build_T2(const double* Gs, const double* taus, double* Tb, E* __restrict__ Tout,
-                                         int lane)
-{
-    static_assert(NP > 16 && NP <= 32, "two 16-column blocks");
-    double* Gd = Tb;         // Gd[256 b + 16 jl + kl] = G(16 b + kl, 16 b + jl), kl < jl
-    double* Td = Tb + 512;   // Td[272 b + r + 17 jl] = T(16 b + r, 16 b + jl)
-    for (int e = lane; e < 512; e += 64) {
-        const int bb = e >> 8, jl = (e >> 4) & 15, kl = e & 15, j = 16 * bb + jl;
-        Gd[e] = (kl < jl && j < NP) ? Gs[gidx<NP, ROWS>(16 * bb + kl, j)] : 0.0;
-    }
-    __builtin_amdgcn_wave_barrier();
-    const int b = (lane >> 4) & 1, r = lane & 15, R0 = 16 * b + r;
-    const bool writer = lane < 32;  // lanes 32-63 repeat the work of lanes 0-31
-    const double* gb = Gd + 256 * b;
-    const double* tb = taus + 16 * b;
-    double* td = Td + 272 * b + r;
-    E* to = Tout + R0;
-    double tr[16];
-#pragma unroll
-    for (int jl = 0; jl < 16; ++jl) tr[jl] = 0.0;
-#pragma unroll
-    for (int jl = 0; jl < 16; ++jl) {
-        const int jmax = NP - 16 * b;  // columns of this lane's block
-        const double tj = jl < jmax ? tb[jl] : 0.0;
-        double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll
-        for (int kl = 0; kl < jl; ++kl) {
-            if (kl & 1) acc1 = fma(tr[kl], gb[16 * jl + kl], acc1);
-            else acc0 = fma(tr[kl], gb[16 * jl + kl], acc0);
-        }
-        const double acc = acc0 + acc1;
-        const double v = (r < jl) ? -tj * acc : (r == jl ? tj : 0.0);
-        tr[jl] = v;
-        if (writer) {
-            td[17 * jl] = v;
-            const int j = 16 * b + jl;
-            if (jl < jmax && r <= jl) to[j * (j + 1) / 2] = (E)v;
-        }
-        // keep the loads of later columns from being hoisted all at once
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    __builtin_amdgcn_wave_barrier();  // T11 and T22 are read across lanes below
-    const int q = lane >> 4, p = lane & 15;
-    dbl4 X = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int c = 16 + 4 * s + q;  // G12(p, c - 16), T22(c - 16, p)
-        const double g = c < NP ? Gs[gidx<NP, ROWS>(p, c < NP ? c : p + 1)] : 0.0;
-        X = mfma16x16x4(g, Td[272 + (4 * s + q) + 17 * p], X);
-    }
-    dbl4 Y = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) Y = mfma16x16x4(Td[p + 17 * (4 * s + q)], X[s], Y);
-    const int col = 16 + p;
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-        const int row = q + 4 * rr;
-        if (col < NP) Tout[col * (col + 1) / 2 + row] = (E)(-Y[rr]);
-    }
-    __builtin_amdgcn_wave_barrier();  // the next tile rewrites Gs and Tb
-}
-
-// The streamed recurrence where it compiles without spilling the factor
-// kernels, the column-chunked one elsewhere.
-#ifndef TSQR_T_STREAMED_MASK
-#define TSQR_T_STREAMED_MASK 0xFBull  // widths 4, 8, 16, 20, 24, 28, 32
-#endif
-__host__ __device__ constexpr bool t_streamed(int np) { return (TSQR_T_STREAMED_MASK >> (np / 4 - 1)) & 1; }
-
-// Either construction of T for a width.
-template <int NP, typename E = double, bool ROWS = false>
-__device__ __forceinline__ void make_T(const double* Gs, const double* taus, double* Tb, E* __restrict__ Tout,
-                                       int lane)
-{
-#if defined(TSQR_T_BLOCKED)
-    if constexpr (NP > 16 && NP <= 32) build_T2<NP, E, ROWS>(Gs, taus, Tb, Tout, lane);
-    else
-#endif
-    if constexpr (t_streamed(NP)) build_T<NP, E, ROWS>(Gs, taus, Tout, lane);
-    else build_T_cols<NP, E, ROWS>(Gs, taus, Tout, lane);
-}
 // Tile load/store in the factor layout.  The per-lane part of the address
 // (row rg, column cg) is one loop-invariant offset; the rest is uniform, so the
 // compiler does not keep one address per element alive across the chain.
@@ -1123,7 +934,7 @@ __device__ __forceinline__ void tree_node(const double* __restrict__ Rin, int64_
 {
     constexpr int LC = col_groups(NP), LR = 64 / LC, KC = NP / LC;
     // the node tile holds R_b (NP rows), padded with zero rows to whole 16-row
-    // chunks of gram_mfma
+    // chunks of gram_out
     constexpr int RLN = round16(NP) / LR, NT = packed_size(NP);
     constexpr int GA = WANT_Q ? gram_area(NP) : 0;
     const int cg = lane / LR, rg = lane % LR;
@@ -1154,11 +965,12 @@ __device__ __forceinline__ void tree_node(const double* __restrict__ Rin, int64_
         }
     }
     __builtin_amdgcn_wave_barrier();
-    factor_tile<NP, RLN, LC, false>(a, sc, Rs, vb, taus, lane);
+    factor_tile<NP, RLN, LC, false, double, 0, NP / LC, true>(a, sc, Rs, vb, taus, lane);
     if (WANT_Q) {
         scale_tile<NP, RLN, LC, false>(a, sc, lane);
-        gram_mfma<NP, RLN, LC, false>(a, Gs, Gs, lane);
-        make_T<NP>(Gs, taus, taus + NP, Tnode + q * NT, lane);
+        // tau and the Gram entries of Y1 to the node's T slot; the T kernel
+        // forms T there once the tree is done (as for the leaf tiles)
+        gram_out<NP, RLN, LC, false, 16, double>(a, Gs, taus, Tnode + q * NT, lane);
         double* Y = Ynode + q * NP * NP;
 #pragma unroll
         for (int i = 0; i < RLN; ++i) {
@@ -1852,8 +1664,12 @@ __global__ void __launch_bounds__(64) k_reorth_factor(const double* __restrict__
 // consecutive rows of one column of Q.  R2^{-1} is upper triangular: output
 // block ob needs k < 16 (ob + 1) only.
 // Row blocks rb = rb0, rb0 + step, ... below rb1 of one problem.
-template <int NP>
-__device__ __forceinline__ void reorth_q_blocks(const float* __restrict__ Q1, int64_t ldq1, int64_t m, int n,
+// E: the element type of Q1 (float in the mixed path; double for the
+// CholeskyQR comparison kernels, which form Q = A R^{-1} the same way).  Each
+// 16-row block is read whole before any of its outputs is stored, so Q may be
+// Q1 itself (FP64).
+template <int NP, typename E = float>
+__device__ __forceinline__ void reorth_q_blocks(const E* __restrict__ Q1, int64_t ldq1, int64_t m, int n,
                                                 const double* __restrict__ R2inv, double* __restrict__ Q,
                                                 int64_t ldq, int64_t rb0, int64_t rb1, int64_t step, int lane)
 {
@@ -1868,8 +1684,21 @@ __device__ __forceinline__ void reorth_q_blocks(const float* __restrict__ Q1, in
     for (int64_t rb = rb0; rb < rb1; rb += step) {
         const int64_t row = 16 * rb + p;
         double x[KS];
+        if constexpr (sizeof(E) == 4) {
+            // the mixed workspace: whole tiles and round16 columns, zero-padded
 #pragma unroll
-        for (int s = 0; s < KS; ++s) x[s] = (double)Q1[row + (int64_t)(4 * s + q) * ldq1];
+            for (int s = 0; s < KS; ++s) x[s] = (double)Q1[row + (int64_t)(4 * s + q) * ldq1];
+        } else {
+            // a caller's m x n matrix: rows past m and columns past n read an
+            // element that exists, then count as zero
+            const int64_t rc = row < m ? row : m - 1;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int c = 4 * s + q, cc = c < n ? c : n - 1;
+                const double v = (double)Q1[rc + (int64_t)cc * ldq1];
+                x[s] = (row < m && c < n) ? v : 0.0;
+            }
+        }
 #pragma unroll
         for (int ob = 0; ob < JB; ++ob) {
             dbl4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -2208,6 +2037,17 @@ hipError_t build_T_np(const Layout& L, double* ws, hipStream_t s)
     return hipGetLastError();
 }
 
+// T in `count` consecutive FP64 slots holding tau and the Gram entries.
+template <int NP>
+hipError_t build_T_slots(double* slots, int64_t count, hipStream_t s)
+{
+    constexpr int waves = NP > 48 ? 1 : 4;
+    const size_t lds = (size_t)waves * BuildTLds<NP>::WS * sizeof(double);
+    allow_lds(k_build_T<NP, double>, lds);
+    hipLaunchKernelGGL((k_build_T<NP, double>), dim3(grid_for(count, waves)), dim3(64 * waves), lds, s, slots, count);
+    return hipGetLastError();
+}
+
 template <int NP>
 hipError_t tree_np(const Layout& L, double* ws, bool want_q, hipStream_t s)
 {
@@ -2228,6 +2068,8 @@ hipError_t tree_np(const Layout& L, double* ws, bool want_q, hipStream_t s)
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    // T of every tree node (the seeds and Q^T B need them, the root does not)
+    if (want_q && L.tree_nodes > 0) return build_T_slots<NP>(ws + L.off_TN[1], L.tree_nodes, s);
     return hipSuccess;
 }
 
@@ -2438,6 +2280,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     }
 }
 
+// T of the tree nodes of level l from the tau and Gram entries tree_node left
+// in their slots (the arithmetic of k_build_T); one wavefront per (problem,
+// node) item.  A pass-through node's slot holds nothing of use and its T is
+// never read.
+template <int NP>
+__global__ void __launch_bounds__(256) k_build_T_nodes_batch(const BatchProblem* __restrict__ probs, double* ws,
+                                                             const int64_t* __restrict__ items, int64_t nitems,
+                                                             int l)
+{
+    constexpr int NT = packed_size(NP);
+    extern __shared__ double smem[];
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    double* W = smem + wave * BuildTLds<NP>::WS;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; it < nitems; it += nw) {
+        const int64_t item = items[it];
+        const int64_t p = item >> 32, q = item & 0xffffffff;
+        const BatchProblem& B = probs[p];
+        build_T_slot<NP, double>(ws + B.ws_off + B.off_TN[l] + q * NT, W, lane);
+    }
+}
+
 // Grid of a persistent batched launch: enough waves to fill the device at two
 // per SIMD, never more than there are items.
 inline unsigned batch_grid(int64_t items, int waves)
@@ -2445,6 +2309,22 @@ inline unsigned batch_grid(int64_t items, int waves)
     const int64_t cap = 256 * 8 / waves;  // 256 CUs, 8 waves each
     const int64_t need = (items + waves - 1) / waves;
     return (unsigned)(need < cap ? (need > 0 ? need : 1) : cap);
+}
+
+// T of every tree node of every problem of a class, level by level.
+template <int NP>
+hipError_t batch_node_T(const BatchClass& C, const BatchProblem* probs, double* ws, hipStream_t s)
+{
+    constexpr int waves = 4;
+    const size_t lds = (size_t)waves * BuildTLds<NP>::WS * sizeof(double);
+    allow_lds(k_build_T_nodes_batch<NP>, lds);
+    for (int l = 1; l <= C.max_levels; ++l) {
+        hipLaunchKernelGGL((k_build_T_nodes_batch<NP>), dim3(batch_grid(C.n_level[l], waves)), dim3(64 * waves), lds,
+                           s, probs, ws, C.level_items[l], C.n_level[l], l);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int NP>
@@ -2483,6 +2363,10 @@ hipError_t batch_factor_np(const BatchClass& C, const BatchProblem* probs, const
             hipLaunchKernelGGL((k_tree_batch<NP, false>), grid, block, tlds, s, probs, ws, C.level_items[l], C.n_level[l], l);
         }
         hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (want_q) {
+        hipError_t e = batch_node_T<NP>(C, probs, ws, s);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_root_batch<NP>), dim3(batch_grid(C.nprob, 4)), dim3(256), 0, s, probs, args, ws,
@@ -2733,6 +2617,10 @@ hipError_t batch_factor_mixed_np(const BatchClass& C, const BatchProblem* probs,
             hipLaunchKernelGGL((k_tree_batch<NP, false>), grid, block, tlds, s, probs, ws, C.level_items[l], C.n_level[l], l);
         }
         e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (want_q) {
+        e = batch_node_T<NP>(C, probs, ws, s);
         if (e != hipSuccess) return e;
     }
     if (!want_q) {
