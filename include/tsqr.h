@@ -303,6 +303,120 @@ tsqr_status tsqr_batched_problem_info(tsqr_batched_plan p, int index, tsqr_info*
  * status, as for tsqr_plan_destroy.  Errors: -1 p; 1 HIP. */
 tsqr_status tsqr_batched_plan_destroy(tsqr_batched_plan p);
 
+/* ---- Out-of-HBM TSQR ---------------------------------------------------------
+ * A matrix that lives in HOST memory, factored by streaming it through the
+ * GPU in blocks of block_rows rows: the out-of-DRAM sequential TSQR of
+ * Sec. 7.1 (Alg. 2) one level up the memory hierarchy, with HBM as the fast
+ * memory.  A flat tree over the blocks: R_0 from A_0, then R_k =
+ * qr([R_{k-1}; A_k]), each stacked block factored on the device by this
+ * library's TSQR (R only).  Two device buffers of (n + block_rows) x n
+ * doubles: block k + 1 is copied in on a copy stream of the plan's own while
+ * block k is factored on hip_stream.  A last block of fewer than n rows joins
+ * the one before it.  block_rows = 0 chooses blocks of about 1 GiB. */
+typedef struct tsqr_stream_plan_s* tsqr_stream_plan;
+
+/* Errors: -1 p NULL, -2 m < 1 or m < n, -3 n < 1 (3 for n > 64), -4
+ * 0 < block_rows < n; 2 out of device memory. */
+tsqr_status tsqr_stream_plan_create(tsqr_stream_plan* p, int64_t m, int64_t n, int64_t block_rows,
+                                    void* hip_stream);
+
+/* R (n x n, ldr >= n, DEVICE memory, sign-normalised upper triangular) of A
+ * (m x n, lda >= m, HOST memory, only read; pinned memory lets the copies run
+ * asynchronously, pageable memory is copied through staging buffers).
+ * Asynchronous on hip_stream: A must stay valid until the stream has passed
+ * the call.  Errors: -1 p, -2 A NULL, -3 lda < m, -4 R NULL, -5 ldr < n. */
+tsqr_status tsqr_stream_factor(tsqr_stream_plan p, const double* A, int64_t lda, double* R, int64_t ldr);
+
+/* The rows per block and the block count the plan uses.  Errors: -1 p,
+ * -2 block_rows NULL, -3 nblocks NULL. */
+tsqr_status tsqr_stream_plan_info(tsqr_stream_plan p, int64_t* block_rows, int64_t* nblocks);
+
+/* Free the plan (synchronises its streams).  Errors: -1 p; 1 HIP error. */
+tsqr_status tsqr_stream_plan_destroy(tsqr_stream_plan p);
+
+/* ---- CAQR: general m x n matrices (Sec. 6, Alg. 3) ---------------------------
+ * The QR factorization of an m x n matrix (m >= n, any n) by panels of
+ * `panel` columns (at most 64; 0 = 32), right-looking: panel j (the active
+ * rows jb .. m-1) is factored by TSQR, then Q_j^T -- the leaf updates and the
+ * updates up the panel's reduction tree (Sec. 3.2) -- is applied to the
+ * trailing columns, whose top rows become R's row block and whose other rows
+ * are the next active matrix.  One TSQR plan per panel (created here).  Q
+ * stays implicit: the reflectors overwrite A panel by panel, the trees stay
+ * in the plan; tsqr_caqr_apply_qt applies Q^T. */
+typedef struct tsqr_caqr_plan_s* tsqr_caqr_plan;
+
+/* Errors: -1 p NULL, -2 m < 1 or m < n, -3 n < 1, -4 panel < 0 or > 64;
+ * 2 out of memory. */
+tsqr_status tsqr_caqr_plan_create(tsqr_caqr_plan* p, int64_t m, int64_t n, int64_t panel, void* hip_stream);
+
+/* Factor A (m x n, lda >= m, device; overwritten by the panels' reflectors
+ * and, above them, R's row blocks) and write R (n x n, ldr >= n, device:
+ * upper triangular, diag >= 0, strictly lower part zero).  Asynchronous.
+ * Errors: -1 p, -2 A NULL, -3 lda < m, -4 R NULL, -5 ldr < n. */
+tsqr_status tsqr_caqr_factor(tsqr_caqr_plan p, double* A, int64_t lda, double* R, int64_t ldr);
+
+/* B (m x k, ldb >= m, device) <- Q^T B in place, Q = Q_0 diag(I, Q_1) ... the
+ * orthogonal factor of the last tsqr_caqr_factor (A_factored its output).
+ * Rows 0..n-1 become D Q_thin^T B (D the signs that made diag(R) >= 0); the
+ * others hold coordinates in the panels' bases of the complement.  k = 0
+ * returns at once.  Errors: -1 p, -2 A NULL, -3 lda < m, -4 k < 0, -5 B NULL,
+ * -6 ldb < m; 4 before a factorisation. */
+tsqr_status tsqr_caqr_apply_qt(tsqr_caqr_plan p, const double* A_factored, int64_t lda, int64_t k, double* B,
+                               int64_t ldb);
+
+/* The panel width and the number of panels.  Errors: -1 p, -2 / -3 NULL. */
+tsqr_status tsqr_caqr_plan_info(tsqr_caqr_plan p, int64_t* panel, int64_t* npanels);
+
+/* Free the plan and its panel plans (synchronises the stream).  Errors: -1 p; 1 HIP. */
+tsqr_status tsqr_caqr_plan_destroy(tsqr_caqr_plan p);
+
+/* ---- Comparison methods (Sec. 5) ----------------------------------------------
+ * TSQR's competitors, for the stability and cost contrast the paper draws:
+ *   CHOLQR   CholeskyQR: G = A^T A, G = R^T R (Cholesky), Q = A R^{-1}; one
+ *            reduction, but the orthogonality of Q degrades with kappa(A)^2
+ *            and the factorisation breaks down once kappa(A)^2 eps ~ 1;
+ *   CHOLQR2  CholeskyQR applied to A and then to its Q, R = R2 R1 (not in the
+ *            paper: the usual repair of CholeskyQR, orthogonal to working
+ *            precision while kappa(A)^2 eps < 1);
+ *   CGS      classical Gram-Schmidt: r_ij = q_i^T a_j (i < j), q_j = the
+ *            normalised a_j - sum r_ij q_i;
+ *   MGS      modified Gram-Schmidt: q_j = v_j / ||v_j||, then
+ *            v_k -= (q_j^T v_k) q_j for every later k (loss of orthogonality
+ *            about kappa eps).
+ * All FP64 and without pivoting.  Q (m x n, ldq >= m) is explicit and may
+ * alias A (same leading dimension: A is then overwritten); R (n x n,
+ * ldr >= n) is upper triangular with a positive diagonal.  A breakdown (a
+ * Cholesky pivot that is not positive; a zero norm in Gram-Schmidt) is
+ * recorded on the device, Q and R are then not meaningful, and
+ * tsqr_cmp_breakdown reports it.  Plans own their workspace (hipMalloc in
+ * create, hipFree in destroy) and are bound to (m, n, method, stream). */
+typedef enum {
+    TSQR_CMP_CHOLQR = 0,
+    TSQR_CMP_CHOLQR2 = 1,
+    TSQR_CMP_CGS = 2,
+    TSQR_CMP_MGS = 3
+} tsqr_cmp_method;
+
+typedef struct tsqr_cmp_plan_s* tsqr_cmp_plan;
+
+/* Errors: -1 p NULL, -2 m < 1 or m < n, -3 n < 1 (3 for n > 64), -4 bad
+ * method; 2 out of memory. */
+tsqr_status tsqr_cmp_plan_create(tsqr_cmp_plan* p, int64_t m, int64_t n, tsqr_cmp_method method, void* hip_stream);
+
+/* Q and R of A (m x n, lda >= m) by the plan's method; asynchronous.
+ * Errors: -1 p, -2 A NULL, -3 lda < m, -4 Q NULL, -5 ldq < m or Q == A with
+ * ldq != lda, -6 R NULL, -7 ldr < n. */
+tsqr_status tsqr_cmp_factor(tsqr_cmp_plan p, const double* A, int64_t lda, double* Q, int64_t ldq, double* R,
+                            int64_t ldr);
+
+/* The breakdown of the last tsqr_cmp_factor: *column = 0 when none, else
+ * j + 1 for the first column j where the method broke down (synchronises
+ * the plan's stream).  Errors: -1 p, -2 column NULL; 1 HIP error. */
+tsqr_status tsqr_cmp_breakdown(tsqr_cmp_plan p, int* column);
+
+/* Free the plan (synchronises its stream).  Errors: -1 p; 1 HIP error. */
+tsqr_status tsqr_cmp_plan_destroy(tsqr_cmp_plan p);
+
 /* ---- Allocation-free entry point ------------------------------------------
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  The FP64

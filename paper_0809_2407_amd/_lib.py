@@ -10,6 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtsqr.so")
 
 TSQR_FP64, TSQR_MIXED = 0, 1
+TSQR_CMP_CHOLQR, TSQR_CMP_CHOLQR2, TSQR_CMP_CGS, TSQR_CMP_MGS = 0, 1, 2, 3
 TSQR_TREE_AUTO, TSQR_TREE_BINARY, TSQR_TREE_FLAT, TSQR_TREE_HYBRID = 0, 1, 2, 3
 
 i64 = ctypes.c_int64
@@ -49,6 +50,10 @@ EXPORTED = [
     "tsqr_batched_plan_create", "tsqr_batched_factor", "tsqr_batched_form_q", "tsqr_batched_problem_info",
     "tsqr_batched_plan_destroy", "tsqr_autotune", "tsqr_tune_cache_lookup", "tsqr_tune_cache_store",
     "tsqr_factor_r_noalloc",
+    "tsqr_cmp_plan_create", "tsqr_cmp_factor", "tsqr_cmp_breakdown", "tsqr_cmp_plan_destroy",
+    "tsqr_stream_plan_create", "tsqr_stream_factor", "tsqr_stream_plan_info", "tsqr_stream_plan_destroy",
+    "tsqr_caqr_plan_create", "tsqr_caqr_factor", "tsqr_caqr_apply_qt", "tsqr_caqr_plan_info",
+    "tsqr_caqr_plan_destroy",
 ]
 
 _lib = None
@@ -125,6 +130,32 @@ def load(path: str = LIB_PATH):
     lib.tsqr_tune_cache_store.argtypes = [ctypes.c_char_p, i64, i64, ctypes.c_int, ctypes.POINTER(TsqrOpts),
                                           ctypes.c_double]
     lib.tsqr_tune_cache_store.restype = ctypes.c_int
+    lib.tsqr_cmp_plan_create.argtypes = [ctypes.POINTER(P), i64, i64, ctypes.c_int, P]
+    lib.tsqr_cmp_plan_create.restype = ctypes.c_int
+    lib.tsqr_cmp_factor.argtypes = [P, dp, i64, dp, i64, dp, i64]
+    lib.tsqr_cmp_factor.restype = ctypes.c_int
+    lib.tsqr_cmp_breakdown.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
+    lib.tsqr_cmp_breakdown.restype = ctypes.c_int
+    lib.tsqr_cmp_plan_destroy.argtypes = [P]
+    lib.tsqr_cmp_plan_destroy.restype = ctypes.c_int
+    lib.tsqr_stream_plan_create.argtypes = [ctypes.POINTER(P), i64, i64, i64, P]
+    lib.tsqr_stream_plan_create.restype = ctypes.c_int
+    lib.tsqr_stream_factor.argtypes = [P, dp, i64, dp, i64]
+    lib.tsqr_stream_factor.restype = ctypes.c_int
+    lib.tsqr_stream_plan_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.tsqr_stream_plan_info.restype = ctypes.c_int
+    lib.tsqr_stream_plan_destroy.argtypes = [P]
+    lib.tsqr_stream_plan_destroy.restype = ctypes.c_int
+    lib.tsqr_caqr_plan_create.argtypes = [ctypes.POINTER(P), i64, i64, i64, P]
+    lib.tsqr_caqr_plan_create.restype = ctypes.c_int
+    lib.tsqr_caqr_factor.argtypes = [P, dp, i64, dp, i64]
+    lib.tsqr_caqr_factor.restype = ctypes.c_int
+    lib.tsqr_caqr_apply_qt.argtypes = [P, dp, i64, i64, dp, i64]
+    lib.tsqr_caqr_apply_qt.restype = ctypes.c_int
+    lib.tsqr_caqr_plan_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.tsqr_caqr_plan_info.restype = ctypes.c_int
+    lib.tsqr_caqr_plan_destroy.argtypes = [P]
+    lib.tsqr_caqr_plan_destroy.restype = ctypes.c_int
     lib.tsqr_factor_r_noalloc.argtypes = [i64, i64, dp, i64, dp, i64, P, ctypes.POINTER(TsqrInfo)]
     lib.tsqr_factor_r_noalloc.restype = ctypes.c_int
     _lib = lib

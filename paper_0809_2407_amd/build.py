@@ -22,7 +22,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtsqr.so")
 
 UNITS = ["tsqr_np_0.hip", "tsqr_np_1.hip", "tsqr_np_2.hip", "tsqr_np_3.hip",
-         "tsqr_dispatch.hip", "tsqr_noalloc.hip", "tsqr_api.cpp", "tsqr_batched.cpp", "tsqr_tune.cpp"]
+         "tsqr_dispatch.hip", "tsqr_noalloc.hip", "tsqr_cmp.hip", "tsqr_api.cpp", "tsqr_batched.cpp",
+         "tsqr_tune.cpp", "tsqr_stream.cpp", "tsqr_caqr.hip"]
 
 ARCH = "gfx950"
 COMMON = [

@@ -290,6 +290,168 @@ def tune_cache_store(path: str, m: int, n: int, opts: dict, ms: float, precision
                                                              ctypes.byref(o), float(ms)))
 
 
+class StreamPlan:
+    """tsqr_stream_plan_create / tsqr_stream_factor / tsqr_stream_plan_info /
+    tsqr_stream_plan_destroy: the R of an m x n matrix held in host memory,
+    streamed through the GPU in blocks (the out-of-DRAM flat tree of Sec. 7.1)."""
+
+    def __init__(self, m: int, n: int, block_rows: int = 0, stream=None):
+        self._lib = _lib.load()
+        self.m, self.n = int(m), int(n)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        check("tsqr_stream_plan_create", self._lib.tsqr_stream_plan_create(ctypes.byref(h), self.m, self.n,
+                                                                           int(block_rows),
+                                                                           _stream_handle(self.stream)))
+        self._h = h
+
+    def info(self) -> dict:
+        b, k = ctypes.c_int64(0), ctypes.c_int64(0)
+        check("tsqr_stream_plan_info", self._lib.tsqr_stream_plan_info(self._h, ctypes.byref(b), ctypes.byref(k)))
+        return {"block_rows": int(b.value), "num_blocks": int(k.value)}
+
+    def factor(self, A: torch.Tensor, R: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """R (on the device) of A, a column-major float64 tensor in host memory."""
+        if A.is_cuda or A.dim() != 2 or A.dtype != torch.float64 or A.shape[0] != self.m or A.shape[1] != self.n:
+            raise ValueError("A: an m x n float64 host tensor is required")
+        if A.stride(0) != 1 and self.m > 1:
+            raise ValueError("A: must be column-major (stride (1, ld))")
+        lda = A.stride(1) if self.n > 1 else self.m
+        if self.n > 1 and lda < self.m:
+            raise ValueError("A: column stride below the row count")
+        if R is None:
+            R = colmajor(self.n, self.n)
+        ldr = _ld(R, self.n, "R")
+        check("tsqr_stream_factor", self._lib.tsqr_stream_factor(self._h, A.data_ptr(), lda, R.data_ptr(), ldr))
+        return R
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h is not None and h.value:
+            check("tsqr_stream_plan_destroy", self._lib.tsqr_stream_plan_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class CaqrPlan:
+    """tsqr_caqr_plan_create / tsqr_caqr_factor / tsqr_caqr_apply_qt /
+    tsqr_caqr_plan_info / tsqr_caqr_plan_destroy: CAQR of an m x n matrix
+    (Sec. 6) with TSQR panels of `panel` columns."""
+
+    def __init__(self, m: int, n: int, panel: int = 0, stream=None):
+        self._lib = _lib.load()
+        self.m, self.n = int(m), int(n)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        check("tsqr_caqr_plan_create", self._lib.tsqr_caqr_plan_create(ctypes.byref(h), self.m, self.n, int(panel),
+                                                                       _stream_handle(self.stream)))
+        self._h = h
+
+    def info(self) -> dict:
+        b, k = ctypes.c_int64(0), ctypes.c_int64(0)
+        check("tsqr_caqr_plan_info", self._lib.tsqr_caqr_plan_info(self._h, ctypes.byref(b), ctypes.byref(k)))
+        return {"panel": int(b.value), "num_panels": int(k.value)}
+
+    def factor(self, A: torch.Tensor, R: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Factor A in place (reflectors and R's row blocks); returns R."""
+        lda = _ld(A, self.m, "A")
+        if R is None:
+            R = colmajor(self.n, self.n, device=A.device)
+        ldr = _ld(R, self.n, "R")
+        check("tsqr_caqr_factor", self._lib.tsqr_caqr_factor(self._h, A.data_ptr(), lda, R.data_ptr(), ldr))
+        return R
+
+    def apply_qt(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
+        lda = _ld(A, self.m, "A")
+        ldb = _ld(B, self.m, "B")
+        check("tsqr_caqr_apply_qt", self._lib.tsqr_caqr_apply_qt(self._h, A.data_ptr(), lda, B.shape[1],
+                                                                 B.data_ptr(), ldb))
+        return B
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h is not None and h.value:
+            check("tsqr_caqr_plan_destroy", self._lib.tsqr_caqr_plan_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+_CMP = {"cholqr": 0, "cholqr2": 1, "cgs": 2, "mgs": 3}
+
+
+class CmpPlan:
+    """tsqr_cmp_plan_create / tsqr_cmp_factor / tsqr_cmp_breakdown /
+    tsqr_cmp_plan_destroy: one of TSQR's competitors of Sec. 5 (method
+    "cholqr", "cholqr2", "cgs" or "mgs") for m x n problems."""
+
+    def __init__(self, m: int, n: int, method: str, stream=None):
+        self._lib = _lib.load()
+        self.m, self.n, self.method = int(m), int(n), method
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        check("tsqr_cmp_plan_create", self._lib.tsqr_cmp_plan_create(ctypes.byref(h), self.m, self.n, _CMP[method],
+                                                                     _stream_handle(self.stream)))
+        self._h = h
+
+    def factor(self, A: torch.Tensor, Q: Optional[torch.Tensor] = None, R: Optional[torch.Tensor] = None):
+        """Q (may be A itself) and R of A; returns (Q, R)."""
+        lda = _ld(A, self.m, "A")
+        if Q is None:
+            Q = colmajor(self.m, self.n, device=A.device)
+        if R is None:
+            R = colmajor(self.n, self.n, device=A.device)
+        ldq, ldr = _ld(Q, self.m, "Q"), _ld(R, self.n, "R")
+        check("tsqr_cmp_factor", self._lib.tsqr_cmp_factor(self._h, A.data_ptr(), lda, Q.data_ptr(), ldq,
+                                                           R.data_ptr(), ldr))
+        return Q, R
+
+    def breakdown(self) -> int:
+        """0, or j + 1 for the first column j where the method broke down."""
+        c = ctypes.c_int(0)
+        check("tsqr_cmp_breakdown", self._lib.tsqr_cmp_breakdown(self._h, ctypes.byref(c)))
+        return int(c.value)
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h is not None and h.value:
+            check("tsqr_cmp_plan_destroy", self._lib.tsqr_cmp_plan_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 def factor_r_noalloc(A: torch.Tensor, R: Optional[torch.Tensor] = None, stream=None):
     """tsqr_factor_r_noalloc: the FP64 R of A (only read) with no device
     allocation by the library (its workspace is a fixed per-GPU array).

@@ -196,3 +196,41 @@ def test_binding_rejects_views_the_kernels_would_overrun():
     ok = torch.zeros(3, 12, dtype=torch.float64).t()[:10]  # ld 12, the last column ends at 34 < 36
     with pytest.raises(ValueError, match="device tensor"):
         _ld(ok, 10, "A")
+
+
+def test_comparison_and_streamed_plans_reject_arguments_without_device():
+    """The Sec. 5 comparison plans and the out-of-HBM plans check their
+    arguments before any device call."""
+    from paper_0809_2407_amd import _lib
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.tsqr_cmp_plan_create(None, 100, 4, 0, None) == -1
+    assert lib.tsqr_cmp_plan_create(ctypes.byref(h), 3, 4, 0, None) == -2
+    assert lib.tsqr_cmp_plan_create(ctypes.byref(h), 100, 0, 0, None) == -3
+    assert lib.tsqr_cmp_plan_create(ctypes.byref(h), 100, 65, 0, None) == 3
+    assert lib.tsqr_cmp_plan_create(ctypes.byref(h), 100, 4, 9, None) == -4
+    assert lib.tsqr_cmp_factor(None, 1, 1, 1, 1, 1, 1) == -1
+    assert lib.tsqr_cmp_breakdown(None, None) == -1
+    assert lib.tsqr_cmp_plan_destroy(None) == -1
+    assert lib.tsqr_stream_plan_create(None, 100, 4, 0, None) == -1
+    assert lib.tsqr_stream_plan_create(ctypes.byref(h), 3, 4, 0, None) == -2
+    assert lib.tsqr_stream_plan_create(ctypes.byref(h), 100, 0, 0, None) == -3
+    assert lib.tsqr_stream_plan_create(ctypes.byref(h), 100, 65, 0, None) == 3
+    assert lib.tsqr_stream_plan_create(ctypes.byref(h), 100, 8, 5, None) == -4  # blocks below n rows
+    assert lib.tsqr_stream_factor(None, 1, 1, 1, 1) == -1
+    assert lib.tsqr_stream_plan_info(None, None, None) == -1
+    assert lib.tsqr_stream_plan_destroy(None) == -1
+
+
+def test_caqr_plans_reject_arguments_without_device():
+    from paper_0809_2407_amd import _lib
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.tsqr_caqr_plan_create(None, 100, 4, 0, None) == -1
+    assert lib.tsqr_caqr_plan_create(ctypes.byref(h), 3, 4, 0, None) == -2
+    assert lib.tsqr_caqr_plan_create(ctypes.byref(h), 100, 0, 0, None) == -3
+    assert lib.tsqr_caqr_plan_create(ctypes.byref(h), 100, 4, 65, None) == -4
+    assert lib.tsqr_caqr_factor(None, 1, 1, 1, 1) == -1
+    assert lib.tsqr_caqr_apply_qt(None, 1, 1, 1, 1, 1) == -1
+    assert lib.tsqr_caqr_plan_info(None, None, None) == -1
+    assert lib.tsqr_caqr_plan_destroy(None) == -1
