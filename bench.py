@@ -281,7 +281,7 @@ def run_single(args, wname: str, cpu: bool, check: bool):
     A, sig = make_input(w, args.seed)
     mixed = w.get("precision", "fp64") == "mixed"
     plan = T.Plan(m, n, precision="mixed" if mixed else "fp64", leaf_rows=w.get("leaf_rows", 0),
-                  want_q=(mode == "rq"))
+                  want_q=(mode == "rq"), leaf_kind=args.leaf_kind)
     info = plan.info()
     log(f"plan: {info}")
     V = T.colmajor(m, n) if mode == "rq" and not mixed else None
@@ -346,7 +346,7 @@ def run_single(args, wname: str, cpu: bool, check: bool):
                    "seed": args.seed, "tree": {1: "binary", 2: "flat", 3: "hybrid"}.get(info["tree"], "auto"),
                    "tile_rows": info["tile_rows"], "leaf_rows": info["leaf_rows"],
                    "num_leaves": info["num_leaves"], "tree_levels": info["tree_levels"],
-                   "parallelism": "single GPU"},
+                   "leaf_kind": info["leaf_kind"], "parallelism": "single GPU"},
         "roofline": roofline,
         "path_roofline": {"t_roof_ms": t_roof * 1e3, "frac": t_roof * 1e3 / ms_step,
                           "bytes": path_bytes, "flops": fl},
@@ -564,6 +564,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-check", action="store_true", help="skip the accuracy check after timing")
     ap.add_argument("--no-extras", action="store_true",
                     help="the default workload only (no mixed-vs-FP64 or batched records)")
+    ap.add_argument("--leaf-kind", default="auto", choices=["auto", "compact_wy", "recursive"],
+                    help="local QR of the leaf tiles (single-problem workloads)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="before warm-up, run one plain device copy of m x n doubles (8mn bytes read, "
                          "8mn written) so that hardware byte counters can be scaled against it")

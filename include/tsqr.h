@@ -68,6 +68,23 @@ typedef enum {
     TSQR_TREE_HYBRID = 3
 } tsqr_tree;
 
+/* Local QR of the leaf tiles (Sec. 3.1; Sec. 7 names both variants):
+ * COMPACT_WY = a tile is factored column by column (in 16-column panels whose
+ *   compact-WY update runs on the matrix cores, where the width allows) and a
+ *   second kernel forms each tile's T from tau and the tile's Gram;
+ * RECURSIVE = Elmroth and Gustavson's recursive QR: the columns are halved down
+ *   to 16-column blocks and each tile's T = [T_L, -T_L Y_L^T Y_R T_R; 0, T_R] is
+ *   assembled inside the leaf kernel (FP64 with Q at padded widths 16 and 32;
+ *   elsewhere it is status -5 at plan creation);
+ * AUTO = COMPACT_WY (at m = 2^24, n = 32 the two take the same time: the
+ *   recursive leaf is slower by what its T assembly costs, the tree beside no
+ *   concurrent T kernel faster by about as much). */
+typedef enum {
+    TSQR_LEAF_AUTO = 0,
+    TSQR_LEAF_COMPACT_WY = 1,
+    TSQR_LEAF_RECURSIVE = 2
+} tsqr_leaf_kind;
+
 /* Plan options; a zero field means "choose automatically".
  *   tree       tree shape
  *   leaf_rows  rows per leaf (block row); rounded up to a multiple of tile_rows
@@ -78,7 +95,9 @@ typedef enum {
  *   waves      wavefronts per workgroup (1, 2 or 4)
  *   want_q     1 (default when opts == NULL): tsqr_factor keeps the reflectors
  *              in A for later tsqr_form_q / tsqr_apply_qt calls;
- *              0: R only, A is not written. */
+ *              0: R only, A is not written.
+ *   leaf_kind  local QR of the leaf tiles (tsqr_leaf_kind); without Q, or on a
+ *              MIXED plan, the variants coincide and it is ignored. */
 typedef struct {
     tsqr_tree tree;
     int64_t leaf_rows;
@@ -86,6 +105,7 @@ typedef struct {
     int flat_len;
     int waves;
     int want_q;
+    tsqr_leaf_kind leaf_kind;
 } tsqr_opts;
 
 /* What the plan chose, and (MIXED) what the second pass measured. */
@@ -103,6 +123,7 @@ typedef struct {
     int64_t workspace_bytes; /* device memory the plan owns */
     int reorth_applied;      /* MIXED: 1 when the second pass corrected Q and R */
     double orth_estimate;    /* MIXED: ||R2^T R2 - I||_F of the second pass */
+    tsqr_leaf_kind leaf_kind; /* the leaf variant that runs (COMPACT_WY or RECURSIVE) */
 } tsqr_info;
 
 typedef struct tsqr_plan_s* tsqr_plan;
@@ -268,7 +289,8 @@ tsqr_status tsqr_tune_cache_store(const char* cache_path, int64_t m, int64_t n, 
  * (FP32 first pass, FP64 second pass per problem inside the same graphs) with
  * the results of single MIXED plans; tsqr_batched_problem_info then reports
  * each problem's check (and synchronises the plan's stream).  opts apply to
- * every problem (tile_rows must be 0). */
+ * every problem (tile_rows must be 0; the batched kernels run the compact-WY
+ * leaf, so leaf_kind must be AUTO or COMPACT_WY). */
 typedef struct tsqr_batched_plan_s* tsqr_batched_plan;
 
 /* count problems with sizes m[i] x n[i] (host arrays).  Errors: -1 p NULL,

@@ -19,7 +19,8 @@ dp = ctypes.c_void_p  # device pointers travel as plain addresses
 
 class TsqrOpts(ctypes.Structure):
     _fields_ = [("tree", ctypes.c_int), ("leaf_rows", i64), ("tile_rows", i64),
-                ("flat_len", ctypes.c_int), ("waves", ctypes.c_int), ("want_q", ctypes.c_int)]
+                ("flat_len", ctypes.c_int), ("waves", ctypes.c_int), ("want_q", ctypes.c_int),
+                ("leaf_kind", ctypes.c_int)]
 
 
 class TsqrInfo(ctypes.Structure):
@@ -27,7 +28,7 @@ class TsqrInfo(ctypes.Structure):
                 ("num_leaves", i64), ("num_tiles", i64), ("tree_levels", ctypes.c_int),
                 ("tree", ctypes.c_int), ("waves", ctypes.c_int), ("precision", ctypes.c_int),
                 ("workspace_bytes", i64), ("reorth_applied", ctypes.c_int),
-                ("orth_estimate", ctypes.c_double)]
+                ("orth_estimate", ctypes.c_double), ("leaf_kind", ctypes.c_int)]
 
 
 PHASES = ["leaf", "tree", "root", "seeds", "form_q", "apply_qt", "q1", "reorth", "leaf_t"]

@@ -15,6 +15,11 @@ namespace tsqr {
 bool tuned_opts(int64_t m, int64_t n, tsqr_precision prec, int want_q, tsqr_opts* out);  // tsqr_tune.cpp
 }
 
+// The leaf variant of TSQR_LEAF_AUTO where both exist (1: recursive).
+#ifndef TSQR_LEAF_AUTO_REC
+#define TSQR_LEAF_AUTO_REC 0
+#endif
+
 namespace tsqr {
 
 bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves,
@@ -316,10 +321,15 @@ static tsqr_status check_plan_args(int64_t m, int64_t n, tsqr_precision prec, co
         if (o.leaf_rows < 0 || o.tile_rows < 0 || o.flat_len < 0) return -5;
         if (o.waves != 0 && o.waves != 1 && o.waves != 2 && o.waves != 4) return -5;
         if (o.want_q != 0 && o.want_q != 1) return -5;
+        if (o.leaf_kind < TSQR_LEAF_AUTO || o.leaf_kind > TSQR_LEAF_RECURSIVE) return -5;
     }
     if (!tsqr::make_layout(L, m, n, o.leaf_rows, o.flat_len, o.tree, o.waves, prec == TSQR_MIXED, o.want_q != 0))
         return 3;
     if (o.tile_rows != 0 && o.tile_rows != L.mt) return -5;
+    // the recursive leaf variant: FP64 with Q at padded widths 16 and 32
+    const bool rec_ok = !L.mixed && o.want_q && (L.np == 16 || L.np == 32);
+    if (o.leaf_kind == TSQR_LEAF_RECURSIVE && !rec_ok && !L.mixed && o.want_q) return -5;
+    L.rec = rec_ok && (o.leaf_kind == TSQR_LEAF_RECURSIVE || (o.leaf_kind == TSQR_LEAF_AUTO && TSQR_LEAF_AUTO_REC));
     return 0;
 }
 
@@ -338,6 +348,7 @@ static void fill_info(const tsqr::Layout& L, tsqr_precision prec, tsqr_info* out
     out->waves = L.waves;
     out->precision = prec;
     out->workspace_bytes = L.total * (int64_t)sizeof(double);
+    out->leaf_kind = L.rec ? TSQR_LEAF_RECURSIVE : TSQR_LEAF_COMPACT_WY;
 }
 
 tsqr_status tsqr_plan_query(int64_t m, int64_t n, tsqr_precision prec, const tsqr_opts* opts, tsqr_info* out)
@@ -420,12 +431,14 @@ tsqr_status tsqr_factor_into(tsqr_plan p, const double* A, int64_t lda, double* 
     hipError_t e = run_phase(p, TSQR_PHASE_LEAF, [&] {
         return tsqr::launch_leaf_factor(p->L, A, lda, V, want_q ? ldv : lda, p->ws, want_q, p->stream);
     });
-    if (e == hipSuccess && want_q) e = fork_T(p);
+    // the recursive leaf variant leaves no T kernel to run
+    const bool t_kernel = want_q && !p->L.rec;
+    if (e == hipSuccess && t_kernel) e = fork_T(p);
     if (e == hipSuccess && p->L.levels > 0)
         e = run_phase(p, TSQR_PHASE_TREE, [&] { return tsqr::launch_tree(p->L, p->ws, want_q, p->stream); });
     if (e == hipSuccess)
         e = run_phase(p, TSQR_PHASE_ROOT, [&] { return tsqr::launch_root(p->L, p->ws, R, ldr, p->stream); });
-    if (e == hipSuccess && want_q) e = join_T(p);
+    if (e == hipSuccess && t_kernel) e = join_T(p);
     if (e != hipSuccess) return hip_status(e);
     p->state = want_q ? 1 : 2;
     return 0;

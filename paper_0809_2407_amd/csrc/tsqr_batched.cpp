@@ -141,6 +141,7 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
         if (o.leaf_rows < 0 || o.tile_rows != 0 || o.flat_len < 0) return -6;
         if (o.waves != 0 && o.waves != 1 && o.waves != 2 && o.waves != 4) return -6;
         if (o.want_q != 0 && o.want_q != 1) return -6;
+        if (o.leaf_kind != TSQR_LEAF_AUTO && o.leaf_kind != TSQR_LEAF_COMPACT_WY) return -6;
     }
     for (int i = 0; i < count; ++i) {
         if (n[i] < 1 || m[i] < 1 || m[i] < n[i]) return -3;
@@ -410,6 +411,7 @@ tsqr_status tsqr_batched_problem_info(tsqr_batched_plan p, int index, tsqr_info*
     out->waves = L.waves;
     out->precision = p->prec;
     out->workspace_bytes = L.total * (int64_t)sizeof(double);
+    out->leaf_kind = TSQR_LEAF_COMPACT_WY;
     if (p->prec == TSQR_MIXED && p->want_q && p->state == 1) {
         // the second pass's check (synchronises the plan's stream)
         double info[2] = {0.0, 0.0};

@@ -73,6 +73,9 @@ struct Layout {
 
     // mixed precision (FP32 first pass, FP64 second pass)
     bool mixed = false;
+    // FP64 with Q: each leaf tile's T is formed by the leaf kernel itself (the
+    // recursive variant, widths 16 and 32) instead of a T kernel after it
+    bool rec = false;
     int64_t ld32 = 0;                       // rows of V32 and Q1: whole tiles, rounded up to 64
     int64_t off_T32 = 0;                    // per-tile T in FP32 (packed), ntiles * nt floats
     int64_t off_V32 = 0, off_Q1 = 0;        // FP32, ld32 x npb, zero past m and past n

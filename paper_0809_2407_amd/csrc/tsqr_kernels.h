@@ -404,12 +404,11 @@ __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC
 // --------------------------------------------------------------------------
 template <int NP, int RL, int P>
 __device__ __forceinline__ void panel_update(double (&a)[RL][NP / 4], double* Rs, double* cb, const double* taus,
-                                             int lane)
+                                             double* Ts, int lane)
 {
     constexpr int NB = NP / 16, LDP = NP + 1, NL = NB - P - 1;  // later 16-column blocks
     static_assert(16 * LDP >= 256 + 272, "the panel's Gram and T fit in the chunk buffer");
     double* Gd = cb;
-    double* Ts = cb + 256;
     const int q = lane >> 4, p = lane & 15;
     dbl4 G = dbl4{0.0, 0.0, 0.0, 0.0};
     dbl4 Z[NL > 0 ? NL : 1];
@@ -484,10 +483,13 @@ __device__ __forceinline__ void panel_update(double (&a)[RL][NP / 4], double* Rs
 }
 
 // The blocked chained factorization (FP64, LC = 4, NP a multiple of 16).
-// On return every reflector is scaled (sc is all ones).
-template <int NP, int RL, int P = 0>
+// On return every reflector is scaled (sc is all ones).  TK: the T_P of every
+// panel but the last is kept at TA + 272 P (16 x 16 at stride 17), the diagonal
+// blocks of the tile's T (the recursive leaf variant assembles the rest);
+// otherwise it lives in the chunk buffer only while its panel update runs.
+template <int NP, int RL, int P = 0, bool TK = false>
 __device__ __forceinline__ void factor_tile_blocked(double (&a)[RL][NP / 4], double (&sc)[NP / 4], double* Rs,
-                                                    double* vb, double* taus, double* cb, int lane)
+                                                    double* vb, double* taus, double* cb, double* TA, int lane)
 {
     factor_tile<NP, RL, 4, false, double, 4 * P, 4 * P + 4>(a, sc, Rs, vb, taus, lane);
 #pragma unroll
@@ -497,8 +499,8 @@ __device__ __forceinline__ void factor_tile_blocked(double (&a)[RL][NP / 4], dou
         sc[k] = 1.0;
     }
     if constexpr (P + 1 < NP / 16) {
-        panel_update<NP, RL, P>(a, Rs, cb, taus, lane);
-        factor_tile_blocked<NP, RL, P + 1>(a, sc, Rs, vb, taus, cb, lane);
+        panel_update<NP, RL, P>(a, Rs, cb, taus, TK ? TA + 272 * P : cb + 256, lane);
+        factor_tile_blocked<NP, RL, P + 1, TK>(a, sc, Rs, vb, taus, cb, TA, lane);
     }
 }
 
@@ -605,6 +607,118 @@ __device__ __forceinline__ void gram_out(const E (&a)[RL][NP / LC], double* cb, 
             }
 }
 
+// The recursive leaf variant (the recursive local QR of Elmroth and Gustavson
+// that Sec. 3.1 and 7 bring into TSQR): the tile's compact-WY factor T is put
+// together inside the leaf kernel from its 16-column blocks, T = [T_L, X; 0,
+// T_R] with X = -T_L (Y_L^T Y_R) T_R (the product of two compact-WY blocks,
+// Sec. 3.2), so no separate T kernel runs over the leaf tiles.  The recursion
+// halves the columns down to the 16-column block of the matrix cores, where a
+// panel is factored column by column (factor_tile); widths of one or two
+// blocks, whose T blocks fit beside the leaf's LDS (NP = 16, 32), have it.
+__host__ __device__ constexpr bool leaf_rec_ok(int np) { return np % 16 == 0 && np / 16 <= 2; }
+// LDS of the T blocks (16 x 16 at stride 17): diagonal block b at 272 b, the
+// block above the diagonal (two blocks) at 272 * 2.
+__host__ __device__ constexpr int rec_ta_doubles(int np) { return (np / 16) * (np / 16 + 1) / 2 * 272; }
+
+// T of a factored tile of the four-group layout (LC = 4: lane 16 cg + rg holds
+// rows 16 i + rg, columns 4 k + cg), scaled reflectors in a, tau in taus,
+// written packed by columns (column c at c (c + 1) / 2, rows 0 .. c) to slot.
+// The diagonal blocks b >= D0 come from the tile's Gram by the column
+// recurrence t_j = -tau_j T (V^T v_j) (earlier ones are already in TA: the
+// panel updates of the blocked factorisation formed them); the block above the
+// diagonal from G_01 = Y_0^T Y_1 on the matrix cores.  16-row chunks of the tile
+// go through cb (16 x (NP+1) doubles) into the f64 16x16x4 operand layout, as in
+// gram_accumulate.  FIRST: reflector c has 1 in row c and zeros above.
+template <int NP, int RL, bool FIRST, int D0>
+__device__ __forceinline__ void tile_T(const double (&a)[RL][NP / 4], double* cb, const double* taus, double* TA,
+                                       double* __restrict__ slot, int lane)
+{
+    constexpr int KC = NP / 4, LDP = NP + 1, NB = NP / 16;
+    static_assert(leaf_rec_ok(NP) && D0 >= 0 && D0 < NB, "one split at most");
+    static_assert(16 * LDP >= 256 * NB, "the dense diagonal Gram blocks fit in the chunk buffer");
+    const int cg = lane >> 4, rg = lane & 15;
+    const int q = lane >> 4, p = lane & 15;
+    dbl4 G[NB], H = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int b = 0; b < NB; ++b) G[b] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+        // chunk i = rows 16 i .. 16 i + 15: lane (cg, rg) holds row rg of it
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            double v = a[i][k];
+            if (FIRST) {
+                const int row = 16 * i + rg, col = 4 * k + cg;
+                v = row > col ? v : (row == col ? 1.0 : 0.0);
+            }
+            cb[rg * LDP + 4 * k + cg] = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            double y[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) y[b] = cb[(4 * s + q) * LDP + 16 * b + p];
+#pragma unroll
+            for (int b = D0; b < NB; ++b) G[b] = mfma16x16x4(y[b], y[b], G[b]);
+            // H(4r + q, p) = (Y_1^T Y_0)(4r + q, p) = G_01(p, 4r + q): the A operand of G_01
+            if constexpr (NB == 2) H = mfma16x16x4(y[1], y[0], H);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    // dense strictly upper diagonal Gram blocks, G(k, j) at cb + 256 b + 16 j + k
+#pragma unroll
+    for (int b = D0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cb[256 * b + 16 * p + 4 * r + q] = (4 * r + q < p) ? G[b][r] : 0.0;
+    __builtin_amdgcn_wave_barrier();
+    {
+        // lane group q builds the rows p of block b (groups past the blocks
+        // repeat the last one without writing it)
+        const int b = q < D0 ? D0 : (q < NB ? q : NB - 1);
+        const double* gb = cb + 256 * b;
+        const double* tb = taus + 16 * b;
+        double tr[16];
+#pragma unroll
+        for (int jl = 0; jl < 16; ++jl) tr[jl] = 0.0;
+#pragma unroll
+        for (int jl = 0; jl < 16; ++jl) {
+            const double tj = tb[jl];
+            double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+            for (int kl = 0; kl < jl; ++kl) {
+                if (kl & 1) acc1 = fma(tr[kl], gb[16 * jl + kl], acc1);
+                else acc0 = fma(tr[kl], gb[16 * jl + kl], acc0);
+            }
+            const double v = (p < jl) ? -tj * (acc0 + acc1) : (p == jl ? tj : 0.0);
+            tr[jl] = v;
+            if (q == b) TA[272 * b + p + 17 * jl] = v;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if constexpr (NB == 2) {
+        // X = G_01 T_11, then T_01 = -T_00 X
+        dbl4 X = dbl4{0.0, 0.0, 0.0, 0.0}, Y = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) X = mfma16x16x4(H[s], TA[272 + (4 * s + q) + 17 * p], X);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) Y = mfma16x16x4(TA[p + 17 * (4 * s + q)], X[s], Y);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) TA[544 + (4 * r + q) + 17 * p] = -Y[r];
+        __builtin_amdgcn_wave_barrier();
+    }
+    // packed by columns: lane r writes row r of column c
+    const int bi = lane >> 4, rl = lane & 15;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+        const int cbk = c / 16;
+        const int blk = bi == cbk ? cbk : (bi < cbk ? NB + cbk * (cbk - 1) / 2 + bi : cbk);
+        const double v = TA[272 * blk + rl + 17 * (c % 16)];
+        if (lane <= c) slot[c * (c + 1) / 2 + lane] = v;
+    }
+    __builtin_amdgcn_wave_barrier();  // the next tile rewrites cb and TA
+}
+
 // Tile load/store in the factor layout.  The per-lane part of the address
 // (row rg, column cg) is one loop-invariant offset; the rest is uniform, so the
 // compiler does not keep one address per element alive across the chain.
@@ -667,13 +781,18 @@ __device__ __forceinline__ void store_tile(const E (&a)[RL][NP / LC], E* tb, int
 // With Q, each tile's T slot receives tau and the Gram entries (gram_out) and
 // the T kernel (k_build_T, k_build_T_batch) forms T afterwards, so the leaf's
 // LDS holds only a chunk buffer for the Gram.
-template <int NP, bool WANT_Q, typename E>
+// REC: the recursive variant (tile_T): each tile's T is written to its slot
+// by the leaf itself; the LDS then also holds the T blocks (rec_ta_doubles).
+template <int NP, bool WANT_Q, typename E, bool REC = false>
 __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, int64_t ldv, int64_t m, int n,
                                            int64_t P, int64_t leaf_rows, int64_t f, E* __restrict__ Ttile,
                                            double* __restrict__ Rleaf, int64_t leaf, double* wsm, int lane)
 {
     constexpr bool MIXED = sizeof(E) == 4;
     constexpr bool BLK = leaf_blocked<E>(NP);
+    constexpr bool RT = REC && WANT_Q;
+    static_assert(!REC || (!MIXED && leaf_rec_ok(NP) && leaf_col_groups<E>(NP) == 4),
+                  "the recursive variant: FP64, one or two 16-column blocks, four column groups");
     constexpr int LC = leaf_col_groups<E>(NP), LR = 64 / LC, MT = tile_rows_e<E>(NP), RL = MT / LR, KC = NP / LC;
     constexpr int NT = packed_size(NP);
     constexpr int CH = leaf_gram_chunk<E>(NP, MT);
@@ -683,6 +802,7 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
     double* Gs = Rs + r_area(NP);
     E* vb = reinterpret_cast<E*>(Gs + GA);
     double* taus = Gs + GA + (LR * vb_stride_e<E>(RL) * (int)sizeof(E) + 7) / 8;
+    double* TA = taus + NP;  // RT: the T blocks
 
     const int64_t row0 = leaf * leaf_rows;
     const int64_t rows = (leaf == P - 1) ? (m - row0) : leaf_rows;
@@ -713,19 +833,22 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
             scale_tile<NP, RL, LC, true, E>(a, sc, lane);
             // the mixed workspace takes whole tiles (zero rows and columns included)
             store_tile<NP, RL, LC, E>(a, V + row0, ldv, lane_off_v, MIXED ? MT : valid, MIXED ? NP : n, rg, cg);
-            gram_out<NP, RL, LC, true, CH, E>(a, Gs, taus, Ttile + (leaf * f) * NT, lane);
+            if constexpr (RT) tile_T<NP, RL, true, 0>(a, Gs, taus, TA, Ttile + (leaf * f) * NT, lane);
+            else gram_out<NP, RL, LC, true, CH, E>(a, Gs, taus, Ttile + (leaf * f) * NT, lane);
         }
     }
     for (int64_t t = 1; t < ntl; ++t) {
         const int64_t t0 = row0 + t * MT;
         const int64_t valid = (rows - t * MT) < MT ? (rows - t * MT) : MT;
         load_tile<NP, RL, LC, E>(a, A + t0, lda, lane_off, valid, n, rg, cg);
-        if constexpr (BLK) factor_tile_blocked<NP, RL>(a, sc, Rs, vb, taus, Gs, lane);
+        if constexpr (BLK) factor_tile_blocked<NP, RL, 0, RT>(a, sc, Rs, vb, taus, Gs, TA, lane);
         else factor_tile<NP, RL, LC, false, E>(a, sc, Rs, vb, taus, lane);
         if (WANT_Q) {
             scale_tile<NP, RL, LC, false, E>(a, sc, lane);
             store_tile<NP, RL, LC, E>(a, V + t0, ldv, lane_off_v, MIXED ? MT : valid, MIXED ? NP : n, rg, cg);
-            gram_out<NP, RL, LC, false, CH, E>(a, Gs, taus, Ttile + (leaf * f + t) * NT, lane);
+            if constexpr (RT)
+                tile_T<NP, RL, false, BLK ? NP / 16 - 1 : 0>(a, Gs, taus, TA, Ttile + (leaf * f + t) * NT, lane);
+            else gram_out<NP, RL, LC, false, CH, E>(a, Gs, taus, Ttile + (leaf * f + t) * NT, lane);
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -736,17 +859,25 @@ __device__ __forceinline__ void leaf_chain(const double* A, int64_t lda, E* V, i
     }
 }
 
-template <int NP, bool WANT_Q, typename E = double>
+// Per-wave LDS of the single-problem leaf kernel (REC: with the T blocks).
+template <typename E = double>
+__host__ __device__ constexpr int leaf_kernel_lds_doubles(int np, bool want_q, bool rec)
+{
+    return leaf_lds_doubles<E>(np, tile_rows_e<E>(np), want_q) + (rec && want_q ? rec_ta_doubles(np) : 0);
+}
+
+template <int NP, bool WANT_Q, typename E = double, bool REC = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_leaf_factor(const double* A, int64_t lda, E* V, int64_t ldv,
                                                      int64_t m, int n, int64_t P, int64_t leaf_rows, int64_t f,
                                                      E* __restrict__ Ttile, double* __restrict__ Rleaf)
 {
-    constexpr int WS = leaf_lds_doubles<E>(NP, tile_rows_e<E>(NP), WANT_Q);
+    constexpr int WS = leaf_kernel_lds_doubles<E>(NP, WANT_Q, REC);
     extern __shared__ double smem[];
     const int wave = wave_index(), lane = threadIdx.x & 63;
     const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (leaf >= P) return;
-    leaf_chain<NP, WANT_Q, E>(A, lda, V, ldv, m, n, P, leaf_rows, f, Ttile, Rleaf, leaf, smem + wave * WS, lane);
+    leaf_chain<NP, WANT_Q, E, REC>(A, lda, V, ldv, m, n, P, leaf_rows, f, Ttile, Rleaf, leaf, smem + wave * WS,
+                                   lane);
 }
 
 // T of every leaf tile (slots 0 .. ntiles-1, one wavefront each) from the tau
@@ -2001,6 +2132,17 @@ hipError_t leaf_factor_np(const Layout& L, const double* A, int64_t lda, double*
     constexpr int MT = tile_rows_for(NP);
     const size_t lds = (size_t)L.waves * leaf_lds_doubles(NP, MT, want_q) * sizeof(double);
     const dim3 grid(grid_for(L.P, L.waves)), block(64 * L.waves);
+    if (want_q && L.rec) {
+        if constexpr (leaf_rec_ok(NP)) {
+            const size_t lds_r = (size_t)L.waves * leaf_kernel_lds_doubles(NP, true, true) * sizeof(double);
+            allow_lds(k_leaf_factor<NP, true, double, true>, lds_r);
+            hipLaunchKernelGGL((k_leaf_factor<NP, true, double, true>), grid, block, lds_r, s, A, lda, V, ldv, L.m,
+                               (int)L.n, L.P, L.leaf_rows, L.f, ws + L.off_T, ws + L.off_R[0]);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (want_q) {
         allow_lds(k_leaf_factor<NP, true>, lds);
         hipLaunchKernelGGL((k_leaf_factor<NP, true>), grid, block, lds, s, A, lda, V, ldv, L.m, (int)L.n, L.P,

@@ -109,6 +109,9 @@ std::vector<Entry> read_cache(const char* path)
               parse_num(body, 0, "ms", &ms)))
             break;
         parse_num(body, 0, "want_q", &q);
+        double lk = 0;
+        parse_num(body, 0, "leaf_kind", &lk);
+        e.o.leaf_kind = (tsqr_leaf_kind)(int)lk;
         e.o.tree = (tsqr_tree)(int)t;
         e.o.leaf_rows = (int64_t)l;
         e.o.flat_len = (int)fl;
@@ -131,9 +134,9 @@ bool write_cache(const char* path, const std::vector<Entry>& es)
         const Entry& e = es[i];
         std::fprintf(f,
                      "    \"%s\": {\"tree\": %d, \"leaf_rows\": %lld, \"flat_len\": %d, \"waves\": %d, "
-                     "\"want_q\": %d, \"ms\": %.6f}%s\n",
+                     "\"want_q\": %d, \"leaf_kind\": %d, \"ms\": %.6f}%s\n",
                      e.key.c_str(), (int)e.o.tree, (long long)e.o.leaf_rows, e.o.flat_len, e.o.waves, e.o.want_q,
-                     e.ms, i + 1 < es.size() ? "," : "");
+                     (int)e.o.leaf_kind, e.ms, i + 1 < es.size() ? "," : "");
     }
     std::fprintf(f, "  }\n}\n");
     const bool ok = std::fclose(f) == 0;
@@ -241,11 +244,23 @@ tsqr_status tsqr_autotune(int64_t m, int64_t n, tsqr_precision prec, int want_q,
     if (he == hipSuccess) he = hipEventCreate(&e1);
 
     // candidates: leaf lengths 1, 2, 4, ... tiles (a single flat chain last,
-    // when within the guard) times 1, 2 or 4 wavefronts per workgroup
+    // when within the guard) times 1, 2 or 4 wavefronts per workgroup, times
+    // both leaf variants where the recursive one exists
     tsqr::Layout L0;
     tsqr_status st = 0;
     if (he == hipSuccess && !tsqr::make_layout(L0, m, n, 0, 0, TSQR_TREE_AUTO, 0, prec == TSQR_MIXED, want_q != 0)) st = 3;
     std::vector<tsqr_opts> cand;
+    const bool two_kinds = st == 0 && prec == TSQR_FP64 && want_q && (L0.np == 16 || L0.np == 32);
+    auto add = [&](tsqr_opts o) {
+        if (!two_kinds) {
+            cand.push_back(o);
+            return;
+        }
+        for (tsqr_leaf_kind k : {TSQR_LEAF_COMPACT_WY, TSQR_LEAF_RECURSIVE}) {
+            o.leaf_kind = k;
+            cand.push_back(o);
+        }
+    };
     if (he == hipSuccess && st == 0) {
         const int64_t tiles = (m + L0.mt - 1) / L0.mt;
         const int64_t fmax = prec == TSQR_MIXED ? tsqr::kMaxChainF32 : kMaxChainTiles;
@@ -257,7 +272,7 @@ tsqr_status tsqr_autotune(int64_t m, int64_t n, tsqr_precision prec, int want_q,
                 o.flat_len = f == 1 ? 0 : (int)f;
                 o.waves = w;
                 o.want_q = want_q;
-                cand.push_back(o);
+                add(o);
             }
         if (tiles <= fmax)
             for (int w : {1, 2, 4}) {
@@ -266,7 +281,7 @@ tsqr_status tsqr_autotune(int64_t m, int64_t n, tsqr_precision prec, int want_q,
                 o.tree = TSQR_TREE_FLAT;
                 o.waves = w;
                 o.want_q = want_q;
-                cand.push_back(o);
+                add(o);
             }
     }
     if (he == hipSuccess && st == 0 && !scratch) {

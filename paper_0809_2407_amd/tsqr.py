@@ -17,6 +17,8 @@ from . import _lib
 from ._lib import (PHASES, TSQR_FP64, TSQR_MIXED, TSQR_TREE_AUTO, TSQR_TREE_BINARY, TSQR_TREE_FLAT,
                    TSQR_TREE_HYBRID, TsqrInfo, TsqrOpts, TsqrTimings, check)
 
+_LEAF_KINDS = {"auto": 0, "compact_wy": 1, "recursive": 2}
+_LEAF_KIND_NAMES = {v: k for k, v in _LEAF_KINDS.items()}
 _TREES = {"auto": TSQR_TREE_AUTO, "binary": TSQR_TREE_BINARY, "flat": TSQR_TREE_FLAT,
           "hybrid": TSQR_TREE_HYBRID}
 _PREC = {"fp64": TSQR_FP64, "mixed": TSQR_MIXED}
@@ -60,23 +62,26 @@ def _stream_handle(stream) -> int:
     return int(stream.cuda_stream)
 
 
-def _opts_or_null(tree, leaf_rows, tile_rows, flat_len, waves, want_q):
+def _opts_or_null(tree, leaf_rows, tile_rows, flat_len, waves, want_q, leaf_kind="auto"):
     """Options for the C ABI; NULL when every field is at its default, so that
     the library may take the autotuned choice of the problem's class."""
-    if tree == "auto" and not (leaf_rows or tile_rows or flat_len or waves) and want_q:
+    if tree == "auto" and not (leaf_rows or tile_rows or flat_len or waves) and want_q and leaf_kind == "auto":
         return None
     return ctypes.byref(TsqrOpts(_TREES[tree], int(leaf_rows), int(tile_rows), int(flat_len), int(waves),
-                                 1 if want_q else 0))
+                                 1 if want_q else 0, _LEAF_KINDS[leaf_kind]))
 
 
 def plan_query(m: int, n: int, precision: str = "fp64", tree: str = "auto", leaf_rows: int = 0,
-               tile_rows: int = 0, flat_len: int = 0, waves: int = 0, want_q: bool = True) -> dict:
+               tile_rows: int = 0, flat_len: int = 0, waves: int = 0, want_q: bool = True,
+               leaf_kind: str = "auto") -> dict:
     """tsqr_plan_query: what a plan would choose (no device needed)."""
     lib = _lib.load()
-    opts = _opts_or_null(tree, leaf_rows, tile_rows, flat_len, waves, want_q)
+    opts = _opts_or_null(tree, leaf_rows, tile_rows, flat_len, waves, want_q, leaf_kind)
     out = TsqrInfo()
     check("tsqr_plan_query", lib.tsqr_plan_query(int(m), int(n), _PREC[precision], opts, ctypes.byref(out)))
-    return {f: getattr(out, f) for f, _ in TsqrInfo._fields_}
+    d = {f: getattr(out, f) for f, _ in TsqrInfo._fields_}
+    d["leaf_kind"] = _LEAF_KIND_NAMES[d["leaf_kind"]]
+    return d
 
 
 class Plan:
@@ -84,11 +89,12 @@ class Plan:
     tsqr_plan_info / tsqr_plan_destroy."""
 
     def __init__(self, m: int, n: int, precision: str = "fp64", tree: str = "auto", leaf_rows: int = 0,
-                 tile_rows: int = 0, flat_len: int = 0, waves: int = 0, want_q: bool = True, stream=None):
+                 tile_rows: int = 0, flat_len: int = 0, waves: int = 0, want_q: bool = True, stream=None,
+                 leaf_kind: str = "auto"):
         self._lib = _lib.load()
         self.m, self.n = int(m), int(n)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        opts = _opts_or_null(tree, leaf_rows, tile_rows, flat_len, waves, want_q)
+        opts = _opts_or_null(tree, leaf_rows, tile_rows, flat_len, waves, want_q, leaf_kind)
         h = ctypes.c_void_p()
         check("tsqr_plan_create", self._lib.tsqr_plan_create(ctypes.byref(h), self.m, self.n, _PREC[precision],
                                                               opts, _stream_handle(self.stream)))
@@ -118,7 +124,9 @@ class Plan:
     def info(self) -> dict:
         out = TsqrInfo()
         check("tsqr_plan_info", self._lib.tsqr_plan_info(self._h, ctypes.byref(out)))
-        return {f: getattr(out, f) for f, _ in TsqrInfo._fields_}
+        d = {f: getattr(out, f) for f, _ in TsqrInfo._fields_}
+        d["leaf_kind"] = _LEAF_KIND_NAMES[d["leaf_kind"]]
+        return d
 
     def factor(self, A: torch.Tensor, R: Optional[torch.Tensor] = None) -> torch.Tensor:
         lda = _ld(A, self.m, "A")
@@ -220,7 +228,9 @@ class BatchedPlan:
     def problem_info(self, i: int) -> dict:
         out = TsqrInfo()
         check("tsqr_batched_problem_info", self._lib.tsqr_batched_problem_info(self._h, int(i), ctypes.byref(out)))
-        return {f: getattr(out, f) for f, _ in TsqrInfo._fields_}
+        d = {f: getattr(out, f) for f, _ in TsqrInfo._fields_}
+        d["leaf_kind"] = _LEAF_KIND_NAMES[d["leaf_kind"]]
+        return d
 
     def close(self) -> None:
         # the library frees the plan even when it reports an error (say, a
@@ -249,7 +259,8 @@ _TREE_NAMES = {0: "auto", 1: "binary", 2: "flat", 3: "hybrid"}
 
 def _opts_dict(o: TsqrOpts) -> dict:
     return {"tree": _TREE_NAMES[o.tree], "leaf_rows": o.leaf_rows, "tile_rows": o.tile_rows,
-            "flat_len": o.flat_len, "waves": o.waves, "want_q": bool(o.want_q)}
+            "flat_len": o.flat_len, "waves": o.waves, "want_q": bool(o.want_q),
+            "leaf_kind": _LEAF_KIND_NAMES[o.leaf_kind]}
 
 
 def autotune(m: int, n: int, precision: str = "fp64", want_q: bool = True, A: Optional[torch.Tensor] = None,
@@ -285,7 +296,8 @@ def tune_cache_store(path: str, m: int, n: int, opts: dict, ms: float, precision
     """tsqr_tune_cache_store."""
     lib = _lib.load()
     o = TsqrOpts(_TREES[opts.get("tree", "auto")], int(opts.get("leaf_rows", 0)), int(opts.get("tile_rows", 0)),
-                 int(opts.get("flat_len", 0)), int(opts.get("waves", 0)), 1 if opts.get("want_q", True) else 0)
+                 int(opts.get("flat_len", 0)), int(opts.get("waves", 0)), 1 if opts.get("want_q", True) else 0,
+                 _LEAF_KINDS[opts.get("leaf_kind", "auto")])
     check("tsqr_tune_cache_store", lib.tsqr_tune_cache_store(path.encode(), int(m), int(n), _PREC[precision],
                                                              ctypes.byref(o), float(ms)))
 

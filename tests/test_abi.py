@@ -234,3 +234,30 @@ def test_caqr_plans_reject_arguments_without_device():
     assert lib.tsqr_caqr_apply_qt(None, 1, 1, 1, 1, 1) == -1
     assert lib.tsqr_caqr_plan_info(None, None, None) == -1
     assert lib.tsqr_caqr_plan_destroy(None) == -1
+
+
+def test_leaf_kind_choice_and_errors():
+    """The recursive leaf variant exists for FP64 with Q at padded widths 16
+    and 32; asked for elsewhere (FP64 with Q) it is an argument error, and
+    without Q or on a MIXED plan the variants coincide and the field is
+    ignored."""
+    from paper_0809_2407_amd import tsqr as T
+    for n in (13, 16, 29, 32):
+        assert T.plan_query(1 << 16, n, leaf_kind="recursive")["leaf_kind"] == "recursive"
+        assert T.plan_query(1 << 16, n, leaf_kind="compact_wy")["leaf_kind"] == "compact_wy"
+    for n in (8, 20, 33, 48, 64):
+        assert T.plan_query(1 << 16, n)["leaf_kind"] == "compact_wy"
+        with pytest.raises(RuntimeError):
+            T.plan_query(1 << 16, n, leaf_kind="recursive")
+    assert T.plan_query(1 << 16, 32, leaf_kind="recursive", want_q=False)["leaf_kind"] == "compact_wy"
+    assert T.plan_query(1 << 16, 32, precision="mixed", leaf_kind="recursive")["leaf_kind"] == "compact_wy"
+    from paper_0809_2407_amd import _lib
+    lib = _lib.load()
+    out = _lib.TsqrInfo()
+    bad = _lib.TsqrOpts(0, 0, 0, 0, 0, 1, 3)
+    assert lib.tsqr_plan_query(1000, 32, 0, ctypes.byref(bad), ctypes.byref(out)) == -4
+    h = ctypes.c_void_p()
+    rec = _lib.TsqrOpts(0, 0, 0, 0, 0, 1, 2)
+    n = (ctypes.c_int64 * 1)(32)
+    m = (ctypes.c_int64 * 1)(1000)
+    assert lib.tsqr_batched_plan_create(ctypes.byref(h), 1, m, n, 0, ctypes.byref(rec), None) == -6
