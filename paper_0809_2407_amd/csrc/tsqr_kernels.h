@@ -271,6 +271,19 @@ __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC
         for (int cgj = 0; cgj < LC; ++cgj) {
             const int j = LC * kb + cgj;
             const bool owner = cg == cgj;
+            // row j of the running R (chained tiles) is written by reflector j
+            // alone, so this step's entries can be read at its start, their LDS
+            // latency hidden behind the norm (measured: 2% off the leaf, 3% off
+            // the tree at n = 32)
+            double rpre[KC];
+            if constexpr (!FIRST) {
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    rpre[k] = 0.0;
+                    if (k < kb || k >= KHI) continue;
+                    rpre[k] = Rs[rpk<NP>(j, LC * k + cg)];
+                }
+            }
             // FP32 tile: column j is final here, so its owner lanes publish it
             // unscaled through LDS now and the round trip overlaps the norm and
             // the square root below; every lane scales its copy once the scale is
@@ -364,7 +377,7 @@ __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC
                 double w = (double)d[k];
                 double rjc = 0.0;
                 if (!FIRST) {
-                    rjc = Rs[rpk<NP>(j, c)];
+                    rjc = rpre[k];
                     w += rjc;
                 }
                 const double tw = trailing ? tau * w : 0.0;
@@ -1330,6 +1343,16 @@ constexpr int fq_col_blocks(int np)
     return round16(np) / 16 <= 3 ? round16(np) / 16 : (sizeof(E) == 8 ? 2 : TSQR_FQ_F32_WINDOWS);
 }
 
+// The seed windows in LDS: element (r, c) of a window at r + c ss_ld, the row
+// stride padded past the padded width so that the 16 lanes of a group (which
+// read 16 consecutive columns of one row) fall on different LDS banks (with a
+// stride of round16(np) doubles they all hit the same banks).
+template <typename E>
+__host__ __device__ constexpr int ss_ld(int npb) { return sizeof(E) == 8 ? npb + 4 : npb + 1; }
+// LDS elements (of E) per wavefront of the Q kernels: JW windows of 16 columns.
+template <typename E>
+__host__ __device__ constexpr int fq_lds_elems(int np, int jw) { return ss_ld<E>(round16(np)) * 16 * jw; }
+
 // E = float is the first pass of the mixed-precision path: V and T in FP32
 // from the mixed leaf kernel, the FP64 seeds rounded to FP32, products on the
 // FP32 matrix cores, and Q1 written to a workspace of whole tiles and
@@ -1350,20 +1373,20 @@ __device__ __forceinline__ void seed_windows(const E* __restrict__ T, const E* V
                                              int64_t valid, int n, bool first, E* Ss, int jofs,
                                              E (&Zr)[round16(NP) / 4][JN], int lane)
 {
-    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
+    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, SLD = ss_ld<E>(NPB);
     typedef Mfma<E> MM;
     const int cg = lane >> 4, rg = lane & 15;
     E Sr[KS][JN];
 #pragma unroll
     for (int s = 0; s < KS; ++s)
 #pragma unroll
-        for (int jb = 0; jb < JN; ++jb) Sr[s][jb] = Ss[krow<E>(s, cg) + (16 * (jofs + jb) + rg) * NPB];
+        for (int jb = 0; jb < JN; ++jb) Sr[s][jb] = Ss[krow<E>(s, cg) + (16 * (jofs + jb) + rg) * SLD];
     if (!first) {
         tri_times_regs<NP, JN, E>(T, Sr, Zr, lane);
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
-            for (int jb = 0; jb < JN; ++jb) Ss[krow<E>(s, cg) + (16 * (jofs + jb) + rg) * NPB] = Sr[s][jb] - Zr[s][jb];
+            for (int jb = 0; jb < JN; ++jb) Ss[krow<E>(s, cg) + (16 * (jofs + jb) + rg) * SLD] = Sr[s][jb] - Zr[s][jb];
     } else {
         E Wr[KS][JN];
 #pragma unroll
@@ -1397,7 +1420,7 @@ __device__ __forceinline__ void form_q_leaf(const E* V, int64_t lda, int64_t m, 
 {
     constexpr bool MIXED = sizeof(E) == 4;
     constexpr int MT = tile_rows_e<E>(NP), RL = MT / 16, KC = NP / 4;
-    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, NT = packed_size(NP);
+    constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, NT = packed_size(NP), SLD = ss_ld<E>(NPB);
     // k-steps of the expansion: the FP32 permutation of k mixes the columns of
     // a 16-block, so whole blocks are contracted (their padding is zero)
     constexpr int KX = MIXED ? KS : KC;
@@ -1421,7 +1444,7 @@ __device__ __forceinline__ void form_q_leaf(const E* V, int64_t lda, int64_t m, 
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
-            for (int jb = 0; jb < JW; ++jb) Ss[krow<E>(s, cg) + (16 * jb + rg) * NPB] = Sr[s][jb];
+            for (int jb = 0; jb < JW; ++jb) Ss[krow<E>(s, cg) + (16 * jb + rg) * SLD] = Sr[s][jb];
     }
     for (int64_t t = ntl - 1; t >= 0; --t) {
         const int ln = opaque(lane);
@@ -1506,7 +1529,7 @@ __device__ __forceinline__ void form_q_leaf(const E* V, int64_t lda, int64_t m, 
                 for (int r = 0; r < 4; ++r) {
                     const int cl = 16 * jb + MM::out_row(lcg, r), c = 16 * j0 + cl;
                     E v = -acc[r];
-                    if (t == 0 && rl < NP) v += Ss[rl + cl * NPB];
+                    if (t == 0 && rl < NP) v += Ss[rl + cl * SLD];
                     if (MIXED) {
                         // every row and column of the workspace is written; zero past n
                         st_at(qb + (int64_t)(16 * jb + r) * ldq, lane_q, c < n ? v : E(0));
@@ -1540,7 +1563,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     const int j0 = (int)(gw % SPLIT) * JW;
     if (leaf >= P) return;
     form_q_leaf<NP, WIDE, E, true, JW>(V, lda, m, n, P, leaf_rows, f, Ttile, Sleaf, Q, ldq, leaf, j0,
-                                       smem + wave * NPB * 16 * JW, lane);
+                                       smem + wave * fq_lds_elems<E>(NP, JW), lane);
 }
 
 // --------------------------------------------------------------------------
@@ -2242,7 +2265,7 @@ hipError_t form_q_launch(const Layout& L, const double* A, int64_t lda, double* 
                          hipStream_t s)
 {
     constexpr int NPB = round16(NP), SPLIT = NPB / 16 / JW;
-    const size_t lds = (size_t)L.waves * NPB * 16 * JW * sizeof(double);
+    const size_t lds = (size_t)L.waves * fq_lds_elems<double>(NP, JW) * sizeof(double);
     const dim3 grid(grid_for(L.P * SPLIT, L.waves)), block(64 * L.waves);
     if (lane_offsets_fit_32(lda) && lane_offsets_fit_32(ldq)) {
         allow_lds(k_form_q<NP, false, double, JW>, lds);
@@ -2416,8 +2439,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         const BatchArgs X = args[p];
         double* w = ws + B.ws_off;
         form_q_leaf<NP, true, double, false, JW>(X.A, X.lda, B.m, B.n, B.P, B.leaf_rows, B.f, w + B.off_T,
-                                                 w + B.off_S[0], X.X, X.ldx, leaf, j0, smem + wave * NPB * 16 * JW,
-                                                 lane);
+                                                 w + B.off_S[0], X.X, X.ldx, leaf, j0,
+                                                 smem + wave * fq_lds_elems<double>(NP, JW), lane);
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -2521,7 +2544,7 @@ hipError_t batch_form_q_launch(const BatchClass& C, const BatchProblem* probs, c
                                int waves, hipStream_t s)
 {
     constexpr int NPB = round16(NP), SPLIT = NPB / 16 / JW;
-    const size_t lds = (size_t)waves * NPB * 16 * JW * sizeof(double);
+    const size_t lds = (size_t)waves * fq_lds_elems<double>(NP, JW) * sizeof(double);
     allow_lds(k_form_q_batch<NP, JW>, lds);
     hipLaunchKernelGGL((k_form_q_batch<NP, JW>), dim3(batch_grid(C.n_leaf * SPLIT, waves)), dim3(64 * waves), lds,
                        s, probs, args, ws, C.leaf_items, C.n_leaf);
@@ -2628,7 +2651,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         form_q_leaf<NP, true, float>(V32, B.ld32, B.m, B.n, B.P, B.leaf_rows, B.f,
                                      reinterpret_cast<const float*>(w + B.off_T32), w + B.off_S[0],
                                      reinterpret_cast<float*>(w + B.off_Q1), B.ld32, leaf, j0,
-                                     smem + wave * NPB * 16 * JW, lane);
+                                     smem + wave * fq_lds_elems<float>(NP, JW), lane);
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -2783,7 +2806,7 @@ hipError_t batch_factor_mixed_np(const BatchClass& C, const BatchProblem* probs,
     }
     {
         constexpr int NPB = round16(NP), JW = fq_col_blocks<float>(NP), SPLIT = NPB / 16 / JW;
-        const size_t lds = (size_t)waves * NPB * 16 * JW * sizeof(float);
+        const size_t lds = (size_t)waves * fq_lds_elems<float>(NP, JW) * sizeof(float);
         allow_lds(k_form_q1_batch<NP>, lds);
         hipLaunchKernelGGL((k_form_q1_batch<NP>), dim3(batch_grid(C.n_leaf * SPLIT, waves)), dim3(64 * waves), lds,
                            s, probs, ws, C.leaf_items, C.n_leaf);
@@ -2848,7 +2871,7 @@ template <int NP>
 hipError_t form_q1_np(const Layout& L, double* ws, hipStream_t s)
 {
     constexpr int NPB = round16(NP), JW = fq_col_blocks<float>(NP), SPLIT = NPB / 16 / JW;
-    const size_t lds = (size_t)L.waves * NPB * 16 * JW * sizeof(float);
+    const size_t lds = (size_t)L.waves * fq_lds_elems<float>(NP, JW) * sizeof(float);
     const dim3 grid(grid_for(L.P * SPLIT, L.waves)), block(64 * L.waves);
     const float* V32 = reinterpret_cast<const float*>(ws + L.off_V32);
     const float* T32 = reinterpret_cast<const float*>(ws + L.off_T32);
