@@ -53,8 +53,10 @@ typedef int tsqr_status;
  *   the second-pass factors live in the plan.  tsqr_factor runs both passes
  *   and returns the final R; tsqr_form_q writes the corrected Q; tsqr_apply_qt
  *   is not available (status 3).  With want_q = 0 only the first pass runs and
- *   R carries the FP32 pass's accuracy.  The paper fixes no precision beyond
- *   FP64; this variant is the library's own. */
+ *   R carries the FP32 pass's accuracy.  The entries of A must lie within
+ *   the FP32 range (FP64 plans rescale columns whose norms leave the FP64
+ *   range).  The paper fixes no precision beyond FP64; this variant is the
+ *   library's own. */
 typedef enum { TSQR_FP64 = 0, TSQR_MIXED = 1 } tsqr_precision;
 
 /* Reduction-tree shape (Sec. 2 and the list of tree shapes in Sec. 7):

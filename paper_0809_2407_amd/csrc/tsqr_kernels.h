@@ -153,6 +153,36 @@ __device__ __forceinline__ double sqrt_pos(double x)
     return fma(d, h, g);
 }
 
+// The scalars of the Householder reflector of a column with pivot entry alpha
+// and squared norm s of the part below the pivot (Sec. 4.2's local QR; LAPACK's
+// convention): beta = -sgn(alpha) ||x||, tau = (beta - alpha)/beta = -d/beta and
+// the scale 1/d of the part below the pivot, with d = alpha - beta (alpha and
+// beta have opposite signs, so d has no cancellation); tau = 0 (H = I) when the
+// part below the pivot is zero.  Branch-free: the selects discard the inf/NaN of
+// s == 0.  alpha^2 + s must lie in the normal range (the caller rescales).
+__device__ __forceinline__ void reflector_scalars(double alpha, double s, double& beta, double& scale, double& tau)
+{
+    const bool nz = s != 0.0;
+    const double nrm = sqrt_pos(fma(alpha, alpha, s));
+    const double bn = alpha < 0.0 ? nrm : -nrm;
+    const double dd = alpha - bn;
+    const double rr = recip(dd * bn);
+    beta = nz ? bn : alpha;
+    scale = nz ? bn * rr : 0.0;
+    tau = nz ? -(dd * dd) * rr : 0.0;
+}
+
+// Maximum over groups of LR consecutive lanes (the pairing of group_sum).
+template <int LR>
+__device__ __forceinline__ double group_max(double v)
+{
+    v = fmax(v, dpp_move<0xB1>(v));
+    v = fmax(v, dpp_move<0x4E>(v));
+    v = fmax(v, dpp_move<0x141>(v));
+    if (LR == 16) v = fmax(v, dpp_move<0x140>(v));
+    return v;
+}
+
 __host__ __device__ constexpr int round16(int np) { return (np + 15) / 16 * 16; }
 // The running triangle R lives in LDS packed by rows: R(r, c), r <= c, at
 // r np - r(r+1)/2 + c (np(np+1)/2 doubles, rounded up to an even count).  The
@@ -317,17 +347,53 @@ __device__ __forceinline__ void factor_tile(E (&a)[RL][NP / LC], E (&sc)[NP / LC
             double alpha;
             if (FIRST) alpha = (double)readlane_d(a[ij][kb], cgj * LR + rg0 + cgj);
             else alpha = Rs[rpk<NP>(j, j)];
-            // beta = -sgn(alpha) ||x||, tau = (beta - alpha)/beta = -d/beta, scale = 1/d
-            // with d = alpha - beta; tau = 0 (H_j = I) when the part below the
-            // pivot is zero.  Branch-free: the selects discard the inf/NaN of s == 0.
-            const bool nz = s != 0.0;
-            const double nrm = sqrt_pos(fma(alpha, alpha, s));
-            const double bn = alpha < 0.0 ? nrm : -nrm;
-            const double dd = alpha - bn;
-            const double rr = recip(dd * bn);
-            const double beta = nz ? bn : alpha;
-            const double scale = nz ? bn * rr : 0.0;
-            const double tau = nz ? -(dd * dd) * rr : 0.0;
+            double beta, scale, tau;
+            if constexpr (sizeof(E) == 8) {
+                // A column whose squared norm alpha^2 + s leaves [2^-960, 2^1002)
+                // (it overflowed, lost bits to underflow, or is zero) gets its
+                // scalars from its entries scaled by a power of two 2^-e that
+                // brings the largest to [1, 2): beta scales back by 2^e and the
+                // reflector's scale by 2^-e, both exactly; tau does not change.
+                // FP32 tiles (norms summed in FP64 from FP32 entries) never get
+                // there.  The test is on the exponent bits of alpha^2 + s in
+                // scalar registers (zero, inf and NaN fall outside); the branch is
+                // wave-uniform and never taken on ordinary data, but it costs the
+                // leaf about 2% (measured at n = 32: the scalar chain can no
+                // longer be scheduled across it; a branch to an empty block costs
+                // the same).
+                double ac = alpha, sc2 = s, up = 1.0, down = 1.0;
+                const unsigned hw = (unsigned)__builtin_amdgcn_readfirstlane(__double2hiint(fma(alpha, alpha, s)));
+                if (__builtin_expect(hw - 0x03F00000u > 0x7E8FFFFFu - 0x03F00000u, 0)) {
+                    double mx = 0.0;
+#pragma unroll
+                    for (int i = 0; i < RL; ++i) {
+                        if (i > imax) continue;
+                        double x = fabs((double)a[i][kb]);
+                        if (FIRST && LR * i + rg <= j) x = 0.0;
+                        mx = fmax(mx, x);
+                    }
+                    mx = fmax(readlane_d(group_max<LR>(mx), cgj * LR), fabs(alpha));
+                    const int e = mx > 0.0 ? ilogb(mx) : 0;
+                    down = ldexp(1.0, -e);
+                    up = ldexp(1.0, e);
+                    double q0 = 0.0, q1 = 0.0;
+#pragma unroll
+                    for (int i = 0; i < RL; ++i) {
+                        if (i > imax) continue;
+                        double x = (double)a[i][kb] * down;
+                        if (FIRST && LR * i + rg <= j) x = 0.0;
+                        if (i & 1) q1 = fma(x, x, q1);
+                        else q0 = fma(x, x, q0);
+                    }
+                    sc2 = readlane_d(group_sum<LR>(q0 + q1), cgj * LR);
+                    ac = alpha * down;
+                }
+                reflector_scalars(ac, sc2, beta, scale, tau);
+                beta *= up;
+                scale *= down;
+            } else {
+                reflector_scalars(alpha, s, beta, scale, tau);
+            }
             // the reflector v_j (the owners scale their own column at the end of the tile)
             if (owner) sc[kb] = (E)scale;
             E vr[RL];
