@@ -56,6 +56,10 @@ WORKLOADS = {
     "tsqr_fp64_rq_krylov_m4194304_n17": dict(m=2048 * 2048, n=17, decades=None, mode="rq", krylov=(2048, 16)),
     "tsqr_mixed_rq_krylov_m4194304_n17": dict(m=2048 * 2048, n=17, decades=None, mode="rq", krylov=(2048, 16),
                                               precision="mixed"),
+    # the mixed path with Q^T B on the 32 right-hand sides (its Q = Q1 R2^-1 has no complement:
+    # only the top n rows of B are written, 8mk bytes read instead of 16mk moved)
+    "tsqr_mixed_rq_qtb_krylov_m4194304_n17_k32": dict(m=2048 * 2048, n=17, decades=None, mode="rq",
+                                                      krylov=(2048, 16), rhs=32, precision="mixed"),
 }
 DEFAULT = "tsqr_fp64_rq_m16777216_n32_kappa1e12"
 
@@ -334,6 +338,8 @@ def run_single(args, wname: str, cpu: bool, check: bool):
     path_bytes = (32.0 if mode == "rq" else 8.0) * m * n + (8.0 * m * n + 16.0 * m * k_rhs if k_rhs else 0.0)
     if mixed and mode == "rq":
         path_bytes = 36.0 * m * n  # the byte model of the mixed path with its Gram pass unfused
+        if k_rhs:
+            path_bytes += 4.0 * m * n + 8.0 * m * k_rhs  # Q1 and B read; n rows of B written
     t_roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), path_bytes / (HBM_PEAK_GBS * 1e9))
 
     result = {

@@ -52,7 +52,7 @@ typedef int tsqr_status;
  *   Q = Q1 R2^{-1} and R = R2 R1.  A is only read; the FP32 reflectors, Q1 and
  *   the second-pass factors live in the plan.  tsqr_factor runs both passes
  *   and returns the final R; tsqr_form_q writes the corrected Q; tsqr_apply_qt
- *   is not available (status 3).  With want_q = 0 only the first pass runs and
+ *   writes Q^T B for that Q (the thin factor only).  With want_q = 0 only the first pass runs and
  *   R carries the FP32 pass's accuracy.  The entries of A must lie within
  *   the FP32 range (FP64 plans rescale columns whose norms leave the FP64
  *   range).  The paper fixes no precision beyond FP64; this variant is the
@@ -173,9 +173,12 @@ tsqr_status tsqr_form_q(tsqr_plan p, const double* A_factored, int64_t lda, doub
  * with Q the thin factor returned by tsqr_form_q; rows n..m-1 hold coordinates
  * of B in the tree's basis of the orthogonal complement (they depend on the
  * tree).  k = 0 returns 0 at once (B may then be NULL).  Right-hand sides are
- * processed 32 at a time.  Errors: -1 p, -2 A NULL, -3 lda < m, -4 k < 0,
- * -5 B NULL, -6 ldb < m; 3 on a MIXED plan; 4 when the plan holds no
- * factorisation with reflectors. */
+ * processed 32 at a time.  On a MIXED plan Q is Q1 R2^{-1}, which has no
+ * complement: rows 0..n-1 become Q^T B = R2^{-T} (Q1^T B) (Q1^T B summed in
+ * FP64 over 64-row groups, pairwise, like the second pass's Gram), rows n..m-1
+ * are left as they are, and A_factored and lda are not used (A_factored may
+ * be NULL).  Errors: -1 p, -2 A NULL, -3 lda < m, -4 k < 0, -5 B NULL,
+ * -6 ldb < m; 4 when the plan holds no factorisation with reflectors. */
 tsqr_status tsqr_apply_qt(tsqr_plan p, const double* A_factored, int64_t lda, int64_t k, double* B,
                           int64_t ldb);
 

@@ -483,7 +483,17 @@ tsqr_status tsqr_form_q(tsqr_plan p, const double* A_factored, int64_t lda, doub
 tsqr_status tsqr_apply_qt(tsqr_plan p, const double* A_factored, int64_t lda, int64_t k, double* B, int64_t ldb)
 {
     if (!p) return -1;
-    if (p->L.mixed) return 3;  // Q^T B is an FP64 path only
+    if (p->L.mixed) {
+        // the reflectors live in the plan: A_factored and lda are not used
+        if (k < 0) return -4;
+        if (k == 0) return 0;
+        if (!B) return -5;
+        if (ldb < p->L.m) return -6;
+        if (p->state != 1) return 4;
+        return hip_status(run_phase(p, TSQR_PHASE_APPLY, [&] {
+            return tsqr::launch_qtb_mixed(p->L, p->ws, k, B, ldb, p->stream);
+        }));
+    }
     if (!A_factored) return -2;
     if (lda < p->L.m) return -3;
     if (k < 0) return -4;

@@ -131,6 +131,13 @@ hipError_t launch_reorth_q(const Layout& L, double* ws, double* Q, int64_t ldq, 
 #undef CALL
 }
 
+hipError_t launch_qtb_mixed(const Layout& L, double* ws, int64_t k, double* B, int64_t ldb, hipStream_t s)
+{
+#define CALL(NP) qtb_mixed_np<NP>(L, ws, k, B, ldb, s)
+    TSQR_NP_SWITCH(L.np, CALL)
+#undef CALL
+}
+
 hipError_t launch_batch_factor(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
                                bool want_q, int waves, hipStream_t s)
 {

@@ -170,6 +170,8 @@ int leaf_lds_bytes(int np, bool mixed, bool want_q);
 hipError_t launch_form_q1(const Layout& L, double* ws, hipStream_t s);
 hipError_t launch_reorth(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s);
 hipError_t launch_reorth_q(const Layout& L, double* ws, double* Q, int64_t ldq, hipStream_t s);
+// Q^T B on a mixed plan: the top n rows of B become R2^{-T} Q1^T B
+hipError_t launch_qtb_mixed(const Layout& L, double* ws, int64_t k, double* B, int64_t ldb, hipStream_t s);
 
 // batched FP64: every problem of a width class in one launch per phase
 hipError_t launch_batch_factor(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
@@ -210,6 +212,8 @@ template <int NP>
 hipError_t reorth_np(const Layout& L, double* ws, double* R, int64_t ldr, hipStream_t s);
 template <int NP>
 hipError_t reorth_q_np(const Layout& L, double* ws, double* Q, int64_t ldq, hipStream_t s);
+template <int NP>
+hipError_t qtb_mixed_np(const Layout& L, double* ws, int64_t k, double* B, int64_t ldb, hipStream_t s);
 template <int NP>
 hipError_t batch_factor_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
                            bool want_q, int waves, hipStream_t s);

@@ -2990,6 +2990,177 @@ hipError_t reorth_q_np(const Layout& L, double* ws, double* Q, int64_t ldq, hipS
     return hipGetLastError();
 }
 
+
+// ---- Q^T B on a mixed plan ---------------------------------------------------
+// The plan's Q is Q1 R2^{-1} (Q1 the FP32 first pass's explicit Q, R2^{-1}
+// from the second pass: the identity when its check did not call for it), so
+// Q^T B = R2^{-T} (Q1^T B): n x kc, written over the top n rows of B (the
+// thin factor has no complement for the other rows).  Q1^T B takes the second
+// pass's route: partial products of 64-row groups on the FP64 matrix cores
+// (Q1's FP32 entries and their products with B exact in FP64 inputs), summed
+// pairwise in two stages (k_psum64, k_psum), then R2^{-T} on the sum.
+__host__ __device__ constexpr int qtb_cols(int npb) { return npb >= 32 ? 32 : 16; }
+
+template <int NP>
+__global__ void __launch_bounds__(256) k_q1tb(const float* __restrict__ Q1, int64_t ldq1, int64_t m,
+                                              const double* __restrict__ B, int64_t ldb, int kc, int64_t rw,
+                                              int64_t nw, double* __restrict__ Pp)
+{
+    constexpr int NPB = round16(NP), JB = NPB / 16, KCOL = qtb_cols(NPB), JK = KCOL / 16;
+    const int wave = wave_index(), lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (w >= nw) return;
+    const int q = lane >> 4, p = lane & 15;
+    dbl4 acc[JB][JK];
+#pragma unroll
+    for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < JK; ++jb) acc[ib][jb] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int64_t r0 = w * rw, r1 = (r0 + rw) < m ? (r0 + rw) : m;
+    // B's columns start 16-byte aligned (aligned base, even ldb): 16-byte loads
+    const bool vec2 = ((reinterpret_cast<uintptr_t>(B) & 15) == 0) && ((ldb & 1) == 0);
+    for (int64_t g = r0; g < r1; g += 64) {
+        // Q1: rows g + 16 q .. + 15 of column 16 b + p (the workspace holds
+        // whole 64-row groups past m); B: the same rows of column 16 jb + p,
+        // columns past kc read column kc - 1 and rows past m row m - 1, then zeroed
+        float x[JB][16];
+#pragma unroll
+        for (int b = 0; b < JB; ++b) {
+            const float* src = Q1 + g + 16 * q + (int64_t)(16 * b + p) * ldq1;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float4 t = *reinterpret_cast<const float4*>(src + 4 * v);
+                x[b][4 * v] = t.x;
+                x[b][4 * v + 1] = t.y;
+                x[b][4 * v + 2] = t.z;
+                x[b][4 * v + 3] = t.w;
+            }
+        }
+        double y[JK][16];
+        const bool full = g + 64 <= m;
+#pragma unroll
+        for (int jb = 0; jb < JK; ++jb) {
+            const int c = 16 * jb + p, cc = c < kc ? c : kc - 1;
+            const double* col = B + (int64_t)cc * ldb;
+            if (full && vec2) {
+                // 16-byte loads: the lane's 16 rows are 128 consecutive bytes
+                const double2* src = reinterpret_cast<const double2*>(col + g + 16 * q);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const double2 t = src[v];
+                    y[jb][2 * v] = c < kc ? t.x : 0.0;
+                    y[jb][2 * v + 1] = c < kc ? t.y : 0.0;
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int64_t r = g + 16 * q + v;
+                    const int64_t rr = full ? r : (r < m ? r : m - 1);
+                    const double val = col[rr];
+                    y[jb][v] = (c < kc && (full || r < m)) ? val : 0.0;
+                }
+            }
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2)
+#pragma unroll
+            for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+                for (int jb = 0; jb < JK; ++jb) acc[ib][jb] = mfma16x16x4((double)x[ib][s2], y[jb][s2], acc[ib][jb]);
+    }
+    double* P = Pp + w * NPB * KCOL;
+#pragma unroll
+    for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < JK; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) P[(16 * ib + q + 4 * r) + (16 * jb + p) * NPB] = acc[ib][jb][r];
+}
+
+// Stage 1: block (x, g) sums partials [64 g, 64 g + 64) entry by entry (eight
+// interleaved accumulators, combined as a tree).
+template <int NP>
+__global__ void __launch_bounds__(256) k_psum64(const double* __restrict__ Pp, int64_t nw, double* __restrict__ Pq)
+{
+    constexpr int ENT = round16(NP) * qtb_cols(round16(NP));
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = blockIdx.y;
+    if (e >= ENT) return;
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int64_t w0 = 64 * g, wn = (nw - w0) < 64 ? (nw - w0) : 64;
+    for (int64_t u = 0; u < wn; ++u) a[u % 8] += Pp[(w0 + u) * ENT + e];
+    Pq[g * ENT + e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// Stage 2: one thread per entry merges the ng group sums as a binary counter.
+template <int NP>
+__global__ void __launch_bounds__(256) k_psum(const double* __restrict__ Pq, int64_t ng, double* __restrict__ P)
+{
+    constexpr int ENT = round16(NP) * qtb_cols(round16(NP));
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ENT) return;
+    double stack[32];
+    int64_t cnt = 0;
+    for (int64_t g = 0; g < ng; ++g) {
+        double cs = Pq[g * ENT + e];
+        int lvl = 0;
+        for (int64_t c = cnt; c & 1; c >>= 1) cs = stack[lvl++] + cs;
+        stack[lvl] = cs;
+        ++cnt;
+    }
+    double sum = 0.0;
+    for (int lvl = 0; cnt >> lvl; ++lvl)
+        if ((cnt >> lvl) & 1) sum = stack[lvl] + sum;
+    P[e] = sum;
+}
+
+// B(i, c) = sum_{j <= i} R2^{-1}(j, i) P(j, c) for i < n, c < kc.
+template <int NP>
+__global__ void __launch_bounds__(256) k_q1tb_finish(const double* __restrict__ P, const double* __restrict__ R2inv,
+                                                     int n, double* __restrict__ B, int64_t ldb, int kc)
+{
+    constexpr int NPB = round16(NP);
+    for (int e = threadIdx.x; e < n * kc; e += blockDim.x) {
+        const int i = e % n, c = e / n;
+        double acc = 0.0;
+        for (int j = 0; j <= i; ++j) acc = fma(R2inv[j + i * NPB], P[j + c * NPB], acc);
+        B[i + (int64_t)c * ldb] = acc;
+    }
+}
+
+template <int NP>
+hipError_t qtb_mixed_np(const Layout& L, double* ws, int64_t k, double* B, int64_t ldb, hipStream_t s)
+{
+    constexpr int NPB = round16(NP), KCOL = qtb_cols(NPB), ENT = NPB * KCOL;
+    static_assert(ENT <= NPB * NPB || NPB == 16, "the partial products fit the Gram areas");
+    const float* Q1 = reinterpret_cast<const float*>(ws + L.off_Q1);
+    const int64_t ng = (L.gram_waves + 63) / 64;
+    for (int64_t c0 = 0; c0 < k; c0 += KCOL) {
+        const int kc = (int)((k - c0) < KCOL ? (k - c0) : KCOL);
+        double* Bc = B + c0 * ldb;
+        hipLaunchKernelGGL((k_q1tb<NP>), dim3(grid_for(L.gram_waves, 4)), dim3(256), 0, s, Q1, L.ld32, L.m, Bc,
+                           ldb, kc, L.gram_rows, L.gram_waves, ws + L.off_Gp);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL((k_psum64<NP>), dim3((ENT + 255) / 256, (unsigned)ng), dim3(256), 0, s, ws + L.off_Gp,
+                               L.gram_waves, ws + L.off_Gq);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL((k_psum<NP>), dim3((ENT + 255) / 256), dim3(256), 0, s, ws + L.off_Gq, ng,
+                               ws + L.off_G);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL((k_q1tb_finish<NP>), dim3(1), dim3(256), 0, s, ws + L.off_G, ws + L.off_R2inv,
+                               (int)L.n, Bc, ldb, kc);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace detail
 
 template <int NP>
@@ -3057,6 +3228,11 @@ hipError_t reorth_q_np(const Layout& L, double* ws, double* Q, int64_t ldq, hipS
 {
     return detail::reorth_q_np<NP>(L, ws, Q, ldq, s);
 }
+template <int NP>
+hipError_t qtb_mixed_np(const Layout& L, double* ws, int64_t k, double* B, int64_t ldb, hipStream_t s)
+{
+    return detail::qtb_mixed_np<NP>(L, ws, k, B, ldb, s);
+}
 
 template <int NP>
 hipError_t batch_factor_np(const BatchClass& C, const BatchProblem* probs, const BatchArgs* args, double* ws,
@@ -3100,6 +3276,7 @@ hipError_t batch_form_q_mixed_np(const BatchClass& C, const BatchProblem* probs,
     template hipError_t form_q1_np<NP>(const Layout&, double*, hipStream_t);                                   \
     template hipError_t reorth_np<NP>(const Layout&, double*, double*, int64_t, hipStream_t);                  \
     template hipError_t reorth_q_np<NP>(const Layout&, double*, double*, int64_t, hipStream_t);                \
+    template hipError_t qtb_mixed_np<NP>(const Layout&, double*, int64_t, double*, int64_t, hipStream_t);       \
     template hipError_t batch_factor_np<NP>(const BatchClass&, const BatchProblem*, const BatchArgs*, double*,  \
                                             bool, int, hipStream_t);                                          \
     template hipError_t batch_form_q_np<NP>(const BatchClass&, const BatchProblem*, const BatchArgs*, double*,  \

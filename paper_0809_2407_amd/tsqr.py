@@ -172,10 +172,12 @@ class Plan:
         check("tsqr_mixed_q1", self._lib.tsqr_mixed_q1(self._h, Q1.data_ptr(), _ld(Q1, self.m, "Q1", torch.float32)))
         return Q1
 
-    def apply_qt(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
-        lda = _ld(A, self.m, "A")
+    def apply_qt(self, A: Optional[torch.Tensor], B: torch.Tensor) -> torch.Tensor:
+        """tsqr_apply_qt, B in place.  A is the factored matrix (FP64 plans); a
+        MIXED plan takes A = None and writes Q^T B into the top n rows of B."""
+        aptr, lda = (A.data_ptr(), _ld(A, self.m, "A")) if A is not None else (0, self.m)
         ldb = _ld(B, self.m, "B")
-        check("tsqr_apply_qt", self._lib.tsqr_apply_qt(self._h, A.data_ptr(), lda, B.shape[1], B.data_ptr(), ldb))
+        check("tsqr_apply_qt", self._lib.tsqr_apply_qt(self._h, aptr, lda, B.shape[1], B.data_ptr(), ldb))
         return B
 
 

@@ -117,25 +117,55 @@ def test_mixed_r_only_and_tiny():
         assert orthogonality(Q) <= ORTH_MIXED
 
 
-def test_mixed_rejects_apply_qt_and_matches_fp64_plan():
+def test_mixed_q1_is_refused_on_an_fp64_plan():
     torch = need_gpu()
     from paper_0809_2407_amd import tsqr as T
     from paper_0809_2407_amd._lib import TsqrError
 
-    A = synth.gaussian(8000, 16, seed=905)
-    Ad = T.to_colmajor(torch.from_numpy(A))
-    B = T.colmajor(8000, 2)
-    announce("mixed apply_qt unsupported")
-    with T.Plan(8000, 16, precision="mixed") as p:
-        p.factor(Ad)
-        with pytest.raises(TsqrError) as e:
-            p.apply_qt(Ad, B)
-        assert e.value.status == 3
+    announce("mixed_q1 on an FP64 plan")
     with T.Plan(8000, 16) as p:
         with pytest.raises(TsqrError) as e:
             p.mixed_q1()
         assert e.value.status == 3
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("m,n,k,ldb_pad,decades", [(8000, 16, 2, 0, 0), (20000, 17, 33, 5, 6), (9001, 8, 40, 0, 0),
+                                                   (30000, 64, 32, 3, 6), (4100, 33, 1, 0, 0), (70, 9, 5, 0, 0)])
+def test_mixed_apply_qt(m, n, k, ldb_pad, decades):
+    """Q^T B on a MIXED plan: the top n rows against the plan's own explicit Q
+    (Q^T B in FP64 on the host; the same Q1 R2^{-1}), the other rows
+    untouched, and, on well-conditioned inputs, against the FP64 oracle's
+    Q^T B within the mixed bound (the same space, the same sign convention;
+    at kappa = 1e6 the FP32 pass moves the space by about kappa times its
+    rounding, so only the plan's own Q is the reference there)."""
+    torch = need_gpu()
+    from paper_0809_2407_amd import tsqr as T
+
+    if decades:
+        A, _ = synth.prescribed_sigma(m, n, seed=960 + n, decades=decades)
+    else:
+        A = synth.gaussian(m, n, seed=960 + n)
+    B = synth.gaussian(m, k, seed=961 + k)
+    Ad = T.to_colmajor(torch.from_numpy(A))
+    Bd = T.colmajor(m, k, ld=m + ldb_pad)
+    Bd.copy_(torch.from_numpy(B))
+    announce(f"mixed apply_qt {m}x{n} k={k} ldb=m+{ldb_pad}")
+    with T.Plan(m, n, precision="mixed") as p:
+        p.factor(Ad)
+        Q = p.form_q(None)
+        p.apply_qt(None, Bd)
+        torch.cuda.synchronize()
+        reorth = p.info()["reorth_applied"]
+    X, Qh = Bd.cpu().numpy(), Q.cpu().numpy()
+    scale = np.linalg.norm(B)
+    assert np.abs(X[:n] - Qh.T @ B).max() <= 1e-13 * scale
+    assert np.array_equal(X[n:], B[n:])
+    if decades == 0:
+        # well conditioned: the FP32 pass moves Q by about its rounding
+        Qo = oracle.qr_reference(A, want_q=True)[1]
+        assert np.abs(X[:n] - Qo.T @ B).max() <= 10 * BWD_MIXED * scale
+    del reorth
 
 
 def test_mixed_leading_dimensions_and_q_over_a():
