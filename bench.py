@@ -436,6 +436,59 @@ def mixed_vs_fp64(args, steps: int, warmup: int) -> dict:
     return out
 
 
+def krylov_mixed_vs_fp64(args, steps: int, warmup: int) -> dict:
+    """The s-step Krylov basis (2-D Laplacian on a 2048 x 2048 grid, n = 17):
+    R, the explicit Q and Q^T B on 32 right-hand sides, FP64 path against the
+    mixed path, each with its accuracy against its stated bounds and the top n
+    rows of Q^T B against Q^T B formed from the plan's own explicit Q."""
+    import torch
+    from paper_0809_2407_amd import tsqr as T
+
+    w = dict(WORKLOADS["tsqr_fp64_rq_qtb_krylov_m4194304_n17_k32"])
+    m, n, k = w["m"], w["n"], w["rhs"]
+    log(f"Krylov mixed vs FP64: m = {m}, n = {n}, {k} right-hand sides, generating input")
+    A, _ = make_input(w, args.seed)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(args.seed + 1)
+    B0 = torch.randn((k, m), generator=g, device="cuda", dtype=torch.float64).t()
+    B = T.colmajor(m, k)
+    Q = T.colmajor(m, n)
+    fl = flops_rq(m, n) + 4.0 * m * n * k
+    out = {"workload": "krylov_rq_qtb_m4194304_n17_k32", "m": m, "n": n, "rhs": k, "seed": args.seed,
+           "steps": steps, "warmup": warmup, "flops_credited": fl,
+           "note": "FP64 Q^T B transforms all m rows (the tree's full orthogonal factor); the mixed Q = Q1 R2^-1 "
+                   "has no complement, so only its top n rows are written"}
+    for prec in ("fp64", "mixed"):
+        plan = T.Plan(m, n, precision=prec)
+        V = T.colmajor(m, n) if prec == "fp64" else None
+        R = T.colmajor(n, n)
+
+        def step():
+            plan.factor_into(A, V, R)
+            plan.form_q(V, Q)
+            B.copy_(B0)
+            plan.apply_qt(V, B)
+
+        ms_step, ph = time_steps(step, plan, steps, warmup)
+        acc = accuracy_of(A, Q, R)
+        with torch.no_grad():
+            acc["qtb_vs_explicit_q"] = float((B[:n] - Q.t().matmul(B0)).abs().max() / torch.linalg.norm(B0))
+        rec = {"ms_per_step": ms_step, "value": fl / (ms_step * 1e-3) / 1e9, "unit": "GFLOP/s",
+               "phases_ms": phase_means(ph), "accuracy": acc,
+               "bounds": MIXED_BOUNDS if prec == "mixed" else fp64_bounds(n)}
+        log(f"Krylov {prec}: {ms_step:.3f} ms/step, accuracy {acc}")
+        out[prec] = rec
+        plan.close()
+        del V, R
+    out["mixed_speedup"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    for prec in ("fp64", "mixed"):
+        a, b = out[prec]["accuracy"], out[prec]["bounds"]
+        out[prec]["within_bounds"] = all(a[kk] <= b[kk] for kk in b if kk in a)
+    del A, B, B0, Q
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_record(args, count: int, m_lo: int, m_hi: int, ns, precision: str, steps: int, warmup: int,
                    loop_steps: int, sample_oracle: bool, state=None) -> dict:
     """One batched plan (captured graph) over `count` problems, R and explicit
@@ -592,6 +645,7 @@ def main(argv=None) -> int:
     result = run_single(args, args.workload, cpu=not args.no_cpu_baseline, check=not args.no_check)
     if args.workload == DEFAULT and not args.no_extras:
         result["mixed_vs_fp64"] = mixed_vs_fp64(args, steps=min(args.steps, 10), warmup=2)
+        result["krylov_mixed_vs_fp64"] = krylov_mixed_vs_fp64(args, steps=min(args.steps, 10), warmup=2)
         w = BATCHED["tsqr_batched_fp64_rq_p2048_m1000_200000_n8_64"]
         fp64, state = batched_record(args, w["count"], w["m_lo"], w["m_hi"], w["ns"], "fp64", steps=3, warmup=1,
                                      loop_steps=2, sample_oracle=not args.no_cpu_baseline)
