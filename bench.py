@@ -146,6 +146,16 @@ def measured_traffic(m: int, n: int, kernel: str):
 
 
 def cpu_model() -> str:
+    """The host CPU's model string, as lscpu reports it (else /proc/cpuinfo)."""
+    import subprocess
+
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
@@ -155,11 +165,14 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(A_dev, info: dict, sample_rows: int, mode: str, one_thread_rows: int = 1 << 20):
+def cpu_baseline(A_dev, info: dict, sample_rows: int, mode: str, one_thread_rows: int = 1 << 20,
+                 k_rhs: int = 32, seed: int = 0):
     """The oracle as it stands, on the first sample_rows rows of the same input,
     on the host cores (tree of the same shape: same leaf and tile rows), and
-    on one core over the first one_thread_rows rows.  Returns the record and
-    the oracle's R of the sample."""
+    on one core over the first one_thread_rows rows.  Three legs on the same
+    input: the factorisation with R (R only), then the explicit Q (factor +
+    form_q), then Q^T B on k_rhs host-generated columns.  Returns the record
+    and the oracle's R of the sample."""
     import numpy as np
 
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
@@ -170,28 +183,37 @@ def cpu_baseline(A_dev, info: dict, sample_rows: int, mode: str, one_thread_rows
     As = np.asfortranarray(A_dev[:ms].cpu().numpy())
     threads = oracle.num_threads()
 
-    def run(X):
+    def legs(X):
+        rows = X.shape[0]
         t0 = time.perf_counter()
         t = oracle.TSQR(X, info["leaf_rows"], info["tile_rows"])
-        if mode == "rq":
-            t.form_q()
         R = t.R()
-        return R, time.perf_counter() - t0
+        t1 = time.perf_counter()
+        t.form_q()
+        t2 = time.perf_counter()
+        B = np.asfortranarray(np.random.default_rng(seed).standard_normal((rows, k_rhs)))
+        t3 = time.perf_counter()
+        t.apply_qt(B)
+        t4 = time.perf_counter()
+        rec = {"r_only": {"gflops": flops_r(rows, n) / (t1 - t0) / 1e9, "s": t1 - t0},
+               "factor_form_q": {"gflops": flops_rq(rows, n) / (t2 - t0) / 1e9, "s": t2 - t0},
+               f"apply_qt_k{k_rhs}": {"gflops": 4.0 * rows * n * k_rhs / (t4 - t3) / 1e9, "s": t4 - t3}}
+        return R, rec
 
-    Ro, dt = run(As)
-    fl = flops_rq(ms, n) if mode == "rq" else flops_r(ms, n)
+    Ro, lg = legs(As)
     m1 = min(ms, one_thread_rows)
     oracle.set_num_threads(1)
     try:
-        _, dt1 = run(np.asfortranarray(As[:m1]))
+        _, lg1 = legs(np.asfortranarray(As[:m1]))
     finally:
         oracle.set_num_threads(threads)
-    fl1 = flops_rq(m1, n) if mode == "rq" else flops_r(m1, n)
+    key = "factor_form_q" if mode == "rq" else "r_only"
     what = "R + explicit Q" if mode == "rq" else "R only"
-    rec = {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-           "sample": f"first {ms} of {m} rows (x{n}), same leaf/tile rows, {what}, {dt:.2f} s",
-           "one_thread": {"value": fl1 / dt1 / 1e9, "unit": "GFLOP/s", "cores": 1,
-                          "sample": f"first {m1} rows, {what}, {dt1:.2f} s"},
+    rec = {"value": lg[key]["gflops"], "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {ms} of {m} rows (x{n}), same leaf/tile rows, {what}, {lg[key]['s']:.2f} s",
+           "legs": lg,
+           "one_thread": {"value": lg1[key]["gflops"], "unit": "GFLOP/s", "cores": 1,
+                          "sample": f"first {m1} rows, {what}, {lg1[key]['s']:.2f} s", "legs": lg1},
            "host": {"nproc": os.cpu_count(), "model": cpu_model()}}
     return rec, Ro
 
@@ -252,22 +274,30 @@ def oracle_r_only(A_dev, leaf_rows: int, tile_rows: int):
 
 def time_steps(step, plan, steps: int, warmup: int):
     """W untimed steps, then K timed ones bracketed by device synchronisation;
-    per-phase device times from the plan's HIP events over the timed steps."""
+    per-phase device times from the plan's HIP events over the timed steps,
+    and each step's device time from events on the plan's stream between the
+    steps."""
     import torch
 
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     plan.profile(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    ev[0].record(plan.stream)
+    for i in range(steps):
         step()
+        ev[i + 1].record(plan.stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ph = plan.timings()
     plan.profile(False)
-    return (t1 - t0) * 1e3 / steps, ph
+    per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    stats = {"median": per[len(per) // 2] if len(per) % 2 else 0.5 * (per[len(per) // 2 - 1] + per[len(per) // 2]),
+             "min": per[0], "max": per[-1], "timing": "HIP events on the plan's stream between steps"}
+    return (t1 - t0) * 1e3 / steps, ph, stats
 
 
 def phase_means(ph: dict) -> dict:
@@ -312,7 +342,7 @@ def run_single(args, wname: str, cpu: bool, check: bool):
         torch.cuda.synchronize()
         del Cdst
         log(f"calibration copy: {8 * m * n} bytes read, {8 * m * n} bytes written")
-    ms_step, ph = time_steps(step, plan, args.steps, args.warmup)
+    ms_step, ph, step_stats = time_steps(step, plan, args.steps, args.warmup)
     log(f"timed {args.steps} steps: {ms_step:.4f} ms/step; phases {ph}")
 
     fl = flops_rq(m, n) if mode == "rq" else flops_r(m, n)
@@ -354,7 +384,10 @@ def run_single(args, wname: str, cpu: bool, check: bool):
                    "num_leaves": info["num_leaves"], "tree_levels": info["tree_levels"],
                    "leaf_kind": info["leaf_kind"], "parallelism": "single GPU"},
         "roofline": roofline,
+        "step_ms": step_stats,
         "path_roofline": {"t_roof_ms": t_roof * 1e3, "frac": t_roof * 1e3 / ms_step,
+                          "frac_median": t_roof * 1e3 / step_stats["median"],
+                          "frac_min": t_roof * 1e3 / step_stats["min"],
                           "bytes": path_bytes, "flops": fl},
         "phases_ms": phase_means(ph),
     }
@@ -366,7 +399,7 @@ def run_single(args, wname: str, cpu: bool, check: bool):
     result["cpu_baseline"] = None
     if cpu:
         log("cpu baseline (oracle on host cores)")
-        rec, Ro = cpu_baseline(A, info, args.cpu_sample_rows, mode)
+        rec, Ro = cpu_baseline(A, info, args.cpu_sample_rows, mode, seed=args.seed + 2)
         result["cpu_baseline"] = rec
         if Ro.shape[0] == n and args.cpu_sample_rows >= m:
             result.setdefault("accuracy", {})["R_vs_oracle"] = r_vs_oracle(R, Ro)
@@ -375,6 +408,79 @@ def run_single(args, wname: str, cpu: bool, check: bool):
     del A, V, Q, R
     torch.cuda.empty_cache()
     return result
+
+
+def measured_peaks(reps: int = 10) -> dict:
+    """The part's own ceilings from libtsqr_peaks: a streaming copy and a
+    streaming read with 16-byte accesses over 1 GiB buffers (far beyond the
+    caches), and FP64 FMA and FP64 MFMA loops; best and median of `reps`
+    launches timed with HIP events on the current stream, each launch's output
+    checked against its exact value."""
+    import torch
+    from paper_0809_2407_amd import peaks as PK
+
+    st = torch.cuda.current_stream()
+    nb = 1 << 30
+    src = torch.empty(nb // 8, dtype=torch.float64, device="cuda").uniform_(-1.0, 1.0)
+    dst = torch.empty_like(src)
+    g0, g1 = PK.default_grid(1, nb), PK.default_grid(2)
+    partial = torch.empty(g0, dtype=torch.float64, device="cuda")
+    out = torch.empty(g1 * 256, dtype=torch.float64, device="cuda")
+
+    def timed(fn):
+        fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(st)
+            fn()
+            b.record(st)
+        torch.cuda.synchronize()
+        t = sorted(a.elapsed_time(b) for a, b in ev)
+        return t[0], t[len(t) // 2]
+
+    def rate(amount, ms_pair, scale):
+        return {"best": amount / (ms_pair[0] * 1e-3) / scale, "median": amount / (ms_pair[1] * 1e-3) / scale,
+                "ms_best": ms_pair[0], "ms_median": ms_pair[1]}
+
+    res = {}
+    t = timed(lambda: PK.copy(src, dst))
+    res["copy"] = dict(rate(2.0 * nb, t, 1e9), unit="GB/s", bytes=2 * nb, ok=bool(torch.equal(src, dst)))
+    del dst
+    t = timed(lambda: PK.read(src, partial))
+    total = float(src.sum())
+    res["read"] = dict(rate(1.0 * nb, t, 1e9), unit="GB/s", bytes=nb,
+                       ok=abs(float(partial.sum()) - total) <= 1e-9 * float(src.abs().sum()))
+    del src
+    it_fma = 100000
+    t = timed(lambda: PK.fma(out, it_fma))
+    res["fp64_fma"] = dict(rate(16.0 * it_fma * g1 * 256, t, 1e12), unit="TFLOP/s", iters=it_fma,
+                           ok=bool((out == 28.0 + 8.0 * it_fma).all()))
+    it_mfma = 1000
+    t = timed(lambda: PK.mfma(out, it_mfma))
+    res["fp64_mfma"] = dict(rate(131072.0 * it_mfma * g1 * 4, t, 1e12), unit="TFLOP/s", iters=it_mfma,
+                            ok=bool((out == 256.0 * it_mfma).all()))
+    res["grids"] = {"copy": PK.default_grid(0, nb), "read": g0, "loops": g1, "block": 256}
+    res["datasheet"] = {"hbm_GBps": HBM_PEAK_GBS, "fp64_TFLOPs": FP64_PEAK_TFLOPS}
+    del partial, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def against_measured(result: dict, pk: dict) -> None:
+    """Roofline fractions against the measured ceilings (copy rate for bytes,
+    the faster FP64 loop for flops), beside the datasheet ones."""
+    if not (pk["copy"]["ok"] and pk["fp64_mfma"]["ok"] and pk["fp64_fma"]["ok"]):
+        return
+    bw = pk["copy"]["best"]
+    fl_rate = max(pk["fp64_mfma"]["best"], pk["fp64_fma"]["best"]) * 1e12
+    rf = result.get("roofline")
+    if rf and rf.get("unit") == "GB/s":
+        rf["frac_of_measured_copy"] = rf["achieved"] / bw
+    pr = result.get("path_roofline")
+    if pr and "flops" in pr:
+        t = max(pr["flops"] / fl_rate, pr["bytes"] / (bw * 1e9)) * 1e3
+        pr["measured_peaks"] = {"t_roof_ms": t, "frac": t / result["ms_per_step"],
+                                "frac_median": t / result["step_ms"]["median"] if "step_ms" in result else None}
 
 
 def mixed_vs_fp64(args, steps: int, warmup: int) -> dict:
@@ -402,9 +508,10 @@ def mixed_vs_fp64(args, steps: int, warmup: int) -> dict:
             plan.factor_into(A, V, R)
             plan.form_q(V, Q)
 
-        ms_step, ph = time_steps(step, plan, steps, warmup)
+        ms_step, ph, step_stats = time_steps(step, plan, steps, warmup)
         acc = accuracy_of(A, Q, R)
-        rec = {"ms_per_step": ms_step, "value": flops_rq(m, n) / (ms_step * 1e-3) / 1e9, "unit": "GFLOP/s",
+        rec = {"ms_per_step": ms_step, "step_ms": step_stats,
+               "value": flops_rq(m, n) / (ms_step * 1e-3) / 1e9, "unit": "GFLOP/s",
                "phases_ms": phase_means(ph), "accuracy": acc,
                "bounds": MIXED_BOUNDS if prec == "mixed" else fp64_bounds(n),
                "leaf_rows": info["leaf_rows"], "tile_rows": info["tile_rows"]}
@@ -469,12 +576,12 @@ def krylov_mixed_vs_fp64(args, steps: int, warmup: int) -> dict:
             B.copy_(B0)
             plan.apply_qt(V, B)
 
-        ms_step, ph = time_steps(step, plan, steps, warmup)
+        ms_step, ph, step_stats = time_steps(step, plan, steps, warmup)
         acc = accuracy_of(A, Q, R)
         with torch.no_grad():
             acc["qtb_vs_explicit_q"] = float((B[:n] - Q.t().matmul(B0)).abs().max() / torch.linalg.norm(B0))
-        rec = {"ms_per_step": ms_step, "value": fl / (ms_step * 1e-3) / 1e9, "unit": "GFLOP/s",
-               "phases_ms": phase_means(ph), "accuracy": acc,
+        rec = {"ms_per_step": ms_step, "step_ms": step_stats, "value": fl / (ms_step * 1e-3) / 1e9,
+               "unit": "GFLOP/s", "phases_ms": phase_means(ph), "accuracy": acc,
                "bounds": MIXED_BOUNDS if prec == "mixed" else fp64_bounds(n)}
         log(f"Krylov {prec}: {ms_step:.3f} ms/step, accuracy {acc}")
         out[prec] = rec
@@ -621,6 +728,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 24)
     ap.add_argument("--no-check", action="store_true", help="skip the accuracy check after timing")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip measuring the part's copy, read, FMA and MFMA ceilings")
     ap.add_argument("--no-extras", action="store_true",
                     help="the default workload only (no mixed-vs-FP64 or batched records)")
     ap.add_argument("--leaf-kind", default="auto", choices=["auto", "compact_wy", "recursive"],
@@ -643,6 +752,12 @@ def main(argv=None) -> int:
     if args.workload in BATCHED:
         return run_batched(args)
     result = run_single(args, args.workload, cpu=not args.no_cpu_baseline, check=not args.no_check)
+    if not args.no_peaks:
+        log("measured ceilings: copy, read, FP64 FMA and MFMA loops")
+        pk = measured_peaks()
+        log(f"measured ceilings {pk}")
+        result["measured_peaks"] = pk
+        against_measured(result, pk)
     if args.workload == DEFAULT and not args.no_extras:
         result["mixed_vs_fp64"] = mixed_vs_fp64(args, steps=min(args.steps, 10), warmup=2)
         result["krylov_mixed_vs_fp64"] = krylov_mixed_vs_fp64(args, steps=min(args.steps, 10), warmup=2)

@@ -4,7 +4,10 @@
     python -m paper_0809_2407_amd.build --np 32    # one padded column count (fast experiments)
 
 Every HIP unit is compiled with hipcc for gfx950 only; the kernel units are
-compiled in parallel and linked into ``paper_0809_2407_amd/libtsqr.so``.
+compiled in parallel and linked into ``paper_0809_2407_amd/libtsqr.so``.  The
+full build also makes ``paper_0809_2407_amd/libtsqr_peaks.so`` (calib/: the
+copy, read, FMA and MFMA loops that measure the part's ceilings), which the
+TSQR library does not link.
 """
 from __future__ import annotations
 
@@ -20,6 +23,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtsqr.so")
+PEAKS_SRC = os.path.join(HERE, "calib", "tsqr_peaks.hip")
+PEAKS_LIB = os.path.join(HERE, "libtsqr_peaks.so")
 
 UNITS = ["tsqr_np_0.hip", "tsqr_np_1.hip", "tsqr_np_2.hip", "tsqr_np_3.hip",
          "tsqr_dispatch.hip", "tsqr_noalloc.hip", "tsqr_cmp.hip", "tsqr_api.cpp", "tsqr_batched.cpp",
@@ -41,8 +46,21 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found: the ROCm toolchain is required to build libtsqr")
 
 
+def build_peaks(verbose: bool = False) -> str:
+    cmd = [_hipcc()] + COMMON + ["-shared", "-x", "hip", PEAKS_SRC, "-o", PEAKS_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {PEAKS_SRC}:\n{r.stderr[-4000:]}")
+    os.replace(PEAKS_LIB + ".tmp", PEAKS_LIB)
+    return PEAKS_LIB
+
+
 def build(only_np: int | None = None, jobs: int | None = None, verbose: bool = False) -> str:
     hipcc = _hipcc()
+    if not only_np:
+        build_peaks(verbose)
     tmp = tempfile.mkdtemp(prefix="tsqr_build_")
     defs = [f"-DTSQR_ONLY_NP={only_np}"] if only_np else []
     objs = []
