@@ -410,12 +410,14 @@ def run_single(args, wname: str, cpu: bool, check: bool):
     return result
 
 
-def measured_peaks(reps: int = 10) -> dict:
+def measured_peaks(reps: int = 10, geom=None) -> dict:
     """The part's own ceilings from libtsqr_peaks: a streaming copy and a
     streaming read with 16-byte accesses over 1 GiB buffers (far beyond the
     caches), and FP64 FMA and FP64 MFMA loops; best and median of `reps`
     launches timed with HIP events on the current stream, each launch's output
-    checked against its exact value."""
+    checked against its exact value.  With geom = (m, n, leaf_rows, tile_rows),
+    also a copy of an m x n matrix in the access pattern of the Q kernel at that
+    geometry (16mn bytes)."""
     import torch
     from paper_0809_2407_amd import peaks as PK
 
@@ -459,6 +461,18 @@ def measured_peaks(reps: int = 10) -> dict:
     t = timed(lambda: PK.mfma(out, it_mfma))
     res["fp64_mfma"] = dict(rate(131072.0 * it_mfma * g1 * 4, t, 1e12), unit="TFLOP/s", iters=it_mfma,
                             ok=bool((out == 256.0 * it_mfma).all()))
+    if geom is not None:
+        from paper_0809_2407_amd import tsqr as T
+
+        m, n, leaf_rows, tile_rows = geom
+        X = T.colmajor(m, n)
+        X.copy_(torch.rand((n, m), device="cuda", dtype=torch.float64).t())
+        Y = T.colmajor(m, n)
+        t = timed(lambda: PK.copy_leaf(X, Y, leaf_rows, tile_rows))
+        res["copy_in_q_pattern"] = dict(rate(16.0 * m * n, t, 1e9), unit="GB/s", bytes=16 * m * n,
+                                        m=m, n=n, leaf_rows=leaf_rows, tile_rows=tile_rows,
+                                        ok=bool(torch.equal(X, Y)))
+        del X, Y
     res["grids"] = {"copy": PK.default_grid(0, nb), "read": g0, "loops": g1, "block": 256}
     res["datasheet"] = {"hbm_GBps": HBM_PEAK_GBS, "fp64_TFLOPs": FP64_PEAK_TFLOPS}
     del partial, out
@@ -476,6 +490,14 @@ def against_measured(result: dict, pk: dict) -> None:
     rf = result.get("roofline")
     if rf and rf.get("unit") == "GB/s":
         rf["frac_of_measured_copy"] = rf["achieved"] / bw
+    cq = pk.get("copy_in_q_pattern")
+    ph = result.get("phases_ms", {})
+    cfg = result.get("config", {})
+    if cq and cq["ok"] and ph.get("form_q") and result.get("dtype") == "f64" and cfg.get("mode") == "rq":
+        q_rate = 16.0 * cfg["m"] * cfg["n"] / (ph["form_q"] * 1e-3) / 1e9
+        result["q_kernel"] = {"ms": ph["form_q"], "GBps": q_rate, "bytes": 16.0 * cfg["m"] * cfg["n"],
+                              "frac_of_copy_in_its_pattern": q_rate / cq["best"],
+                              "frac_of_measured_copy": q_rate / bw}
     pr = result.get("path_roofline")
     if pr and "flops" in pr:
         t = max(pr["flops"] / fl_rate, pr["bytes"] / (bw * 1e9)) * 1e3
@@ -754,7 +776,9 @@ def main(argv=None) -> int:
     result = run_single(args, args.workload, cpu=not args.no_cpu_baseline, check=not args.no_check)
     if not args.no_peaks:
         log("measured ceilings: copy, read, FP64 FMA and MFMA loops")
-        pk = measured_peaks()
+        c = result["config"]
+        geom = (c["m"], c["n"], c["leaf_rows"], c["tile_rows"]) if c.get("mode") == "rq" else None
+        pk = measured_peaks(geom=geom)
         log(f"measured ceilings {pk}")
         result["measured_peaks"] = pk
         against_measured(result, pk)

@@ -45,6 +45,18 @@ int tsqr_peak_copy(const void* src, void* dst, int64_t bytes, int grid, void* st
  * size is returned by tsqr_peak_grid(1, bytes)).  HBM traffic: bytes. */
 int tsqr_peak_read(const void* src, int64_t bytes, double* partial, int grid, void* stream);
 
+/* Copy of the column-major m x n matrix src (leading dimension lds) into dst
+ * (ldd) in the access pattern of the TSQR Q kernel, without its arithmetic:
+ * one wavefront per leaf of leaf_rows rows (floor(m / leaf_rows) leaves, at
+ * least one, the last taking the remaining rows), its tiles of tile_rows rows
+ * walked from the last to the first, 16 rows at a time, lane 16 g + r moving
+ * row r of those in columns 4 k + g.  Requirements: lds, ldd >= m >= 1,
+ * 1 <= n <= 64, tile_rows a positive multiple of 16, leaf_rows a multiple of
+ * tile_rows, the two matrices disjoint (-3 otherwise).  The ceiling of that
+ * access pattern at that concurrency.  HBM traffic: 16 m n bytes. */
+int tsqr_peak_copy_leaf(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t m, int n,
+                        int64_t leaf_rows, int tile_rows, void* stream);
+
 /* FP64 FMA loop on the vector ALU: every thread runs `iters` rounds of eight
  * independent chains x <- fma(x, c, d) started at x = 0 .. 7 and writes the
  * sum of the eight results to out[thread] (grid * 256 doubles).  With c = 1,

@@ -65,6 +65,42 @@ __global__ __launch_bounds__(kBlock) void k_read16(const d2* __restrict__ src, s
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// A copy in the access pattern of the TSQR Q kernel: wavefront w owns the rows
+// of leaf w (leaf_rows each, the last leaf takes the rest), walks its tiles of
+// tile_rows rows from the last to the first and moves each 16 rows at a time;
+// lane 16 g + r moves row r of those 16 in columns 4 k + g (k < NK).  All of a
+// block's loads are issued before its stores, as there.
+template <int NK>
+__global__ __launch_bounds__(kBlock) void k_copy_leaf(const double* __restrict__ src, int64_t lds,
+                                                      double* __restrict__ dst, int64_t ldd, int64_t m, int n,
+                                                      int64_t leaf_rows, int tile_rows, int64_t leaves)
+{
+    const int64_t leaf = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (leaf >= leaves) return;
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const int64_t row0 = leaf * leaf_rows;
+    const int64_t rend = leaf == leaves - 1 ? m : row0 + leaf_rows;
+    const int64_t ntl = (rend - row0 + tile_rows - 1) / tile_rows;
+    for (int64_t t = ntl - 1; t >= 0; --t) {
+        const int64_t t0 = row0 + t * tile_rows;
+        const int64_t tend = t0 + tile_rows < rend ? t0 + tile_rows : rend;
+        for (int64_t b = t0; b < tend; b += 16) {
+            const int64_t row = b + r;
+            double y[NK];
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                const int c = 4 * k + g;
+                y[k] = (row < tend && c < n) ? src[row + (int64_t)c * lds] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                const int c = 4 * k + g;
+                if (row < tend && c < n) dst[row + (int64_t)c * ldd] = y[k];
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fma_loop(double* __restrict__ out, int iters, double c, double d) {
     double x[8];
 #pragma unroll
@@ -153,6 +189,34 @@ int tsqr_peak_read(const void* src, int64_t bytes, double* partial, int grid, vo
     const int g = pick_grid(grid, 1, bytes);
     hipLaunchKernelGGL(k_read16, dim3(g), dim3(kBlock), 0, (hipStream_t)stream, (const d2*)src,
                        (size_t)(bytes / 16), partial);
+    return launched();
+}
+
+int tsqr_peak_copy_leaf(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t m, int n,
+                        int64_t leaf_rows, int tile_rows, void* stream)
+{
+    if (!src) return -1;
+    if (lds < m) return -2;
+    if (!dst) return -3;
+    if (ldd < m) return -4;
+    if (m < 1) return -5;
+    if (n < 1 || n > 64) return -6;
+    if (tile_rows < 16 || tile_rows % 16 != 0) return -8;
+    if (leaf_rows < tile_rows || leaf_rows % tile_rows != 0) return -7;
+    const char* s0 = (const char*)src;
+    const char* s1 = (const char*)(src + (n - 1) * lds + m);
+    const char* d0 = (const char*)dst;
+    const char* d1 = (const char*)(dst + (n - 1) * ldd + m);
+    if (s0 < d1 && d0 < s1) return -3;
+    const int64_t leaves = m / leaf_rows > 0 ? m / leaf_rows : 1;
+    const int64_t grid = (leaves + kBlock / 64 - 1) / (kBlock / 64);
+    if (grid > ((int64_t)1 << 31) - 1) return -7;
+    const hipStream_t st = (hipStream_t)stream;
+    const dim3 g((unsigned)grid), b(kBlock);
+    if (n <= 8) hipLaunchKernelGGL(k_copy_leaf<2>, g, b, 0, st, src, lds, dst, ldd, m, n, leaf_rows, tile_rows, leaves);
+    else if (n <= 16) hipLaunchKernelGGL(k_copy_leaf<4>, g, b, 0, st, src, lds, dst, ldd, m, n, leaf_rows, tile_rows, leaves);
+    else if (n <= 32) hipLaunchKernelGGL(k_copy_leaf<8>, g, b, 0, st, src, lds, dst, ldd, m, n, leaf_rows, tile_rows, leaves);
+    else hipLaunchKernelGGL(k_copy_leaf<16>, g, b, 0, st, src, lds, dst, ldd, m, n, leaf_rows, tile_rows, leaves);
     return launched();
 }
 

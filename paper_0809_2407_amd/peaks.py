@@ -12,7 +12,8 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtsqr_peaks.so")
 
-EXPORTED = ["tsqr_peak_copy", "tsqr_peak_read", "tsqr_peak_fma", "tsqr_peak_mfma", "tsqr_peak_grid"]
+EXPORTED = ["tsqr_peak_copy", "tsqr_peak_read", "tsqr_peak_copy_leaf", "tsqr_peak_fma", "tsqr_peak_mfma",
+            "tsqr_peak_grid"]
 
 _lib = None
 
@@ -28,6 +29,7 @@ def load() -> ctypes.CDLL:
     c_int = ctypes.c_int
     lib.tsqr_peak_copy.argtypes = [dp, dp, i64, c_int, dp]
     lib.tsqr_peak_read.argtypes = [dp, i64, dp, c_int, dp]
+    lib.tsqr_peak_copy_leaf.argtypes = [dp, i64, dp, i64, i64, c_int, i64, c_int, dp]
     lib.tsqr_peak_fma.argtypes = [dp, c_int, c_int, d, d, dp]
     lib.tsqr_peak_mfma.argtypes = [dp, c_int, c_int, d, d, dp]
     lib.tsqr_peak_grid.argtypes = [c_int, i64]
@@ -77,6 +79,19 @@ def read(src: torch.Tensor, partial: torch.Tensor, grid: int = 0, stream=None) -
     g = grid if grid > 0 else default_grid(1, nb)
     _need(partial.is_contiguous() and partial.numel() >= g, f"read: partial needs {g} doubles")
     _check("tsqr_peak_read", load().tsqr_peak_read(src.data_ptr(), nb, partial.data_ptr(), grid, _stream(stream)))
+
+
+def copy_leaf(src: torch.Tensor, dst: torch.Tensor, leaf_rows: int, tile_rows: int, stream=None) -> None:
+    """tsqr_peak_copy_leaf between two column-major FP64 device matrices of one shape."""
+    _need(src.is_cuda and dst.is_cuda and src.dtype == torch.float64 and dst.dtype == torch.float64
+          and src.dim() == 2 and src.shape == dst.shape, "copy_leaf: two FP64 device matrices of one shape")
+    m, n = src.shape
+    for X in (src, dst):
+        _need(X.stride(0) == 1 and (n == 1 or X.stride(1) >= m), "copy_leaf: column-major matrices")
+    lds = src.stride(1) if n > 1 else m
+    ldd = dst.stride(1) if n > 1 else m
+    _check("tsqr_peak_copy_leaf", load().tsqr_peak_copy_leaf(src.data_ptr(), lds, dst.data_ptr(), ldd, m, n,
+                                                             leaf_rows, tile_rows, _stream(stream)))
 
 
 def fma(out: torch.Tensor, iters: int, c: float = 1.0, d: float = 1.0, grid: int = 0, stream=None) -> None:

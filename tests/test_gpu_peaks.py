@@ -48,3 +48,23 @@ def test_fma_and_mfma_loops(grid, iters):
     PK.mfma(out, iters, 1.5, -2.0, grid=grid)
     torch.cuda.synchronize()
     assert bool((out == 1024.0 * 1.5 * -2.0 * iters).all())
+
+
+@pytest.mark.parametrize("m,n,leaf_rows,tile_rows,pad", [(20000 + 37, 32, 2048, 128, 0), (9000, 17, 1024, 128, 5),
+                                                          (6000 + 3, 64, 512, 64, 0), (100, 5, 128, 16, 2),
+                                                          (15, 1, 64, 16, 0)])
+def test_copy_in_leaf_pattern(m, n, leaf_rows, tile_rows, pad):
+    torch = need_gpu()
+    from paper_0809_2407_amd import peaks as PK
+    from paper_0809_2407_amd import tsqr as T
+
+    announce(f"peaks copy_leaf {m}x{n} leaf {leaf_rows} tile {tile_rows} pad {pad}")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(m + n)
+    src = T.colmajor(m, n, ld=m + pad)
+    src.copy_(torch.rand((m, n), generator=g, device="cuda", dtype=torch.float64))
+    dst = T.colmajor(m, n, ld=m + 2 * pad)
+    dst.fill_(-3.0)
+    PK.copy_leaf(src, dst, leaf_rows, tile_rows)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)

@@ -41,5 +41,17 @@ def test_argument_errors_without_device():
     assert lib.tsqr_peak_mfma(None, 1, 1, 0.5, 0.5, None) == -1
     assert lib.tsqr_peak_mfma(4096, (1 << 20) + 1, 1, 0.5, 0.5, None) == -2
     assert lib.tsqr_peak_mfma(4096, 1, -1, 0.5, 0.5, None) == -3
+    # copy_leaf(src, lds, dst, ldd, m, n, leaf_rows, tile_rows, stream)
+    big = 1 << 40
+    assert lib.tsqr_peak_copy_leaf(None, 100, big, 100, 100, 8, 64, 16, None) == -1
+    assert lib.tsqr_peak_copy_leaf(4096, 99, big, 100, 100, 8, 64, 16, None) == -2
+    assert lib.tsqr_peak_copy_leaf(4096, 100, None, 100, 100, 8, 64, 16, None) == -3
+    assert lib.tsqr_peak_copy_leaf(4096, 100, 4096 + 800, 100, 100, 8, 64, 16, None) == -3  # overlapping
+    assert lib.tsqr_peak_copy_leaf(4096, 100, big, 99, 100, 8, 64, 16, None) == -4
+    assert lib.tsqr_peak_copy_leaf(4096, 100, big, 100, 0, 8, 64, 16, None) == -5
+    assert lib.tsqr_peak_copy_leaf(4096, 100, big, 100, 100, 65, 64, 16, None) == -6
+    assert lib.tsqr_peak_copy_leaf(4096, 100, big, 100, 100, 0, 64, 16, None) == -6
+    assert lib.tsqr_peak_copy_leaf(4096, 100, big, 100, 100, 8, 40, 16, None) == -7  # not a multiple of tile
+    assert lib.tsqr_peak_copy_leaf(4096, 100, big, 100, 100, 8, 64, 24, None) == -8
     assert lib.tsqr_peak_grid(3, 0) == -1
     assert lib.tsqr_peak_grid(0, -16) == -1
