@@ -16,10 +16,18 @@ The default line also carries, unless --no-extras:
                          the mixed path on the same matrix, both times, each
                          path's accuracy against its own stated bounds and the
                          R of each against the FP64 oracle;
+  krylov_mixed_vs_fp64   the s-step Krylov basis (m = 2^22, n = 17): R, Q and
+                         Q^T B on 32 right-hand sides, FP64 against mixed;
   batched                2048 problems (m_i uniform on 1000..200000, n_i on
                          {8, 16, 32, 64}): one batched plan per call against the
                          loop of single calls on the same stream (FP64), and
                          the mixed batched plan on the same problems.
+Unless --no-peaks, every single-problem line also carries the part's measured
+ceilings (measured_peaks: streaming copy and read, FP64 FMA and MFMA loops, and
+a copy in the Q kernel's access pattern at the workload's geometry) and the
+fractions against them (roofline.frac_of_measured_copy, q_kernel,
+path_roofline.measured_peaks).  step_ms holds the median, minimum and maximum
+of the timed steps (events between steps).
 
 Flop convention (nominal): R + Q = 4mn^2 - 4n^3/3, R only = 2mn^2 - 2n^3/3.
 Byte convention (algorithmic HBM traffic): factor with reflectors 16mn (read A,
