@@ -284,7 +284,10 @@ tsqr_status tsqr_tune_cache_store(const char* cache_path, int64_t m, int64_t n, 
  * library's own batched launch, not a construct of the paper, which treats one
  * matrix.  Each problem gets the single-problem method (leaf chains, binary
  * tree over the leaves, sign normalisation; the explicit Q by the seed
- * broadcast) and the same results.  Problems of one padded width share every
+ * broadcast) and the results of a single plan with the same leaf rows
+ * (tsqr_batched_problem_info reports them; a small problem in a batch keeps
+ * longer leaf chains than a plan of its own would choose, since the other
+ * problems supply the parallelism).  Problems of one padded width share every
  * launch: persistent kernels walk device work lists of (problem, leaf) and
  * (problem, tree node) items, one launch per phase and tree level, and the
  * whole sequence is captured once into a HIP graph that each call replays

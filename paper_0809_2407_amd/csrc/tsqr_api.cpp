@@ -23,7 +23,7 @@ bool tuned_opts(int64_t m, int64_t n, tsqr_precision prec, int want_q, tsqr_opts
 namespace tsqr {
 
 bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves,
-                 bool mixed, bool want_q)
+                 bool mixed, bool want_q, bool in_batch)
 {
     if (n < 1 || n > kMaxN || m < n) return false;
     L = Layout();
@@ -56,11 +56,19 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
         // stay under a quarter of the leaf's f * mt * n doubles.
         // Narrow widths (np <= 24) keep about 4096 leaves.  Mixed precision caps
         // the chain at kMaxChainF32 tiles (accuracy guard: FP32 rounding grows
-        // along a chain).
+        // along a chain).  For a problem on its own, the quarter-of-the-data
+        // guard never leaves fewer than 512 leaves: on small problems (m below
+        // about 2^21 at n = 64) the parallelism of more, shorter chains
+        // outweighs the larger per-leaf factors (measured at m = 131072,
+        // n = 64: R 0.80 against 1.30 ms, R + Q 1.12 against 1.69 ms, R with
+        // Q^T B on 192 columns 1.49 against 1.98 ms).  In a batch the other
+        // problems supply the parallelism and the guard stays (2048 problems of
+        // m in [1000, 200000]: 107 ms with it, 147 ms without).
         const bool two_per_simd = leaf_lds_bytes(L.np, mixed, want_q) <= 20480;
         const int64_t target = !want_q ? 16384 : (!two_per_simd ? 1024 : (L.np > 24 ? 2048 : 4096));
         f = tiles_total / target;
-        const int64_t f_mem = (16 * (int64_t)L.np * L.np + L.mt * n - 1) / (L.mt * n);
+        int64_t f_mem = (16 * (int64_t)L.np * L.np + L.mt * n - 1) / (L.mt * n);
+        if (!in_batch) f_mem = std::min<int64_t>(f_mem, std::max<int64_t>(1, tiles_total / 512));
         f = std::max<int64_t>(std::max<int64_t>(1, f_mem), std::min<int64_t>(256, f));
         if (mixed) f = std::min<int64_t>(f, kMaxChainF32);
         f = std::min<int64_t>(f, std::max<int64_t>(1, tiles_total));

@@ -168,7 +168,8 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
             oi.leaf_rows = tuned.leaf_rows;
             oi.flat_len = tuned.flat_len;
         }
-        if (!tsqr::make_layout(L, m[i], n[i], oi.leaf_rows, oi.flat_len, oi.tree, oi.waves, mixed, o.want_q != 0) ||
+        if (!tsqr::make_layout(L, m[i], n[i], oi.leaf_rows, oi.flat_len, oi.tree, oi.waves, mixed, o.want_q != 0,
+                               true) ||
             L.levels >= tsqr::kBatchLevels) {
             delete p;
             return 3;

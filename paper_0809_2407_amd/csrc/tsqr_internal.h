@@ -140,9 +140,12 @@ struct BatchClass {
     int64_t n_rq = 0;
 };
 
-// Fills the geometry.  Returns false for an unsupported shape.
+// Fills the geometry.  Returns false for an unsupported shape.  in_batch: the
+// problem is one of many run together (a batched plan), whose parallelism
+// comes from the other problems, so the automatic leaf length keeps the
+// per-leaf factors under a quarter of the data at every size.
 bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int flat_len, int tree, int waves,
-                 bool mixed, bool want_q);
+                 bool mixed, bool want_q, bool in_batch = false);
 // The geometry of an FP64 R-only factorisation with leaves of leaf_rows_req
 // rows and a workspace holding only the R factors of every tree level, the
 // signs and the root seed (L.total doubles).

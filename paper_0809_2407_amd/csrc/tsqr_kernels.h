@@ -1988,12 +1988,16 @@ __device__ __forceinline__ void trit_times_regs(const double* __restrict__ T,
 // kernel), which makes B^T - X^T Y^T land in B's own coalesced layout.
 template <int NP>
 __global__ void __launch_bounds__(256) k_apply_leaf(const double* __restrict__ V, int64_t lda, double* B,
-                                                    int64_t ldb, int kc, int64_t m, int n, int64_t P,
+                                                    int64_t ldb, int64_t k, int64_t m, int n, int64_t P,
                                                     int64_t leaf_rows, int64_t f, const double* __restrict__ Ttile)
 {
     constexpr int MT = tile_rows_for(NP), NPB = round16(NP), JB = NPB / 16, KS = NPB / 4;
     constexpr int JK = kApplyCols / 16, KC4 = NP / 4, NT = packed_size(NP);
     extern __shared__ double smem[];
+    // blockIdx.y picks the chunk of kApplyCols columns of B
+    const int64_t c0 = (int64_t)blockIdx.y * kApplyCols;
+    const int kc = (int)((k - c0) < kApplyCols ? (k - c0) : kApplyCols);
+    B += c0 * ldb;
     const int wave = wave_index(), lane = threadIdx.x & 63;
     const int q = lane >> 4, p = lane & 15;
     const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
@@ -2120,11 +2124,15 @@ __global__ void __launch_bounds__(256) k_apply_leaf(const double* __restrict__ V
 // child) and C_b (first leaf of its bottom child): D = C_a + Y1^T C_b,
 // X = T^T D, C_a <- C_a - X, C_b <- C_b - Y1 X.
 template <int NP>
-__global__ void __launch_bounds__(256) k_apply_tree(double* B, int64_t ldb, int kc, int64_t leaf_rows,
+__global__ void __launch_bounds__(256) k_apply_tree(double* B, int64_t ldb, int64_t k, int64_t leaf_rows,
                                                     int64_t span, const double* __restrict__ Ynode,
                                                     const double* __restrict__ Tnode, int64_t cin, int64_t cout)
 {
     constexpr int NPB = round16(NP), JB = NPB / 16, KS = NPB / 4, JK = kApplyCols / 16, NT = packed_size(NP);
+    // blockIdx.y picks the chunk of kApplyCols columns of B
+    const int64_t c0 = (int64_t)blockIdx.y * kApplyCols;
+    const int kc = (int)((k - c0) < kApplyCols ? (k - c0) : kApplyCols);
+    B += c0 * ldb;
     const int wave = wave_index(), lane = threadIdx.x & 63;
     const int q = lane >> 4, p = lane & 15;
     const int64_t nq = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
@@ -2195,13 +2203,14 @@ __global__ void __launch_bounds__(256) k_apply_tree(double* B, int64_t ldb, int 
 
 // Root of Q^T B: rows 0..n-1 <- D rows 0..n-1.
 template <int NP>
-__global__ void __launch_bounds__(256) k_apply_signs(double* B, int64_t ldb, int n, int kc,
+__global__ void __launch_bounds__(256) k_apply_signs(double* B, int64_t ldb, int n, int64_t k,
                                                      const double* __restrict__ Dsig)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * kc) return;
-    const int r = idx % n, c = idx / n;
-    B[r + (int64_t)c * ldb] *= Dsig[r];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * k) return;
+    const int r = (int)(idx % n);
+    const int64_t c = idx / n;
+    B[r + c * ldb] *= Dsig[r];
 }
 
 template <typename K>
@@ -2361,24 +2370,30 @@ hipError_t apply_qt_np(const Layout& L, const double* A, int64_t lda, int64_t k,
 {
     const size_t lds = (size_t)L.waves * NP * kApplyCols * sizeof(double);
     allow_lds(k_apply_leaf<NP>, lds);
-    for (int64_t c0 = 0; c0 < k; c0 += kApplyCols) {
-        const int kc = (int)((k - c0) < kApplyCols ? (k - c0) : kApplyCols);
-        double* Bc = B + c0 * ldb;
-        hipLaunchKernelGGL((k_apply_leaf<NP>), dim3(grid_for(L.P, L.waves)), dim3(64 * L.waves), lds, s, A, lda,
-                           Bc, ldb, kc, L.m, (int)L.n, L.P, L.leaf_rows, L.f, ws + L.off_T);
+    // every chunk of kApplyCols columns in the same launches (grid y), at most
+    // kMaxChunks chunks per launch
+    constexpr int64_t kMaxChunks = 65535;
+    const int64_t nch = (k + kApplyCols - 1) / kApplyCols;
+    for (int64_t g0 = 0; g0 < nch; g0 += kMaxChunks) {
+        const int64_t ng = (nch - g0) < kMaxChunks ? (nch - g0) : kMaxChunks;
+        const int64_t kg = (k - g0 * kApplyCols) < ng * kApplyCols ? (k - g0 * kApplyCols) : ng * kApplyCols;
+        double* Bg = B + g0 * kApplyCols * ldb;
+        hipLaunchKernelGGL((k_apply_leaf<NP>), dim3(grid_for(L.P, L.waves), (unsigned)ng), dim3(64 * L.waves), lds, s,
+                           A, lda, Bg, ldb, kg, L.m, (int)L.n, L.P, L.leaf_rows, L.f, ws + L.off_T);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         int64_t span = 1;
         for (int l = 1; l <= L.levels; ++l) {
-            hipLaunchKernelGGL((k_apply_tree<NP>), dim3(grid_for(L.count[l], 4)), dim3(256), 0, s, Bc, ldb, kc,
-                               L.leaf_rows, span, ws + L.off_Y[l], ws + L.off_TN[l], L.count[l - 1], L.count[l]);
+            hipLaunchKernelGGL((k_apply_tree<NP>), dim3(grid_for(L.count[l], 4), (unsigned)ng), dim3(256), 0, s, Bg,
+                               ldb, kg, L.leaf_rows, span, ws + L.off_Y[l], ws + L.off_TN[l], L.count[l - 1],
+                               L.count[l]);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
             span *= 2;
         }
-        const int cnt = (int)L.n * kc;
-        hipLaunchKernelGGL((k_apply_signs<NP>), dim3((cnt + 255) / 256), dim3(256), 0, s, Bc, ldb, (int)L.n, kc,
-                           ws + L.off_D);
+        const int64_t cnt = L.n * kg;
+        hipLaunchKernelGGL((k_apply_signs<NP>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, Bg, ldb,
+                           (int)L.n, kg, ws + L.off_D);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -27,13 +27,15 @@ def _inputs(seed0):
     return mats
 
 
-def _single(A):
+def _single(A, leaf_rows):
+    """A single plan with the geometry the batched plan chose for the problem
+    (a problem in a batch keeps longer leaf chains than one on its own)."""
     torch = need_gpu()
     from paper_0809_2407_amd import tsqr as T
 
     m, n = A.shape
     Ad = T.to_colmajor(torch.from_numpy(A))
-    with T.Plan(m, n) as p:
+    with T.Plan(m, n, leaf_rows=leaf_rows) as p:
         R = p.factor(Ad)
         Q = p.form_q(Ad, T.colmajor(m, n))
         torch.cuda.synchronize()
@@ -56,7 +58,7 @@ def test_batched_equals_single_plans_and_meets_oracle_bounds():
             for i, A in enumerate(data):
                 announce(f"batched rep {rep} problem {i} {A.shape}")
                 R, Q = Rs[i].cpu().numpy(), Qs[i].cpu().numpy()
-                Rs1, Qs1 = _single(A)
+                Rs1, Qs1 = _single(A, bp.problem_info(i)["leaf_rows"])
                 assert np.array_equal(R, Rs1) and np.array_equal(Q, Qs1)
                 n = A.shape[1]
                 assert is_upper(R) and np.all(np.diag(R) >= 0)
@@ -130,7 +132,7 @@ def test_batched_mixed_equals_single_mixed_plans():
             m, n = A.shape
             announce(f"batched mixed problem {i} {A.shape}")
             Ad = T.to_colmajor(torch.from_numpy(A))
-            with T.Plan(m, n, precision="mixed") as p:
+            with T.Plan(m, n, precision="mixed", leaf_rows=bp.problem_info(i)["leaf_rows"]) as p:
                 R1 = p.factor(Ad)
                 Q1 = p.form_q(Ad, T.colmajor(m, n))
                 torch.cuda.synchronize()
@@ -153,9 +155,9 @@ def test_batched_mixed_r_only_and_check():
     with T.BatchedPlan([m for m, _ in shapes], [n for _, n in shapes], precision="mixed", want_q=False) as bp:
         Rs = bp.factor([T.to_colmajor(torch.from_numpy(A)) for A in mats])
         torch.cuda.synchronize()
-        for A, R in zip(mats, Rs):
+        for i, (A, R) in enumerate(zip(mats, Rs)):
             m, n = A.shape
-            with T.Plan(m, n, precision="mixed", want_q=False) as p:
+            with T.Plan(m, n, precision="mixed", want_q=False, leaf_rows=bp.problem_info(i)["leaf_rows"]) as p:
                 R1 = p.factor(T.to_colmajor(torch.from_numpy(A)))
                 torch.cuda.synchronize()
             assert np.array_equal(R.cpu().numpy(), R1.cpu().numpy())

@@ -76,6 +76,7 @@ def _check_scale(precision, count, m_lo, m_hi, seed, tree="auto", min_items=GRID
         items = _leaf_items_per_class(bp, count)
         announce(f"leaf items per width class {items}")
         assert len(items) == 4 and min(items.values()) >= min_items
+        lrs = [bp.problem_info(i)["leaf_rows"] for i in range(count)]
         Rb, Qb = _run_batched(T, torch, bp, mats)
     announce("oracle R of every problem")
     Ro = _oracle_rs(mats)
@@ -85,7 +86,7 @@ def _check_scale(precision, count, m_lo, m_hi, seed, tree="auto", min_items=GRID
         if i % 500 == 0:
             announce(f"batched {precision} problem {i} {A.shape}")
         n = A.shape[1]
-        R1, Q1 = _single(T, torch, A, precision, **kw)
+        R1, Q1 = _single(T, torch, A, precision, leaf_rows=lrs[i], **kw)
         assert np.array_equal(Rb[i], R1) and np.array_equal(Qb[i], Q1), f"problem {i} {A.shape}"
         assert is_upper(Rb[i]) and np.all(np.diag(Rb[i]) >= 0)
         dr = rel_diff(Rb[i], Ro[i])

@@ -111,11 +111,12 @@ def test_batched_widths_57_to_60_equal_single_plans(precision):
         Rs = bp.factor(As)
         Qs = bp.form_q(As, [T.colmajor(m, n) for m, n in shapes])
         torch.cuda.synchronize()
+        lrs = [bp.problem_info(i)["leaf_rows"] for i in range(len(shapes))]
     for i, A in enumerate(mats):
         m, n = A.shape
         announce(f"batched {precision} problem {i} {A.shape} against a single plan")
         Ad = T.to_colmajor(torch.from_numpy(A))
-        with T.Plan(m, n, precision=precision) as p:
+        with T.Plan(m, n, precision=precision, leaf_rows=lrs[i]) as p:
             R1 = p.factor(Ad)
             Q1 = p.form_q(Ad if precision == "fp64" else None, T.colmajor(m, n))
             torch.cuda.synchronize()
