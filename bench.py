@@ -83,6 +83,17 @@ BATCHED = {
 }
 
 
+# The rows beyond the TSQR path, each measured on its own line (--workload):
+# CAQR of a general tall matrix with Q^T B (Sec. 6), the out-of-HBM flat tree
+# over host-resident blocks (Sec. 7.1), and TSQR's competitors of Sec. 5 on
+# the headline matrix and on a well-conditioned one.
+NEXT_ROWS = {
+    "caqr_fp64_rqtb_m131072_n256_b64_k32": dict(m=1 << 17, n=256, panel=64, rhs=32, decades=6.0),
+    "stream_fp64_r_m16777216_n32_kappa1e12": dict(m=1 << 24, n=32, decades=12.0),
+    "competitors_fp64_rq_m16777216_n32": dict(m=1 << 24, n=32, decades=(3.0, 12.0)),
+}
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -748,12 +759,260 @@ def batched_record(args, count: int, m_lo: int, m_hi: int, ns, precision: str, s
     return rec, state
 
 
+def events_time(work, steps: int, warmup: int, prepare=None):
+    """Per-step device times (ms) of work() from events on the current stream;
+    prepare() runs before each step outside the events."""
+    import torch
+
+    st = torch.cuda.current_stream()
+    for _ in range(warmup):
+        if prepare:
+            prepare()
+        work()
+    torch.cuda.synchronize()
+    ev = []
+    for _ in range(steps):
+        if prepare:
+            prepare()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        work()
+        b.record(st)
+        ev.append((a, b))
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) for a, b in ev)
+    return {"mean": sum(t) / len(t), "median": t[len(t) // 2] if len(t) % 2 else 0.5 * (t[len(t) // 2 - 1] + t[len(t) // 2]),
+            "min": t[0], "max": t[-1], "timing": "HIP events on the stream around each step"}
+
+
+def line(metric: str, value: float, unit: str, steps: int, warmup: int, ms: float, dtype: str, config: dict) -> dict:
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def caqr_line(args, name: str) -> dict:
+    """CAQR (Sec. 6) of a tall general matrix with TSQR panels, then Q^T B on
+    k columns: per panel the panel's TSQR and the tree-structured update of the
+    trailing columns.  R against the oracle's plain Householder R of the whole
+    matrix, Q^T B through the column norms it must keep."""
+    import numpy as np
+    import torch
+    from paper_0809_2407_amd import tsqr as T
+
+    w = NEXT_ROWS[name]
+    m, n, b, k = w["m"], w["n"], w["panel"], w["rhs"]
+    log(f"CAQR m = {m}, n = {n}, panel {b}, {k} right-hand sides: generating input")
+    A0, _ = make_input(dict(m=m, n=n, decades=w["decades"]), args.seed)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(args.seed + 1)
+    B0 = torch.randn((k, m), generator=g, device="cuda", dtype=torch.float64).t()
+    A, B, R = T.colmajor(m, n), T.colmajor(m, k), T.colmajor(n, n)
+    plan = T.CaqrPlan(m, n, b)
+    info = plan.info()
+
+    def prepare():
+        A.copy_(A0)
+        B.copy_(B0)
+
+    def work():
+        plan.factor(A, R)
+        plan.apply_qt(A, B)
+
+    t = events_time(work, args.steps, args.warmup, prepare)
+    fl = flops_r(m, n) + 4.0 * m * n * k - 2.0 * n * n * k
+    by = 0.0
+    for j in range(info["num_panels"]):
+        mj, bj = m - j * b, min(b, n - j * b)
+        cj = n - j * b - bj
+        by += 16.0 * mj * bj + -(-cj // 32) * 8.0 * mj * bj + 16.0 * mj * cj
+        by += -(-k // 32) * 8.0 * mj * bj + 16.0 * mj * k
+    t_roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), by / (HBM_PEAK_GBS * 1e9)) * 1e3
+    with torch.no_grad():
+        keep = float(((torch.linalg.norm(B, dim=0) - torch.linalg.norm(B0, dim=0)).abs()
+                      / torch.linalg.norm(B0, dim=0)).max())
+    res = line("CAQR R + Q^T B GFLOP/s & % roofline", fl / (t["median"] * 1e-3) / 1e9, "GFLOP/s", args.steps,
+               args.warmup, t["mean"], "f64",
+               {"workload": name, "m": m, "n": n, "panel": b, "num_panels": info["num_panels"], "rhs": k,
+                "sigma": f"logspace(0,-{w['decades']:g},{n})", "seed": args.seed, "parallelism": "single GPU"})
+    res["step_ms"] = t
+    res["roofline"] = None
+    res["path_roofline"] = {"t_roof_ms": t_roof, "frac_median": t_roof / t["median"], "bytes": by, "flops": fl,
+                            "bytes_model": "per panel: 16 m_j b (panel TSQR), 8 m_j b per 32 trailing or B "
+                                           "columns (reflectors re-read) + 16 m_j per trailing or B column"}
+    res["accuracy"] = {"qtb_column_norms_kept": keep}
+    res["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+        import oracle
+
+        log("CAQR: the oracle's plain Householder R of the whole matrix (one thread)")
+        Ah = np.asfortranarray(A0.cpu().numpy())
+        t0 = time.perf_counter()
+        Ro = oracle.qr_reference(Ah, want_q=False)
+        dt = time.perf_counter() - t0
+        res["accuracy"]["R_vs_oracle"] = r_vs_oracle(R, Ro)
+        res["cpu_baseline"] = {"value": flops_r(m, n) / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+                               "sample": f"plain Householder R of the whole {m} x {n} matrix, {dt:.2f} s",
+                               "host": {"nproc": os.cpu_count(), "model": cpu_model()}}
+    log(f"CAQR: {t['median']:.3f} ms median, accuracy {res['accuracy']}")
+    plan.close()
+    return res
+
+
+def stream_line(args, name: str) -> dict:
+    """The out-of-HBM flat tree (Sec. 7.1): A in pinned host memory, streamed
+    to the GPU in row blocks while the previous block is factored.  Bound by
+    the host link: the line reports the rate against a measured pinned
+    host-to-device copy."""
+    import numpy as np
+    import torch
+    from paper_0809_2407_amd import tsqr as T
+
+    w = NEXT_ROWS[name]
+    m, n = w["m"], w["n"]
+    log(f"out-of-HBM m = {m}, n = {n}: generating input")
+    A, _ = make_input(dict(m=m, n=n, decades=w["decades"]), args.seed)
+    H = torch.empty((n, m), dtype=torch.float64, pin_memory=True).t()
+    H.copy_(A)
+    plan = T.StreamPlan(m, n)
+    info = plan.info()
+    R = T.colmajor(n, n)
+    t = events_time(lambda: plan.factor(H, R), args.steps, args.warmup)
+    by = 8.0 * m * n
+    # the link's ceiling: a pinned host-to-device copy of 1 GiB
+    nb = 1 << 30
+    hsrc = torch.empty(nb // 8, dtype=torch.float64, pin_memory=True)
+    dd = torch.empty(nb // 8, dtype=torch.float64, device="cuda")
+    tc = events_time(lambda: dd.copy_(hsrc, non_blocking=True), 5, 1)
+    h2d = nb / (tc["min"] * 1e-3) / 1e9
+    del hsrc, dd
+    with T.Plan(m, n, want_q=False) as p:
+        Rh = p.factor(A)
+    rate = by / (t["median"] * 1e-3) / 1e9
+    res = line("out-of-HBM TSQR R: host GB/s streamed & % of the measured host link", rate, "GB/s", args.steps,
+               args.warmup, t["mean"], "f64",
+               {"workload": name, "m": m, "n": n, "block_rows": info["block_rows"], "num_blocks": info["num_blocks"],
+                "sigma": f"logspace(0,-{w['decades']:g},{n})", "seed": args.seed, "host_memory": "pinned",
+                "parallelism": "single GPU"})
+    res["step_ms"] = t
+    res["gflops"] = flops_r(m, n) / (t["median"] * 1e-3) / 1e9
+    res["roofline"] = {"bound": "host link", "achieved": rate, "peak": h2d, "unit": "GB/s", "frac": rate / h2d,
+                       "peak_source": "pinned host-to-device copy of 1 GiB, measured in the same run",
+                       "traffic": None}
+    res["accuracy"] = {"R_vs_in_hbm_tsqr": r_vs_oracle(R, Rh.cpu().numpy())}
+    res["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        log("out-of-HBM: the oracle's TSQR R of the whole matrix (host cores)")
+        sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+        import oracle
+
+        pi = T.plan_query(m, n, want_q=False)
+        Ro, dt = oracle_r_only(A, pi["leaf_rows"], pi["tile_rows"])
+        res["accuracy"]["R_vs_oracle"] = r_vs_oracle(R, Ro)
+        res["cpu_baseline"] = {"value": flops_r(m, n) / dt / 1e9, "unit": "GFLOP/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"TSQR R of the whole matrix (in host memory), {dt:.2f} s",
+                               "host": {"nproc": os.cpu_count(), "model": cpu_model()}}
+    log(f"out-of-HBM: {t['median']:.2f} ms median, {rate:.1f} GB/s of {h2d:.1f}, accuracy {res['accuracy']}")
+    plan.close()
+    del H
+    return res
+
+
+CMP_FLOPS = {  # nominal flops of each method for R and Q (m x n): half of Householder's 4mn^2
+    "cholqr": lambda m, n: 2.0 * m * n * n,        # Gram (symmetric) mn^2, Q = A R^-1 (triangular) mn^2
+    "cholqr2": lambda m, n: 4.0 * m * n * n,
+    "cgs": lambda m, n: 2.0 * m * n * n,
+    "mgs": lambda m, n: 2.0 * m * n * n,
+}
+CMP_BYTES = {  # algorithmic HBM bytes: CholeskyQR reads A twice and writes Q; Gram-Schmidt passes over the columns
+    "cholqr": lambda m, n: 24.0 * m * n,
+    "cholqr2": lambda m, n: 48.0 * m * n,
+    "cgs": lambda m, n: 8.0 * m * n * n,
+    "mgs": lambda m, n: 8.0 * m * n * n,
+}
+
+
+def competitors_line(args, name: str) -> dict:
+    """TSQR's competitors of Sec. 5 (CholeskyQR, CholeskyQR2, CGS, MGS) beside
+    TSQR on the same matrices: a well-conditioned one (kappa = 1e3) and the
+    headline one (kappa = 1e12), with times, roofline fractions, backward error,
+    orthogonality and breakdowns (the stability contrast of Sec. 5)."""
+    import numpy as np
+    import torch
+    from paper_0809_2407_amd import tsqr as T
+
+    w = NEXT_ROWS[name]
+    m, n = w["m"], w["n"]
+    out = {}
+    for dec in w["decades"]:
+        key = f"kappa1e{int(dec)}"
+        log(f"competitors m = {m}, n = {n}, kappa = 1e{int(dec)}: generating input")
+        A, _ = make_input(dict(m=m, n=n, decades=dec), args.seed)
+        Q, R = T.colmajor(m, n), T.colmajor(n, n)
+        rec = {}
+        with T.Plan(m, n) as p:
+            V = T.colmajor(m, n)
+
+            def tsqr_step():
+                p.factor_into(A, V, R)
+                p.form_q(V, Q)
+
+            t = events_time(tsqr_step, args.steps, args.warmup)
+            fl = flops_rq(m, n)
+            t_roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), 32.0 * m * n / (HBM_PEAK_GBS * 1e9)) * 1e3
+            rec["tsqr"] = {"ms_median": t["median"], "gflops": fl / (t["median"] * 1e-3) / 1e9,
+                           "path_roofline_frac": t_roof / t["median"], "breakdown": 0, **accuracy_of(A, Q, R)}
+            del V
+        for meth in ("cholqr", "cholqr2", "cgs", "mgs"):
+            with T.CmpPlan(m, n, meth) as p:
+                t = events_time(lambda: p.factor(A, Q, R), args.steps, args.warmup)
+                bd = p.breakdown()
+            fl, by = CMP_FLOPS[meth](m, n), CMP_BYTES[meth](m, n)
+            t_roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), by / (HBM_PEAK_GBS * 1e9)) * 1e3
+            r = {"ms_median": t["median"], "gflops": fl / (t["median"] * 1e-3) / 1e9,
+                 "path_roofline_frac": t_roof / t["median"], "bytes": by, "breakdown": bd}
+            if bd == 0:
+                r.update(accuracy_of(A, Q, R))
+            rec[meth] = r
+            log(f"  {key} {meth}: {r}")
+        out[key] = rec
+        del A, Q, R
+        torch.cuda.empty_cache()
+    tk = out["kappa1e3"]["tsqr"]["ms_median"]
+    res = line("TSQR against its competitors of Sec. 5: ms per R + Q, orthogonality", out["kappa1e3"]["tsqr"]["gflops"],
+               "GFLOP/s", args.steps, args.warmup, tk, "f64",
+               {"workload": name, "m": m, "n": n, "sigmas": [f"logspace(0,-{d:g},{n})" for d in w["decades"]],
+                "seed": args.seed, "parallelism": "single GPU"})
+    res["methods"] = out
+    res["roofline"] = None
+    res["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+        import oracle
+
+        ms_ = 1 << 18
+        As, _ = make_input(dict(m=ms_, n=n, decades=w["decades"][0]), args.seed)
+        Ah = np.asfortranarray(As.cpu().numpy())
+        legs = {}
+        for meth, fn in (("cholqr", oracle.cholqr), ("cholqr2", oracle.cholqr2), ("cgs", oracle.cgs),
+                         ("mgs", oracle.mgs)):
+            t0 = time.perf_counter()
+            fn(Ah)
+            dt = time.perf_counter() - t0
+            legs[meth] = {"gflops": CMP_FLOPS[meth](ms_, n) / dt / 1e9, "s": dt}
+        res["cpu_baseline"] = {"value": legs["cholqr"]["gflops"], "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{ms_} x {n}, kappa = 1e{int(w['decades'][0])}, each method once",
+                               "legs": legs, "host": {"nproc": os.cpu_count(), "model": cpu_model()}}
+    return res
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(BATCHED))
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(BATCHED) + sorted(NEXT_ROWS))
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 24)
@@ -781,6 +1040,10 @@ def main(argv=None) -> int:
         return 1
     if args.workload in BATCHED:
         return run_batched(args)
+    if args.workload in NEXT_ROWS:
+        fn = {"caqr": caqr_line, "stream": stream_line, "competitors": competitors_line}[args.workload.split("_")[0]]
+        print(json.dumps(fn(args, args.workload)), flush=True)
+        return 0
     result = run_single(args, args.workload, cpu=not args.no_cpu_baseline, check=not args.no_check)
     if not args.no_peaks:
         log("measured ceilings: copy, read, FP64 FMA and MFMA loops")
