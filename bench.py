@@ -1028,6 +1028,9 @@ def main(argv=None) -> int:
                          "8mn written) so that hardware byte counters can be scaled against it")
     args = ap.parse_args(argv)
 
+    if args.steps < 1 or args.warmup < 0:
+        print(json.dumps({"error": "--steps must be at least 1 and --warmup at least 0"}))
+        return 2
     if args.gpus != 1:
         print(json.dumps({"error": "this TSQR build runs on one GPU; the multi-GPU path (one all-gather "
                                    "of the R factors) is a design, not a build: use --gpus 1"}))

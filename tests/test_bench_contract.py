@@ -31,6 +31,14 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in msg["error"]
 
 
+def test_bad_step_counts_are_refused():
+    for argv in (["--steps", "0"], ["--warmup", "-1"]):
+        out = io.StringIO()
+        with redirect_stdout(out):
+            rc = bench.main(argv)
+        assert rc == 2 and "steps" in json.loads(out.getvalue())["error"]
+
+
 def test_workloads_are_well_formed():
     for name, w in bench.WORKLOADS.items():
         assert w["mode"] in ("r", "rq"), name
