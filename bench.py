@@ -88,7 +88,7 @@ BATCHED = {
 # over host-resident blocks (Sec. 7.1), and TSQR's competitors of Sec. 5 on
 # the headline matrix and on a well-conditioned one.
 NEXT_ROWS = {
-    "caqr_fp64_rqtb_m131072_n256_b64_k32": dict(m=1 << 17, n=256, panel=64, rhs=32, decades=6.0),
+    "caqr_fp64_rqtb_m131072_n256_b32_k32": dict(m=1 << 17, n=256, panel=32, rhs=32, decades=6.0),
     "stream_fp64_r_m16777216_n32_kappa1e12": dict(m=1 << 24, n=32, decades=12.0),
     "competitors_fp64_rq_m16777216_n32": dict(m=1 << 24, n=32, decades=(3.0, 12.0)),
 }
