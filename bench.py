@@ -21,7 +21,10 @@ The default line also carries, unless --no-extras:
   batched                2048 problems (m_i uniform on 1000..200000, n_i on
                          {8, 16, 32, 64}): one batched plan per call against the
                          loop of single calls on the same stream (FP64), and
-                         the mixed batched plan on the same problems.
+                         the mixed batched plan on the same problems;
+  beyond_tsqr            CAQR, the out-of-HBM flat tree and the competitors of
+                         Sec. 5, three timed steps each (their full lines:
+                         --workload caqr_... / stream_... / competitors_...).
 Unless --no-peaks, every single-problem line also carries the part's measured
 ceilings (measured_peaks: streaming copy and read, FP64 FMA and MFMA loops, and
 a copy in the Q kernel's access pattern at the workload's geometry) and the
@@ -1067,6 +1070,13 @@ def main(argv=None) -> int:
         del state
         result["batched"] = {"workload": "tsqr_batched_rq_p2048_m1000_200000_n8_64", "fp64": fp64, "mixed": mx,
                              "mixed_vs_fp64_batched": fp64["ms_per_step"] / mx["ms_per_step"]}
+        # the rows beyond the TSQR path, three timed steps each (their own lines: --workload NAME)
+        short = argparse.Namespace(**vars(args))
+        short.steps, short.warmup = 3, 1
+        result["beyond_tsqr"] = {name.split("_")[0]: fn(short, name) for name, fn in (
+            ("caqr_fp64_rqtb_m131072_n256_b32_k32", caqr_line),
+            ("stream_fp64_r_m16777216_n32_kappa1e12", stream_line),
+            ("competitors_fp64_rq_m16777216_n32", competitors_line))}
     print(json.dumps(result), flush=True)
     return 0
 
