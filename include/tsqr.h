@@ -269,13 +269,15 @@ tsqr_status tsqr_autotune(int64_t m, int64_t n, tsqr_precision prec, int want_q,
 
 /* Cached options of the class of (m, n, prec, want_q), and their time when ms
  * is not NULL.  Host only.  Errors: -1 path NULL, -2 m, -3 n, -4 prec,
- * -5 want_q, -6 out NULL; 5 when the class is not in the cache. */
+ * -5 want_q, -6 out NULL; 5 when the class is not in the cache.  A cache entry
+ * whose values no option can take (a tree or leaf kind out of range, a
+ * fractional or negative count) is skipped as if absent. */
 tsqr_status tsqr_tune_cache_lookup(const char* cache_path, int64_t m, int64_t n, tsqr_precision prec, int want_q,
                                    tsqr_opts* out, double* ms);
 
 /* Store (or replace) the options of a class in the cache file.  Host only.
- * Errors: -1 path NULL, -2 m, -3 n, -4 prec, -5 opts NULL or bad want_q;
- * 1 when the file cannot be written. */
+ * Errors: -1 path NULL, -2 m, -3 n, -4 prec, -5 opts NULL, bad want_q or a
+ * tree or leaf kind out of range; 1 when the file cannot be written. */
 tsqr_status tsqr_tune_cache_store(const char* cache_path, int64_t m, int64_t n, tsqr_precision prec,
                                   const tsqr_opts* opts, double ms);
 

@@ -7,7 +7,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtsqr.so")
+# TSQR_LIBRARY names another build of the same library (the host-sanitized
+# libtsqr_checked.so of the sanitizer tests)
+LIB_PATH = os.environ.get("TSQR_LIBRARY") or os.path.join(HERE, "libtsqr.so")
 
 TSQR_FP64, TSQR_MIXED = 0, 1
 TSQR_CMP_CHOLQR, TSQR_CMP_CHOLQR2, TSQR_CMP_CGS, TSQR_CMP_MGS = 0, 1, 2, 3

@@ -46,6 +46,64 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found: the ROCm toolchain is required to build libtsqr")
 
 
+CHECKED_LIB = os.path.join(HERE, "libtsqr_checked.so")
+# host code under AddressSanitizer and UndefinedBehaviorSanitizer (the device
+# code is compiled as usual); one padded width (32) keeps the build short
+CHECKED_FLAGS = ["-O1", "-g", "-DTSQR_ONLY_NP=32",
+                 "-Xarch_host", "-fsanitize=address",
+                 "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_checked(out: str | None = None, jobs: int | None = None) -> str:
+    """libtsqr_checked.so (at ``out``, by default beside libtsqr.so): the library
+    with its host code under ASan and UBSan, for the sanitizer tests (loaded
+    through TSQR_LIBRARY with the ASan runtime preloaded)."""
+    out = out or CHECKED_LIB
+    hipcc = _hipcc()
+    tmp = tempfile.mkdtemp(prefix="tsqr_checked_")
+    common = [c for c in COMMON if c != "-O3"]
+
+    def compile_unit(u: str) -> str:
+        obj = os.path.join(tmp, u + ".o")
+        lang = ["-x", "hip"] if u.endswith(".hip") else []
+        cmd = [hipcc] + common + CHECKED_FLAGS + lang + ["-c", os.path.join(CSRC, u), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {u}:\n{r.stderr[-4000:]}")
+        return obj
+
+    try:
+        n = jobs or min(len(UNITS), max(1, os.cpu_count() or 1))
+        with cf.ThreadPoolExecutor(max_workers=n) as ex:
+            objs = list(ex.map(compile_unit, UNITS))
+        cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC",
+               "-Xarch_host", "-fsanitize=address",
+               "-Xarch_host", "-fsanitize=undefined",
+               "-Xarch_host", "-shared-libsan", "-o", out + ".tmp"] + objs
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
+        os.replace(out + ".tmp", out)
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    return out
+
+
+def asan_runtime() -> str | None:
+    """The shared AddressSanitizer runtime of the ROCm compiler (to preload)."""
+    import glob
+
+    root = os.path.dirname(os.path.dirname(os.path.realpath(_hipcc())))
+    for base in (os.path.join(root, "llvm", "lib", "clang"), os.path.join(root, "lib", "llvm", "lib", "clang"),
+                 "/opt/rocm/llvm/lib/clang"):
+        hits = sorted(glob.glob(os.path.join(base, "*", "lib", "linux", "libclang_rt.asan-x86_64.so")))
+        if hits:
+            return hits[-1]
+    return None
+
+
 def build_peaks(verbose: bool = False) -> str:
     cmd = [_hipcc()] + COMMON + ["-shared", "-x", "hip", PEAKS_SRC, "-o", PEAKS_LIB + ".tmp"]
     if verbose:
@@ -97,8 +155,9 @@ def main(argv=None) -> int:
     ap.add_argument("--np", type=int, default=None, help="build a single padded column count")
     ap.add_argument("-j", "--jobs", type=int, default=None)
     ap.add_argument("-v", "--verbose", action="store_true")
+    ap.add_argument("--checked", action="store_true", help="the host-sanitized libtsqr_checked.so instead")
     a = ap.parse_args(argv)
-    path = build(a.np, a.jobs, a.verbose)
+    path = build_checked(jobs=a.jobs) if a.checked else build(a.np, a.jobs, a.verbose)
     print(path)
     return 0
 

@@ -312,24 +312,28 @@ const char* tsqr_status_string(tsqr_status s)
 
 // Argument checks shared by tsqr_plan_create and tsqr_plan_query; fills the
 // layout on success.
-static tsqr_status check_plan_args(int64_t m, int64_t n, tsqr_precision prec, const tsqr_opts* opts,
+// prec: the caller's precision argument read as an int (tsqr::abi_int)
+static tsqr_status check_plan_args(int64_t m, int64_t n, int pv, const tsqr_opts* opts,
                                    tsqr_opts& o, tsqr::Layout& L)
 {
     if (m < 1 || m < n) return -2;
     if (n < 1) return -3;
     if (n > tsqr::kMaxN) return 3;
-    if (prec != TSQR_FP64 && prec != TSQR_MIXED) return -4;
+    if (pv != TSQR_FP64 && pv != TSQR_MIXED) return -4;
+    const tsqr_precision prec = (tsqr_precision)pv;
     std::memset(&o, 0, sizeof(o));
     o.want_q = 1;
     tsqr_opts tuned;
     if (!opts && tsqr::tuned_opts(m, n, prec, 1, &tuned)) opts = &tuned;
     if (opts) {
         o = *opts;
-        if (o.tree < TSQR_TREE_AUTO || o.tree > TSQR_TREE_HYBRID) return -5;
+        const int tv = tsqr::abi_int(o.tree);
+        if (tv < TSQR_TREE_AUTO || tv > TSQR_TREE_HYBRID) return -5;
         if (o.leaf_rows < 0 || o.tile_rows < 0 || o.flat_len < 0) return -5;
         if (o.waves != 0 && o.waves != 1 && o.waves != 2 && o.waves != 4) return -5;
         if (o.want_q != 0 && o.want_q != 1) return -5;
-        if (o.leaf_kind < TSQR_LEAF_AUTO || o.leaf_kind > TSQR_LEAF_RECURSIVE) return -5;
+        const int kv = tsqr::abi_int(o.leaf_kind);
+        if (kv < TSQR_LEAF_AUTO || kv > TSQR_LEAF_RECURSIVE) return -5;
     }
     if (!tsqr::make_layout(L, m, n, o.leaf_rows, o.flat_len, o.tree, o.waves, prec == TSQR_MIXED, o.want_q != 0))
         return 3;
@@ -363,7 +367,7 @@ tsqr_status tsqr_plan_query(int64_t m, int64_t n, tsqr_precision prec, const tsq
 {
     tsqr_opts o;
     tsqr::Layout L;
-    tsqr_status st = check_plan_args(m, n, prec, opts, o, L);
+    tsqr_status st = check_plan_args(m, n, tsqr::abi_int(prec), opts, o, L);
     if (st < 0) return st + 1;  // argument positions are one lower than in tsqr_plan_create
     if (st != 0) return st;
     if (!out) return -5;
@@ -378,12 +382,12 @@ tsqr_status tsqr_plan_create(tsqr_plan* p, int64_t m, int64_t n, tsqr_precision 
     *p = nullptr;
     tsqr_opts o;
     tsqr::Layout L;
-    tsqr_status st = check_plan_args(m, n, prec, opts, o, L);
+    tsqr_status st = check_plan_args(m, n, tsqr::abi_int(prec), opts, o, L);
     if (st != 0) return st;
     tsqr_plan_s* P = new (std::nothrow) tsqr_plan_s();
     if (!P) return 2;
     P->L = L;
-    P->prec = prec;
+    P->prec = prec;  // validated above
     P->tree = o.tree;
     P->want_q = o.want_q;
     P->stream = (hipStream_t)hip_stream;

@@ -131,17 +131,20 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
     if (count < 1) return -2;
     if (!m) return -3;
     if (!n) return -4;
-    if (prec != TSQR_FP64 && prec != TSQR_MIXED) return -5;
+    const int pv = tsqr::abi_int(prec);
+    if (pv != TSQR_FP64 && pv != TSQR_MIXED) return -5;
     tsqr_opts o;
     std::memset(&o, 0, sizeof(o));
     o.want_q = 1;
     if (opts) {
         o = *opts;
-        if (o.tree < TSQR_TREE_AUTO || o.tree > TSQR_TREE_HYBRID) return -6;
+        const int tv = tsqr::abi_int(o.tree);
+        if (tv < TSQR_TREE_AUTO || tv > TSQR_TREE_HYBRID) return -6;
         if (o.leaf_rows < 0 || o.tile_rows != 0 || o.flat_len < 0) return -6;
         if (o.waves != 0 && o.waves != 1 && o.waves != 2 && o.waves != 4) return -6;
         if (o.want_q != 0 && o.want_q != 1) return -6;
-        if (o.leaf_kind != TSQR_LEAF_AUTO && o.leaf_kind != TSQR_LEAF_COMPACT_WY) return -6;
+        const int kv = tsqr::abi_int(o.leaf_kind);
+        if (kv != TSQR_LEAF_AUTO && kv != TSQR_LEAF_COMPACT_WY) return -6;
     }
     for (int i = 0; i < count; ++i) {
         if (n[i] < 1 || m[i] < 1 || m[i] < n[i]) return -3;

@@ -582,7 +582,8 @@ tsqr_status tsqr_cmp_plan_create(tsqr_cmp_plan* out, int64_t m, int64_t n, tsqr_
     if (m < 1 || m < n) return -2;
     if (n < 1) return -3;
     if (n > tsqr::kMaxN) return 3;
-    if (method < TSQR_CMP_CHOLQR || method > TSQR_CMP_MGS) return -4;
+    const int mv = tsqr::abi_int(method);
+    if (mv < TSQR_CMP_CHOLQR || mv > TSQR_CMP_MGS) return -4;
     tsqr_cmp_plan_s* p = new (std::nothrow) tsqr_cmp_plan_s();
     if (!p) return 2;
     p->m = m;

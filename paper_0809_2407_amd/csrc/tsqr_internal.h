@@ -5,7 +5,22 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstring>
+
 namespace tsqr {
+
+// The int a caller passed for an enumeration-typed argument or field of the C
+// ABI.  A C caller may pass any int there, and reading a value outside an
+// enumeration's range as that enumeration is undefined in C++, so the entry
+// points read the bytes as an int before they validate them.
+template <typename En>
+inline int abi_int(const En& e)
+{
+    static_assert(sizeof(En) == sizeof(int), "C enumerations have the size of int");
+    int v;
+    std::memcpy(&v, &e, sizeof v);
+    return v;
+}
 
 constexpr int kMaxLevels = 48;
 constexpr int kMaxN = 64;

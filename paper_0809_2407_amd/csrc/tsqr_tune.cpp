@@ -111,6 +111,13 @@ std::vector<Entry> read_cache(const char* path)
         parse_num(body, 0, "want_q", &q);
         double lk = 0;
         parse_num(body, 0, "leaf_kind", &lk);
+        pos = cb + 1;
+        // an entry with a value no option can take is skipped (and nothing is
+        // converted to an integer type that cannot hold it)
+        auto whole_in = [](double x, double lo, double hi) { return x >= lo && x <= hi && x == std::floor(x); };
+        if (!(whole_in(t, TSQR_TREE_AUTO, TSQR_TREE_HYBRID) && whole_in(lk, TSQR_LEAF_AUTO, TSQR_LEAF_RECURSIVE) &&
+              whole_in(l, 0, 4.0e18) && whole_in(fl, 0, 2147483647.0) && whole_in(w, 0, 4) && whole_in(q, 0, 1)))
+            continue;
         e.o.leaf_kind = (tsqr_leaf_kind)(int)lk;
         e.o.tree = (tsqr_tree)(int)t;
         e.o.leaf_rows = (int64_t)l;
@@ -119,7 +126,6 @@ std::vector<Entry> read_cache(const char* path)
         e.o.want_q = (int)q;
         e.ms = ms;
         out.push_back(e);
-        pos = cb + 1;
     }
     return out;
 }
@@ -173,7 +179,7 @@ tsqr_status tsqr_tune_cache_lookup(const char* cache_path, int64_t m, int64_t n,
     if (!cache_path) return -1;
     if (m < 1 || m < n) return -2;
     if (n < 1) return -3;
-    if (prec != TSQR_FP64 && prec != TSQR_MIXED) return -4;
+    if (tsqr::abi_int(prec) != TSQR_FP64 && tsqr::abi_int(prec) != TSQR_MIXED) return -4;
     if (want_q != 0 && want_q != 1) return -5;
     if (!out) return -6;
     const std::string key = class_key(m, n, prec, want_q);
@@ -192,8 +198,10 @@ tsqr_status tsqr_tune_cache_store(const char* cache_path, int64_t m, int64_t n, 
     if (!cache_path) return -1;
     if (m < 1 || m < n) return -2;
     if (n < 1) return -3;
-    if (prec != TSQR_FP64 && prec != TSQR_MIXED) return -4;
+    if (tsqr::abi_int(prec) != TSQR_FP64 && tsqr::abi_int(prec) != TSQR_MIXED) return -4;
     if (!opts || (opts->want_q != 0 && opts->want_q != 1)) return -5;
+    const int tv = tsqr::abi_int(opts->tree), kv = tsqr::abi_int(opts->leaf_kind);
+    if (tv < TSQR_TREE_AUTO || tv > TSQR_TREE_HYBRID || kv < TSQR_LEAF_AUTO || kv > TSQR_LEAF_RECURSIVE) return -5;
     const std::string key = class_key(m, n, prec, opts->want_q);
     std::vector<Entry> es = read_cache(cache_path);
     bool found = false;
@@ -213,7 +221,7 @@ tsqr_status tsqr_autotune(int64_t m, int64_t n, tsqr_precision prec, int want_q,
     if (m < 1 || m < n) return -1;
     if (n < 1) return -2;
     if (n > tsqr::kMaxN) return 3;
-    if (prec != TSQR_FP64 && prec != TSQR_MIXED) return -3;
+    if (tsqr::abi_int(prec) != TSQR_FP64 && tsqr::abi_int(prec) != TSQR_MIXED) return -3;
     if (want_q != 0 && want_q != 1) return -4;
     if (scratch && ld < m) return -6;
     if (reps < 1) return -9;

@@ -152,6 +152,30 @@ def test_tune_cache_roundtrip(tmp_path):
     assert T.tune_cache_lookup(path, 100000, 16) is None  # unreadable: treated as empty
 
 
+def test_tune_cache_skips_entries_no_option_can_take(tmp_path):
+    """Hand-edited or damaged cache entries (a tree out of range, a fractional
+    leaf length, a huge wave count) read as absent; a store of an out-of-range
+    tree is refused."""
+    import json
+
+    from paper_0809_2407_amd import _lib
+    from paper_0809_2407_amd import tsqr as T
+    path = str(tmp_path / "tune.json")
+    T.tune_cache_store(path, 100000, 16, {"tree": "hybrid", "flat_len": 4, "waves": 2}, 1.25)
+    doc = json.load(open(path))
+    (key, good), = doc["entries"].items()
+    for field, bad in (("tree", 9), ("tree", -1), ("leaf_rows", 1.5), ("waves", 1e30), ("flat_len", -3),
+                       ("want_q", 2), ("leaf_kind", 7)):
+        e = dict(good, **{field: bad})
+        json.dump({"format": doc["format"], "entries": {key: e}}, open(path, "w"))
+        assert T.tune_cache_lookup(path, 100000, 16) is None, (field, bad)
+    json.dump(doc, open(path, "w"))
+    assert T.tune_cache_lookup(path, 100000, 16)["opts"]["flat_len"] == 4
+    lib = _lib.load()
+    bad = _lib.TsqrOpts(9, 0, 0, 0, 0, 1)
+    assert lib.tsqr_tune_cache_store(path.encode(), 100000, 16, 0, ctypes.byref(bad), 1.0) == -5
+
+
 def test_tuned_options_reach_plan_query(tmp_path, monkeypatch):
     from paper_0809_2407_amd import tsqr as T
     path = str(tmp_path / "tune.json")
