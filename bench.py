@@ -132,22 +132,28 @@ def make_input(w: dict, seed: int):
     return A, sig
 
 
+# The files the kernels' code comes from: a byte-counter summary stays valid
+# while these are unchanged and the launch geometry (leaf and tile rows) is
+# the one it was taken at; host code (argument checks, plans) does not enter.
+KERNEL_SOURCES = ("tsqr_kernels.h", "tsqr_internal.h", "tsqr_dispatch.hip", "tsqr_np_0.hip", "tsqr_np_1.hip",
+                  "tsqr_np_2.hip", "tsqr_np_3.hip")
+
+
 def sources_sha256() -> str:
-    import glob
     import hashlib
 
     h = hashlib.sha256()
     here = os.path.dirname(os.path.abspath(__file__))
-    for f in sorted(glob.glob(os.path.join(here, "paper_0809_2407_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(here, "paper_0809_2407_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(m: int, n: int, kernel: str):
+def measured_traffic(m: int, n: int, kernel: str, leaf_rows: int, tile_rows: int):
     """HBM bytes (read + write) of one launch of `kernel` from the committed
     rocprofv3 byte-counter summary under profiles/, or None when no summary
-    matches this workload and the current kernel sources."""
+    matches this workload, its geometry and the current kernel sources."""
     import glob
     import re
 
@@ -160,7 +166,8 @@ def measured_traffic(m: int, n: int, kernel: str):
                 d = json.loads(blk)
             except ValueError:
                 continue
-            if d.get("workload_m") == m and d.get("workload_n") == n and d.get("sources_sha256") == sha:
+            if (d.get("workload_m") == m and d.get("workload_n") == n and d.get("sources_sha256") == sha
+                    and d.get("leaf_rows") == leaf_rows and d.get("tile_rows") == tile_rows):
                 k = d.get("kernels", {}).get(kernel)
                 if k:
                     return k["read_bytes"] + k["write_bytes"]
@@ -383,7 +390,8 @@ def run_single(args, wname: str, cpu: bool, check: bool):
     achieved = phase_bytes[dom] / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(m, n, dom) if mode == "rq" and not mixed else None,
+                "traffic": (measured_traffic(m, n, dom, info["leaf_rows"], info["tile_rows"])
+                            if mode == "rq" and not mixed else None),
                 "kernel": dom, "kernel_ms": dom_ms, "bytes_per_launch": phase_bytes[dom],
                 "timing": "HIP events on the plan's stream around each launch of the kernel, "
                           "mean over the timed steps"}

@@ -53,10 +53,14 @@ def test_workloads_are_well_formed():
 
 def test_profiles_match_the_kernel_sources():
     # the default workload's dominant kernel and the Q kernel have byte counters
-    # taken from the sources as they are now
+    # taken from the kernel sources as they are now, at the geometry a plan
+    # chooses for it
+    from paper_0809_2407_amd import tsqr as T
+
     m, n = bench.WORKLOADS[bench.DEFAULT]["m"], bench.WORKLOADS[bench.DEFAULT]["n"]
+    info = T.plan_query(m, n)
     for kernel in ("leaf", "form_q"):
-        t = bench.measured_traffic(m, n, kernel)
+        t = bench.measured_traffic(m, n, kernel, info["leaf_rows"], info["tile_rows"])
         assert t is not None, f"no byte counters for {kernel} at the current kernel sources"
         # within 15% of the algorithmic 16mn bytes (counters include T slots and re-reads)
         assert 16.0 * m * n <= t <= 1.15 * 16.0 * m * n, (kernel, t)
