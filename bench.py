@@ -803,10 +803,13 @@ def line(metric: str, value: float, unit: str, steps: int, warmup: int, ms: floa
 
 
 def caqr_line(args, name: str) -> dict:
-    """CAQR (Sec. 6) of a tall general matrix with TSQR panels, then Q^T B on
-    k columns: per panel the panel's TSQR and the tree-structured update of the
-    trailing columns.  R against the oracle's plain Householder R of the whole
-    matrix, Q^T B through the column norms it must keep."""
+    """CAQR (Sec. 6) of a tall general matrix with TSQR panels and Q^T B on k
+    columns carried along (tsqr_caqr_factor_rhs on [A B]): per panel the
+    panel's TSQR and one tree-structured update of the trailing columns and B
+    together.  R against the oracle's plain Householder R of the whole matrix,
+    Q^T B through the column norms it must keep.  The same results from
+    tsqr_caqr_factor then tsqr_caqr_apply_qt (B in passes of its own) are
+    timed beside it."""
     import numpy as np
     import torch
     from paper_0809_2407_amd import tsqr as T
@@ -818,26 +821,38 @@ def caqr_line(args, name: str) -> dict:
     g = torch.Generator(device="cuda")
     g.manual_seed(args.seed + 1)
     B0 = torch.randn((k, m), generator=g, device="cuda", dtype=torch.float64).t()
-    A, B, R = T.colmajor(m, n), T.colmajor(m, k), T.colmajor(n, n)
+    AB, R = T.colmajor(m, n + k), T.colmajor(n, n)
+    B = AB[:, n:]
     plan = T.CaqrPlan(m, n, b)
     info = plan.info()
 
     def prepare():
-        A.copy_(A0)
+        AB[:, :n].copy_(A0)
         B.copy_(B0)
 
-    def work():
-        plan.factor(A, R)
-        plan.apply_qt(A, B)
+    t = events_time(lambda: plan.factor_rhs(AB, R), args.steps, args.warmup, prepare)
+    t2 = same = None
+    if not args.no_extras:
+        # the same results with B in passes of its own
+        A2, B2, R2 = T.colmajor(m, n), T.colmajor(m, k), T.colmajor(n, n)
 
-    t = events_time(work, args.steps, args.warmup, prepare)
+        def prepare2():
+            A2.copy_(A0)
+            B2.copy_(B0)
+
+        def separate():
+            plan.factor(A2, R2)
+            plan.apply_qt(A2, B2)
+
+        t2 = events_time(separate, args.steps, args.warmup, prepare2)
+        same = bool(torch.equal(R, R2) and torch.equal(B, B2))
+        del A2, B2, R2
     fl = flops_r(m, n) + 4.0 * m * n * k - 2.0 * n * n * k
     by = 0.0
     for j in range(info["num_panels"]):
         mj, bj = m - j * b, min(b, n - j * b)
         cj = n - j * b - bj
-        by += 16.0 * mj * bj + -(-cj // 32) * 8.0 * mj * bj + 16.0 * mj * cj
-        by += -(-k // 32) * 8.0 * mj * bj + 16.0 * mj * k
+        by += 16.0 * mj * bj + -(-(cj + k) // 32) * 8.0 * mj * bj + 16.0 * mj * (cj + k)
     t_roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), by / (HBM_PEAK_GBS * 1e9)) * 1e3
     with torch.no_grad():
         keep = float(((torch.linalg.norm(B, dim=0) - torch.linalg.norm(B0, dim=0)).abs()
@@ -847,9 +862,11 @@ def caqr_line(args, name: str) -> dict:
                {"workload": name, "m": m, "n": n, "panel": b, "num_panels": info["num_panels"], "rhs": k,
                 "sigma": f"logspace(0,-{w['decades']:g},{n})", "seed": args.seed, "parallelism": "single GPU"})
     res["step_ms"] = t
+    res["separate_rhs_passes"] = None if t2 is None else {
+        "step_ms": t2, "speedup_median": t2["median"] / t["median"], "same_R_and_QtB_bitwise": same}
     res["roofline"] = None
     res["path_roofline"] = {"t_roof_ms": t_roof, "frac_median": t_roof / t["median"], "bytes": by, "flops": fl,
-                            "bytes_model": "per panel: 16 m_j b (panel TSQR), 8 m_j b per 32 trailing or B "
+                            "bytes_model": "per panel: 16 m_j b (panel TSQR), 8 m_j b per 32 trailing and B "
                                            "columns (reflectors re-read) + 16 m_j per trailing or B column"}
     res["accuracy"] = {"qtb_column_norms_kept": keep}
     res["cpu_baseline"] = None
@@ -866,7 +883,8 @@ def caqr_line(args, name: str) -> dict:
         res["cpu_baseline"] = {"value": flops_r(m, n) / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
                                "sample": f"plain Householder R of the whole {m} x {n} matrix, {dt:.2f} s",
                                "host": {"nproc": os.cpu_count(), "model": cpu_model()}}
-    log(f"CAQR: {t['median']:.3f} ms median, accuracy {res['accuracy']}")
+    sep = f" ({t2['median']:.3f} with B in passes of its own)" if t2 else ""
+    log(f"CAQR: {t['median']:.3f} ms median{sep}, accuracy {res['accuracy']}")
     plan.close()
     return res
 
@@ -1031,7 +1049,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-peaks", action="store_true",
                     help="skip measuring the part's copy, read, FMA and MFMA ceilings")
     ap.add_argument("--no-extras", action="store_true",
-                    help="the default workload only (no mixed-vs-FP64 or batched records)")
+                    help="the default workload only (no mixed-vs-FP64, batched or beyond-TSQR records); "
+                         "CAQR without the timing of B in passes of its own")
     ap.add_argument("--leaf-kind", default="auto", choices=["auto", "compact_wy", "recursive"],
                     help="local QR of the leaf tiles (single-problem workloads)")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -387,6 +387,16 @@ tsqr_status tsqr_caqr_plan_create(tsqr_caqr_plan* p, int64_t m, int64_t n, int64
  * Errors: -1 p, -2 A NULL, -3 lda < m, -4 R NULL, -5 ldr < n. */
 tsqr_status tsqr_caqr_factor(tsqr_caqr_plan p, double* A, int64_t lda, double* R, int64_t ldr);
 
+/* tsqr_caqr_factor with k right-hand sides carried along (Alg. 3 on the
+ * augmented matrix [A B]): the k columns that follow A's n columns in the
+ * same array (B = A + n lda, leading dimension lda, so the array holds
+ * n + k columns) join each panel's trailing update, one pass of Q_j^T over
+ * both, and on return hold Q^T B: the values tsqr_caqr_apply_qt gives after
+ * tsqr_caqr_factor, with n/b fewer passes up the panels' trees.  k = 0 is
+ * tsqr_caqr_factor.  Asynchronous.  Errors: as tsqr_caqr_factor, and -6
+ * k < 0. */
+tsqr_status tsqr_caqr_factor_rhs(tsqr_caqr_plan p, double* A, int64_t lda, double* R, int64_t ldr, int64_t k);
+
 /* B (m x k, ldb >= m, device) <- Q^T B in place, Q = Q_0 diag(I, Q_1) ... the
  * orthogonal factor of the last tsqr_caqr_factor (A_factored its output).
  * Rows 0..n-1 become D Q_thin^T B (D the signs that made diag(R) >= 0); the

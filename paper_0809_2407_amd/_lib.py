@@ -55,7 +55,7 @@ EXPORTED = [
     "tsqr_factor_r_noalloc",
     "tsqr_cmp_plan_create", "tsqr_cmp_factor", "tsqr_cmp_breakdown", "tsqr_cmp_plan_destroy",
     "tsqr_stream_plan_create", "tsqr_stream_factor", "tsqr_stream_plan_info", "tsqr_stream_plan_destroy",
-    "tsqr_caqr_plan_create", "tsqr_caqr_factor", "tsqr_caqr_apply_qt", "tsqr_caqr_plan_info",
+    "tsqr_caqr_plan_create", "tsqr_caqr_factor", "tsqr_caqr_factor_rhs", "tsqr_caqr_apply_qt", "tsqr_caqr_plan_info",
     "tsqr_caqr_plan_destroy",
 ]
 
@@ -153,6 +153,8 @@ def load(path: str = LIB_PATH):
     lib.tsqr_caqr_plan_create.restype = ctypes.c_int
     lib.tsqr_caqr_factor.argtypes = [P, dp, i64, dp, i64]
     lib.tsqr_caqr_factor.restype = ctypes.c_int
+    lib.tsqr_caqr_factor_rhs.argtypes = [P, dp, i64, dp, i64, i64]
+    lib.tsqr_caqr_factor_rhs.restype = ctypes.c_int
     lib.tsqr_caqr_apply_qt.argtypes = [P, dp, i64, i64, dp, i64]
     lib.tsqr_caqr_apply_qt.restype = ctypes.c_int
     lib.tsqr_caqr_plan_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]

@@ -84,13 +84,14 @@ tsqr_status tsqr_caqr_plan_create(tsqr_caqr_plan* out, int64_t m, int64_t n, int
     return 0;
 }
 
-tsqr_status tsqr_caqr_factor(tsqr_caqr_plan p, double* A, int64_t lda, double* R, int64_t ldr)
+}  // extern "C"
+
+namespace {
+
+// Alg. 3 on [A B]: the k columns after A's n (same array, same lda) are
+// updated with the trailing matrix, panel by panel.
+tsqr_status caqr_factor(tsqr_caqr_plan p, double* A, int64_t lda, double* R, int64_t ldr, int64_t k)
 {
-    if (!p) return -1;
-    if (!A) return -2;
-    if (lda < p->m) return -3;
-    if (!R) return -4;
-    if (ldr < p->n) return -5;
     p->state = 0;
     const int64_t n = p->n, b = p->b;
     // the strictly lower part of R is zero; the panels fill the rest
@@ -104,10 +105,12 @@ tsqr_status tsqr_caqr_factor(tsqr_caqr_plan p, double* A, int64_t lda, double* R
         tsqr_status st = tsqr_factor(p->panels[j], Aj, lda, R + j0 + j0 * ldr, ldr);
         if (st != 0) return st;
         const int64_t rest = n - j0 - w;
-        if (rest == 0) break;
+        if (rest + k == 0) break;
+        // one pass of Q_j^T over the trailing columns and the right-hand sides
         double* C = Aj + w * lda;
-        st = tsqr_apply_qt(p->panels[j], Aj, lda, rest, C, lda);
+        st = tsqr_apply_qt(p->panels[j], Aj, lda, rest + k, C, lda);
         if (st != 0) return st;
+        if (rest == 0) continue;
         // the top w rows of the updated trailing columns are R's row block
         e = hipMemcpy2DAsync(R + j0 + (j0 + w) * ldr, (size_t)ldr * sizeof(double), C, (size_t)lda * sizeof(double),
                              (size_t)w * sizeof(double), (size_t)rest, hipMemcpyDeviceToDevice, p->stream);
@@ -115,6 +118,31 @@ tsqr_status tsqr_caqr_factor(tsqr_caqr_plan p, double* A, int64_t lda, double* R
     }
     p->state = 1;
     return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+tsqr_status tsqr_caqr_factor(tsqr_caqr_plan p, double* A, int64_t lda, double* R, int64_t ldr)
+{
+    if (!p) return -1;
+    if (!A) return -2;
+    if (lda < p->m) return -3;
+    if (!R) return -4;
+    if (ldr < p->n) return -5;
+    return caqr_factor(p, A, lda, R, ldr, 0);
+}
+
+tsqr_status tsqr_caqr_factor_rhs(tsqr_caqr_plan p, double* A, int64_t lda, double* R, int64_t ldr, int64_t k)
+{
+    if (!p) return -1;
+    if (!A) return -2;
+    if (lda < p->m) return -3;
+    if (!R) return -4;
+    if (ldr < p->n) return -5;
+    if (k < 0) return -6;
+    return caqr_factor(p, A, lda, R, ldr, k);
 }
 
 tsqr_status tsqr_caqr_apply_qt(tsqr_caqr_plan p, const double* A, int64_t lda, int64_t k, double* B, int64_t ldb)

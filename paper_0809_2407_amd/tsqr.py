@@ -359,7 +359,7 @@ class StreamPlan:
 
 
 class CaqrPlan:
-    """tsqr_caqr_plan_create / tsqr_caqr_factor / tsqr_caqr_apply_qt /
+    """tsqr_caqr_plan_create / tsqr_caqr_factor / tsqr_caqr_factor_rhs / tsqr_caqr_apply_qt /
     tsqr_caqr_plan_info / tsqr_caqr_plan_destroy: CAQR of an m x n matrix
     (Sec. 6) with TSQR panels of `panel` columns."""
 
@@ -384,6 +384,20 @@ class CaqrPlan:
             R = colmajor(self.n, self.n, device=A.device)
         ldr = _ld(R, self.n, "R")
         check("tsqr_caqr_factor", self._lib.tsqr_caqr_factor(self._h, A.data_ptr(), lda, R.data_ptr(), ldr))
+        return R
+
+    def factor_rhs(self, AB: torch.Tensor, R: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """tsqr_caqr_factor_rhs on AB = [A B] (m x (n + k), column-major): A is
+        factored in place and B becomes Q^T B; returns R."""
+        if AB.dim() != 2 or AB.shape[1] < self.n:
+            raise ValueError(f"AB: expected at least {self.n} columns")
+        k = AB.shape[1] - self.n
+        lda = _ld(AB, self.m, "AB")
+        if R is None:
+            R = colmajor(self.n, self.n, device=AB.device)
+        ldr = _ld(R, self.n, "R")
+        check("tsqr_caqr_factor_rhs", self._lib.tsqr_caqr_factor_rhs(self._h, AB.data_ptr(), lda, R.data_ptr(), ldr,
+                                                                     k))
         return R
 
     def apply_qt(self, A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:

@@ -255,6 +255,7 @@ def test_caqr_plans_reject_arguments_without_device():
     assert lib.tsqr_caqr_plan_create(ctypes.byref(h), 100, 0, 0, None) == -3
     assert lib.tsqr_caqr_plan_create(ctypes.byref(h), 100, 4, 65, None) == -4
     assert lib.tsqr_caqr_factor(None, 1, 1, 1, 1) == -1
+    assert lib.tsqr_caqr_factor_rhs(None, 1, 1, 1, 1, 0) == -1
     assert lib.tsqr_caqr_apply_qt(None, 1, 1, 1, 1, 1) == -1
     assert lib.tsqr_caqr_plan_info(None, None, None) == -1
     assert lib.tsqr_caqr_plan_destroy(None) == -1

@@ -76,3 +76,44 @@ def test_caqr_refactor_and_errors():
             Ad = T.to_colmajor(torch.from_numpy(A))
             R = p.factor(Ad).cpu().numpy()
             assert rel_diff(R, oracle.qr_reference(A, want_q=False)) <= 1e-13
+
+
+@pytest.mark.parametrize("m,n,panel,k", [
+    (20000, 200, 32, 5),    # trailing widths 168, 136, ..., 8: B shares the last 32-column chunk
+    (4096, 512, 64, 40),    # more right-hand sides than one chunk
+    (2000, 1000, 32, 3),    # the last panels see few rows
+    (3000, 64, 64, 7),      # one panel: its only pass is over B
+])
+def test_caqr_with_right_hand_sides_equals_factor_then_apply(m, n, panel, k):
+    """B carried as columns n .. n+k-1 of the factored array: R, the reflectors
+    and Q^T B bit for bit those of tsqr_caqr_factor followed by
+    tsqr_caqr_apply_qt (the same operations on every column, in the same order),
+    and Q^T B's top rows against the oracle's thin Q."""
+    torch = need_gpu()
+    from paper_0809_2407_amd import tsqr as T
+
+    announce(f"caqr with {k} right-hand sides m={m} n={n} panel={panel}")
+    A, _ = synth.prescribed_sigma(m, n, seed=930 + n, decades=1)
+    Bh = synth.gaussian(m, k, 931)
+    with T.CaqrPlan(m, n, panel) as p:
+        Ad, Bd = T.to_colmajor(torch.from_numpy(A)), T.to_colmajor(torch.from_numpy(Bh))
+        R0 = p.factor(Ad)
+        p.apply_qt(Ad, Bd)
+        AB = T.colmajor(m, n + k)
+        AB[:, :n].copy_(torch.from_numpy(A))
+        AB[:, n:].copy_(torch.from_numpy(Bh))
+        R1 = p.factor_rhs(AB)
+        # the plan then holds this factorisation: Q^T of a fresh copy of B
+        B2 = T.to_colmajor(torch.from_numpy(Bh))
+        p.apply_qt(AB[:, :n], B2)
+        assert p._lib.tsqr_caqr_factor_rhs(p._h, AB.data_ptr(), m, R1.data_ptr(), n, -1) == -6
+        torch.cuda.synchronize()
+        assert torch.equal(R0, R1)
+        assert torch.equal(Ad, AB[:, :n])
+        assert torch.equal(Bd, AB[:, n:])
+        assert torch.equal(B2, Bd)
+    X = Bd.cpu().numpy()
+    Ro, Qo = oracle.qr_reference(A)
+    assert rel_diff(R0.cpu().numpy(), Ro) <= 1e-13
+    assert np.abs(X[:n] - Qo.T @ Bh).max() <= 1e-12 * np.abs(Bh).max() * np.sqrt(m)
+    assert np.allclose(np.linalg.norm(X, axis=0), np.linalg.norm(Bh, axis=0), rtol=1e-12)
