@@ -130,11 +130,14 @@ typedef struct {
 
 typedef struct tsqr_plan_s* tsqr_plan;
 
-/* Create a plan for m x n problems (n <= m, 1 <= n <= 64) on hip_stream (a
+/* Create a plan for m x n problems (n <= m, 0 <= n <= 64) on hip_stream (a
  * hipStream_t, NULL = the default stream).  The plan allocates its device
  * workspace (per-tile compact-WY factors T, per-node tree factors, seeds, signs)
  * with hipMalloc here and frees it in tsqr_plan_destroy.
- * Errors: -1 p NULL, -2 m < n or m < 1, -3 n < 1 or n > 64 (3 = unsupported for
+ * The empty problem (n = 0, any m >= 0) gets a plan with no workspace: its
+ * calls check their leading dimensions, reference no matrix (the pointers may
+ * be NULL), launch nothing and return 0 (Q is m x 0, Q^T B = B).
+ * Errors: -1 p NULL, -2 m < n or m < 0, -3 n < 0 or n > 64 (3 = unsupported for
  * n > 64), -4 bad precision, -5 bad option field; 2 out of memory. */
 tsqr_status tsqr_plan_create(tsqr_plan* p, int64_t m, int64_t n, tsqr_precision prec,
                              const tsqr_opts* opts, void* hip_stream);
@@ -172,7 +175,7 @@ tsqr_status tsqr_form_q(tsqr_plan p, const double* A_factored, int64_t lda, doub
  * factor of the tree (the reduction of Sec. 4.1).  Rows 0..n-1 become D Q^T B
  * with Q the thin factor returned by tsqr_form_q; rows n..m-1 hold coordinates
  * of B in the tree's basis of the orthogonal complement (they depend on the
- * tree).  k = 0 returns 0 at once (B may then be NULL).  Right-hand sides are
+ * tree).  k = 0 returns 0 at once (B may then be NULL, as when m = 0).  Right-hand sides are
  * processed 32 at a time.  On a MIXED plan Q is Q1 R2^{-1}, which has no
  * complement: rows 0..n-1 become Q^T B = R2^{-T} (Q1^T B) (Q1^T B summed in
  * FP64 over 64-row groups, pairwise, like the second pass's Gram), rows n..m-1
@@ -303,10 +306,11 @@ tsqr_status tsqr_tune_cache_store(const char* cache_path, int64_t m, int64_t n, 
  * leaf, so leaf_kind must be AUTO or COMPACT_WY). */
 typedef struct tsqr_batched_plan_s* tsqr_batched_plan;
 
-/* count problems with sizes m[i] x n[i] (host arrays).  Errors: -1 p NULL,
- * -2 count < 1, -3 m NULL or some m[i] < n[i] or m[i] < 1 or n[i] < 1, -4 n
- * NULL, -5 bad precision, -6 bad option field; 3 n[i] > 64 or a tree too deep;
- * 2 out of memory. */
+/* count problems with sizes m[i] x n[i] (host arrays).  An empty problem
+ * (n[i] = 0) takes no work and no workspace, and its pointers may be NULL.
+ * Errors: -1 p NULL, -2 count < 1, -3 m NULL or some m[i] < n[i] or m[i] < 0
+ * or n[i] < 0, -4 n NULL, -5 bad precision, -6 bad option field; 3 n[i] > 64
+ * or a tree too deep; 2 out of memory. */
 tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* p, int count, const int64_t* m, const int64_t* n,
                                      tsqr_precision prec, const tsqr_opts* opts, void* hip_stream);
 
@@ -377,8 +381,9 @@ tsqr_status tsqr_stream_plan_destroy(tsqr_stream_plan p);
  * in the plan; tsqr_caqr_apply_qt applies Q^T. */
 typedef struct tsqr_caqr_plan_s* tsqr_caqr_plan;
 
-/* Errors: -1 p NULL, -2 m < 1 or m < n, -3 n < 1, -4 panel < 0 or > 64;
- * 2 out of memory. */
+/* n = 0 (any m >= 0) gives a plan with no panels, whose calls reference no
+ * matrix and return 0.  Errors: -1 p NULL, -2 m < 0 or m < n, -3 n < 0,
+ * -4 panel < 0 or > 64; 2 out of memory. */
 tsqr_status tsqr_caqr_plan_create(tsqr_caqr_plan* p, int64_t m, int64_t n, int64_t panel, void* hip_stream);
 
 /* Factor A (m x n, lda >= m, device; overwritten by the panels' reflectors
@@ -477,7 +482,8 @@ tsqr_status tsqr_cmp_plan_destroy(tsqr_cmp_plan p);
  * refused with status 6 (at 64 columns that is m above about 2^24 rows, at
  * 32 columns about 2^27).  Every call on one GPU shares that GPU's array:
  * calls that overlap on one GPU (other streams, other host threads) race.
- * Errors: -1 m < 1 or m < n, -2 n < 1 (3 for n > 64), -3 A NULL, -4 lda < m,
+ * n = 0 returns 0 at once (A and R may then be NULL).
+ * Errors: -1 m < 0 or m < n, -2 n < 0 (3 for n > 64), -3 A NULL, -4 lda < m,
  * -5 R NULL, -6 ldr < n; 6 beyond the array; 1 HIP error. */
 tsqr_status tsqr_factor_r_noalloc(int64_t m, int64_t n, const double* A, int64_t lda, double* R, int64_t ldr,
                                   void* hip_stream, tsqr_info* info);

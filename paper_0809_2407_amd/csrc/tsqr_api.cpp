@@ -316,15 +316,15 @@ const char* tsqr_status_string(tsqr_status s)
 static tsqr_status check_plan_args(int64_t m, int64_t n, int pv, const tsqr_opts* opts,
                                    tsqr_opts& o, tsqr::Layout& L)
 {
-    if (m < 1 || m < n) return -2;
-    if (n < 1) return -3;
+    if (m < 0 || m < n) return -2;
+    if (n < 0) return -3;
     if (n > tsqr::kMaxN) return 3;
     if (pv != TSQR_FP64 && pv != TSQR_MIXED) return -4;
     const tsqr_precision prec = (tsqr_precision)pv;
     std::memset(&o, 0, sizeof(o));
     o.want_q = 1;
     tsqr_opts tuned;
-    if (!opts && tsqr::tuned_opts(m, n, prec, 1, &tuned)) opts = &tuned;
+    if (!opts && n > 0 && tsqr::tuned_opts(m, n, prec, 1, &tuned)) opts = &tuned;
     if (opts) {
         o = *opts;
         const int tv = tsqr::abi_int(o.tree);
@@ -334,6 +334,14 @@ static tsqr_status check_plan_args(int64_t m, int64_t n, int pv, const tsqr_opts
         if (o.want_q != 0 && o.want_q != 1) return -5;
         const int kv = tsqr::abi_int(o.leaf_kind);
         if (kv < TSQR_LEAF_AUTO || kv > TSQR_LEAF_RECURSIVE) return -5;
+    }
+    if (n == 0) {
+        // the empty problem (n = 0, any m >= 0): no tiles, no tree and no
+        // workspace; the calls on its plan check their arguments and return
+        L = tsqr::Layout{};
+        L.m = m;
+        L.mixed = prec == TSQR_MIXED;
+        return 0;
     }
     if (!tsqr::make_layout(L, m, n, o.leaf_rows, o.flat_len, o.tree, o.waves, prec == TSQR_MIXED, o.want_q != 0))
         return 3;
@@ -356,7 +364,7 @@ static void fill_info(const tsqr::Layout& L, tsqr_precision prec, tsqr_info* out
     out->num_leaves = L.P;
     out->num_tiles = L.ntiles;
     out->tree_levels = L.levels;
-    out->tree = L.P == 1 ? TSQR_TREE_FLAT : (L.f == 1 ? TSQR_TREE_BINARY : TSQR_TREE_HYBRID);
+    out->tree = L.P <= 1 ? TSQR_TREE_FLAT : (L.f == 1 ? TSQR_TREE_BINARY : TSQR_TREE_HYBRID);
     out->waves = L.waves;
     out->precision = prec;
     out->workspace_bytes = L.total * (int64_t)sizeof(double);
@@ -391,6 +399,10 @@ tsqr_status tsqr_plan_create(tsqr_plan* p, int64_t m, int64_t n, tsqr_precision 
     P->tree = o.tree;
     P->want_q = o.want_q;
     P->stream = (hipStream_t)hip_stream;
+    if (P->L.n == 0) {  // the empty problem: nothing to allocate
+        *p = P;
+        return 0;
+    }
     hipError_t e = hipMalloc((void**)&P->ws, (size_t)P->L.total * sizeof(double));
     if (e != hipSuccess) {
         delete P;
@@ -428,17 +440,21 @@ tsqr_status tsqr_factor_into(tsqr_plan p, const double* A, int64_t lda, double* 
                              int64_t ldr)
 {
     if (!p) return -1;
-    if (!A) return -2;
+    if (!A && p->L.n > 0) return -2;  // an empty problem references no matrix
     if (lda < p->L.m) return -3;
     const bool want_q = p->want_q != 0;
     if (want_q && !p->L.mixed) {
-        if (!V) return -4;
+        if (!V && p->L.n > 0) return -4;
         if (ldv < p->L.m) return -5;
         if ((const double*)V == A && ldv != lda) return -5;
     }
-    if (!R) return -6;
+    if (!R && p->L.n > 0) return -6;
     if (ldr < p->L.n) return -7;
     p->state = 0;
+    if (p->L.n == 0) {
+        p->state = want_q ? 1 : 2;
+        return 0;
+    }
     if (p->L.mixed) return factor_mixed(p, A, lda, R, ldr);
     hipError_t e = run_phase(p, TSQR_PHASE_LEAF, [&] {
         return tsqr::launch_leaf_factor(p->L, A, lda, V, want_q ? ldv : lda, p->ws, want_q, p->stream);
@@ -467,21 +483,24 @@ tsqr_status tsqr_factor(tsqr_plan p, double* A, int64_t lda, double* R, int64_t 
 tsqr_status tsqr_form_q(tsqr_plan p, const double* A_factored, int64_t lda, double* Q, int64_t ldq)
 {
     if (!p) return -1;
+    const bool empty = p->L.n == 0;  // no reflectors: Q is m x 0, nothing to write
     if (p->L.mixed) {
         // the reflectors live in the plan: A_factored and lda are not used
-        if (!Q) return -4;
+        if (!Q && !empty) return -4;
         if (ldq < p->L.m) return -5;
         if (p->state != 1) return 4;
+        if (empty) return 0;
         return hip_status(run_phase(p, TSQR_PHASE_FORM_Q, [&] {
             return tsqr::launch_reorth_q(p->L, p->ws, Q, ldq, p->stream);
         }));
     }
-    if (!A_factored) return -2;
+    if (!A_factored && !empty) return -2;
     if (lda < p->L.m) return -3;
-    if (!Q) return -4;
+    if (!Q && !empty) return -4;
     if (ldq < p->L.m) return -5;
     if ((const double*)Q == A_factored && ldq != lda) return -5;
     if (p->state != 1) return 4;
+    if (empty) return 0;
     hipError_t e = hipSuccess;
     if (p->L.levels > 0)
         e = run_phase(p, TSQR_PHASE_SEEDS, [&] { return tsqr::launch_seeds(p->L, p->ws, p->stream); });
@@ -499,20 +518,22 @@ tsqr_status tsqr_apply_qt(tsqr_plan p, const double* A_factored, int64_t lda, in
         // the reflectors live in the plan: A_factored and lda are not used
         if (k < 0) return -4;
         if (k == 0) return 0;
-        if (!B) return -5;
+        if (!B && p->L.m > 0) return -5;  // a 0 x k B is not referenced
         if (ldb < p->L.m) return -6;
         if (p->state != 1) return 4;
+        if (p->L.n == 0) return 0;  // no reflectors: Q^T B = B
         return hip_status(run_phase(p, TSQR_PHASE_APPLY, [&] {
             return tsqr::launch_qtb_mixed(p->L, p->ws, k, B, ldb, p->stream);
         }));
     }
-    if (!A_factored) return -2;
+    if (!A_factored && p->L.n > 0) return -2;
     if (lda < p->L.m) return -3;
     if (k < 0) return -4;
     if (k == 0) return 0;  // nothing to apply; B may be NULL
-    if (!B) return -5;
+    if (!B && p->L.m > 0) return -5;  // a 0 x k B is not referenced
     if (ldb < p->L.m) return -6;
     if (p->state != 1) return 4;
+    if (p->L.n == 0) return 0;  // no reflectors: Q^T B = B
     hipError_t e = run_phase(p, TSQR_PHASE_APPLY, [&] {
         return tsqr::launch_apply_qt(p->L, A_factored, lda, k, B, ldb, p->ws, p->stream);
     });
@@ -524,7 +545,7 @@ tsqr_status tsqr_plan_info(tsqr_plan p, tsqr_info* out)
     if (!p) return -1;
     if (!out) return -2;
     fill_info(p->L, p->prec, out);
-    if (p->L.mixed && p->state == 1) {
+    if (p->L.mixed && p->state == 1 && p->L.n > 0) {
         // what the second pass measured: waits for the plan's stream
         double h[2] = {0.0, 0.0};
         hipError_t e = hipStreamSynchronize(p->stream);
@@ -539,10 +560,11 @@ tsqr_status tsqr_plan_info(tsqr_plan p, tsqr_info* out)
 tsqr_status tsqr_mixed_q1(tsqr_plan p, float* Q1, int64_t ldq1)
 {
     if (!p) return -1;
-    if (!Q1) return -2;
+    if (!Q1 && p->L.n > 0) return -2;
     if (ldq1 < p->L.m) return -3;
     if (!p->L.mixed) return 3;
     if (p->state != 1) return 4;
+    if (p->L.n == 0) return 0;
     hipError_t e = hipMemcpy2DAsync(Q1, (size_t)ldq1 * sizeof(float), p->ws + p->L.off_Q1,
                                     (size_t)p->L.ld32 * sizeof(float), (size_t)p->L.m * sizeof(float),
                                     (size_t)p->L.n, hipMemcpyDeviceToDevice, p->stream);

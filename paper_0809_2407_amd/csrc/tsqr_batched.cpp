@@ -147,7 +147,7 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
         if (kv != TSQR_LEAF_AUTO && kv != TSQR_LEAF_COMPACT_WY) return -6;
     }
     for (int i = 0; i < count; ++i) {
-        if (n[i] < 1 || m[i] < 1 || m[i] < n[i]) return -3;
+        if (n[i] < 0 || m[i] < 0 || m[i] < n[i]) return -3;
         if (n[i] > tsqr::kMaxN) return 3;
     }
     tsqr_batched_plan_s* p = new (std::nothrow) tsqr_batched_plan_s();
@@ -163,6 +163,13 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
     int64_t off = 0;
     for (int i = 0; i < count; ++i) {
         tsqr::Layout& L = p->L[i];
+        if (n[i] == 0) {
+            // an empty problem: no work items, no workspace, pointers not referenced
+            L.m = m[i];
+            bp[i].m = m[i];
+            bp[i].ws_off = off;
+            continue;
+        }
         // without options, each problem takes the cached choice of its class (if any)
         tsqr_opts oi = o;
         tsqr_opts tuned;
@@ -214,7 +221,8 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
     // take items in order)
     std::vector<int> widths;
     for (int i = 0; i < count; ++i)
-        if (std::find(widths.begin(), widths.end(), p->L[i].np) == widths.end()) widths.push_back(p->L[i].np);
+        if (p->L[i].n > 0 && std::find(widths.begin(), widths.end(), p->L[i].np) == widths.end())
+            widths.push_back(p->L[i].np);
     std::sort(widths.begin(), widths.end());
     std::vector<std::vector<int64_t>> lists;  // host copies, concatenated below
     struct ClassLists {
@@ -280,7 +288,7 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
         all.insert(all.end(), lists[k].begin(), lists[k].end());
     }
 
-    hipError_t e = hipMalloc((void**)&p->ws, (size_t)p->ws_doubles * sizeof(double));
+    hipError_t e = hipMalloc((void**)&p->ws, (size_t)std::max<int64_t>(1, p->ws_doubles) * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_probs, sizeof(tsqr::BatchProblem) * count);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, sizeof(int64_t) * std::max<size_t>(1, all.size()));
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_args_f, sizeof(tsqr::BatchArgs) * count);
@@ -310,7 +318,7 @@ tsqr_status tsqr_batched_plan_create(tsqr_batched_plan* out, int count, const in
         C.gsum_items = p->d_items + start[where[c].gsum];
         C.rq_items = p->d_items + start[where[c].rq];
     }
-    if (mixed) {
+    if (mixed && p->ws_doubles > 0) {
         // the FP32 workspaces are read in whole tiles and 16-column blocks: what
         // the kernels never write (rows past the last tile, columns past np) stays zero
         e = hipMemset(p->ws, 0, (size_t)p->ws_doubles * sizeof(double));
@@ -332,12 +340,17 @@ tsqr_status tsqr_batched_factor(tsqr_batched_plan p, double* const* A, const int
     if (!R) return -4;
     if (!ldr) return -5;
     for (int i = 0; i < p->count; ++i) {
-        if (!A[i]) return -2;
+        const bool empty = p->L[i].n == 0;  // references no matrix
+        if (!A[i] && !empty) return -2;
         if (lda[i] < p->L[i].m) return -3;
-        if (!R[i]) return -4;
+        if (!R[i] && !empty) return -4;
         if (ldr[i] < p->L[i].n) return -5;
     }
     p->state = 0;
+    if (p->classes.empty()) {  // every problem is empty
+        p->state = p->want_q ? 1 : 2;
+        return 0;
+    }
     hipError_t e = stage_args(p, p->h_args_f, p->d_args_f, p->ev_f, p->next_f, A, lda, R, ldr);
     // The width classes run one after another in one graph.  Measured at 2048
     // problems (n in {8, 16, 32, 64}): the classes as parallel branches of the
@@ -373,17 +386,19 @@ tsqr_status tsqr_batched_form_q(tsqr_batched_plan p, double* const* A, const int
     if (!Q) return -4;
     if (!ldq) return -5;
     for (int i = 0; i < p->count; ++i) {
-        if (!A[i]) return -2;
+        const bool empty = p->L[i].n == 0;  // references no matrix
+        if (!A[i] && !empty) return -2;
         if (lda[i] < p->L[i].m) return -3;
-        if (!Q[i]) return -4;
+        if (!Q[i] && !empty) return -4;
         if (ldq[i] < p->L[i].m) return -5;
         if (Q[i] == A[i] && ldq[i] != lda[i]) return -5;
     }
     if (p->state != 1) return 4;
+    if (p->classes.empty()) return 0;  // every problem is empty
     // FP64: Q over A in any problem selects the graph with one wavefront per
     // leaf (MIXED plans read their reflectors from the workspace)
     bool alias = false;
-    for (int i = 0; i < p->count && p->prec != TSQR_MIXED; ++i) alias = alias || Q[i] == A[i];
+    for (int i = 0; i < p->count && p->prec != TSQR_MIXED; ++i) alias = alias || (Q[i] == A[i] && p->L[i].n > 0);
     hipGraphExec_t* g = alias ? &p->g_form_q_alias : &p->g_form_q;
     hipError_t e = stage_args(p, p->h_args_q, p->d_args_q, p->ev_q, p->next_q, A, lda, Q, ldq);
     if (e == hipSuccess && !*g) {
@@ -417,12 +432,12 @@ tsqr_status tsqr_batched_problem_info(tsqr_batched_plan p, int index, tsqr_info*
     out->num_leaves = L.P;
     out->num_tiles = L.ntiles;
     out->tree_levels = L.levels;
-    out->tree = L.P == 1 ? TSQR_TREE_FLAT : (L.f == 1 ? TSQR_TREE_BINARY : TSQR_TREE_HYBRID);
+    out->tree = L.P <= 1 ? TSQR_TREE_FLAT : (L.f == 1 ? TSQR_TREE_BINARY : TSQR_TREE_HYBRID);
     out->waves = L.waves;
     out->precision = p->prec;
     out->workspace_bytes = L.total * (int64_t)sizeof(double);
     out->leaf_kind = TSQR_LEAF_COMPACT_WY;
-    if (p->prec == TSQR_MIXED && p->want_q && p->state == 1) {
+    if (p->prec == TSQR_MIXED && p->want_q && p->state == 1 && L.n > 0) {
         // the second pass's check (synchronises the plan's stream)
         double info[2] = {0.0, 0.0};
         hipError_t e = hipStreamSynchronize(p->stream);

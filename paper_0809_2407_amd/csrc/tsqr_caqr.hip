@@ -59,14 +59,14 @@ tsqr_status tsqr_caqr_plan_create(tsqr_caqr_plan* out, int64_t m, int64_t n, int
 {
     if (!out) return -1;
     *out = nullptr;
-    if (m < 1 || m < n) return -2;
-    if (n < 1) return -3;
+    if (m < 0 || m < n) return -2;
+    if (n < 0) return -3;  // n = 0: a plan with no panels
     if (panel < 0 || panel > tsqr::kMaxN) return -4;
     tsqr_caqr_plan_s* p = new (std::nothrow) tsqr_caqr_plan_s();
     if (!p) return 2;
     p->m = m;
     p->n = n;
-    p->b = panel > 0 ? panel : std::min<int64_t>(32, n);
+    p->b = panel > 0 ? panel : std::max<int64_t>(1, std::min<int64_t>(32, n));
     p->stream = (hipStream_t)hip_stream;
     tsqr_opts o = {};
     o.want_q = 1;
@@ -94,6 +94,10 @@ tsqr_status caqr_factor(tsqr_caqr_plan p, double* A, int64_t lda, double* R, int
 {
     p->state = 0;
     const int64_t n = p->n, b = p->b;
+    if (n == 0) {  // no columns: nothing to factor, Q = I leaves the right-hand sides
+        p->state = 1;
+        return 0;
+    }
     // the strictly lower part of R is zero; the panels fill the rest
     hipLaunchKernelGGL(k_caqr_zero_lower, dim3((unsigned)std::min<int64_t>(1024, (n * n + 255) / 256)), dim3(256), 0,
                        p->stream, R, ldr, n);
@@ -127,9 +131,9 @@ extern "C" {
 tsqr_status tsqr_caqr_factor(tsqr_caqr_plan p, double* A, int64_t lda, double* R, int64_t ldr)
 {
     if (!p) return -1;
-    if (!A) return -2;
+    if (!A && p->n > 0) return -2;  // an empty problem references no matrix
     if (lda < p->m) return -3;
-    if (!R) return -4;
+    if (!R && p->n > 0) return -4;
     if (ldr < p->n) return -5;
     return caqr_factor(p, A, lda, R, ldr, 0);
 }
@@ -137,9 +141,9 @@ tsqr_status tsqr_caqr_factor(tsqr_caqr_plan p, double* A, int64_t lda, double* R
 tsqr_status tsqr_caqr_factor_rhs(tsqr_caqr_plan p, double* A, int64_t lda, double* R, int64_t ldr, int64_t k)
 {
     if (!p) return -1;
-    if (!A) return -2;
+    if (!A && p->n > 0) return -2;  // an empty problem references no matrix
     if (lda < p->m) return -3;
-    if (!R) return -4;
+    if (!R && p->n > 0) return -4;
     if (ldr < p->n) return -5;
     if (k < 0) return -6;
     return caqr_factor(p, A, lda, R, ldr, k);
@@ -148,11 +152,11 @@ tsqr_status tsqr_caqr_factor_rhs(tsqr_caqr_plan p, double* A, int64_t lda, doubl
 tsqr_status tsqr_caqr_apply_qt(tsqr_caqr_plan p, const double* A, int64_t lda, int64_t k, double* B, int64_t ldb)
 {
     if (!p) return -1;
-    if (!A) return -2;
+    if (!A && p->n > 0) return -2;
     if (lda < p->m) return -3;
     if (k < 0) return -4;
     if (k == 0) return 0;
-    if (!B) return -5;
+    if (!B && p->m > 0) return -5;  // a 0 x k B is not referenced
     if (ldb < p->m) return -6;
     if (p->state != 1) return 4;
     // Q^T = ... Q_1^T Q_0^T: panel j acts on rows jb .. of B
@@ -177,7 +181,8 @@ tsqr_status tsqr_caqr_plan_info(tsqr_caqr_plan p, int64_t* panel, int64_t* npane
 tsqr_status tsqr_caqr_plan_destroy(tsqr_caqr_plan p)
 {
     if (!p) return -1;
-    hipError_t e = hipStreamSynchronize(p->stream);
+    // a plan with no panels (n = 0) never enqueued work
+    hipError_t e = p->panels.empty() ? hipSuccess : hipStreamSynchronize(p->stream);
     release(p);
     return caqr_hip(e);
 }

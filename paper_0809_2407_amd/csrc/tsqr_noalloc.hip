@@ -49,13 +49,22 @@ tsqr_status hip_status(hipError_t e) { return e == hipSuccess ? 0 : (e == hipErr
 extern "C" tsqr_status tsqr_factor_r_noalloc(int64_t m, int64_t n, const double* A, int64_t lda, double* R,
                                              int64_t ldr, void* hip_stream, tsqr_info* info)
 {
-    if (m < 1 || m < n) return -1;
-    if (n < 1) return -2;
+    if (m < 0 || m < n) return -1;
+    if (n < 0) return -2;
     if (n > tsqr::kMaxN) return 3;
-    if (!A) return -3;
+    if (!A && n > 0) return -3;  // an empty problem references no matrix
     if (lda < m) return -4;
-    if (!R) return -5;
+    if (!R && n > 0) return -5;
     if (ldr < n) return -6;
+    if (n == 0) {  // the empty problem: nothing to compute
+        if (info) {
+            *info = tsqr_info{};
+            info->m = m;
+            info->tree = TSQR_TREE_FLAT;
+            info->precision = TSQR_FP64;
+        }
+        return 0;
+    }
     // geometry: as many short chains as the R-only plans use (16384 leaves),
     // fewer when their R factors would not fit the scratch array; chains are
     // capped at kMaxChain tiles, beyond which the size is rejected (status 6)

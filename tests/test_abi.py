@@ -42,8 +42,8 @@ def test_argument_errors_without_device():
     h = ctypes.c_void_p()
     assert lib.tsqr_plan_create(None, 100, 4, 0, None, None) == -1
     assert lib.tsqr_plan_create(ctypes.byref(h), 3, 4, 0, None, None) == -2  # m < n
-    assert lib.tsqr_plan_create(ctypes.byref(h), 0, 0, 0, None, None) == -2
-    assert lib.tsqr_plan_create(ctypes.byref(h), 100, 0, 0, None, None) == -3
+    assert lib.tsqr_plan_create(ctypes.byref(h), -1, 0, 0, None, None) == -2
+    assert lib.tsqr_plan_create(ctypes.byref(h), 100, -1, 0, None, None) == -3
     assert lib.tsqr_plan_create(ctypes.byref(h), 1000, 65, 0, None, None) == 3  # n > 64 unsupported
     assert lib.tsqr_plan_create(ctypes.byref(h), 1000, 8, 7, None, None) == -4
     bad = _lib.TsqrOpts(9, 0, 0, 0, 0, 1)
@@ -57,7 +57,7 @@ def test_argument_errors_without_device():
     assert lib.tsqr_plan_destroy(None) == -1
     out = _lib.TsqrInfo()
     assert lib.tsqr_plan_query(3, 4, 0, None, ctypes.byref(out)) == -1
-    assert lib.tsqr_plan_query(100, 0, 0, None, ctypes.byref(out)) == -2
+    assert lib.tsqr_plan_query(100, -1, 0, None, ctypes.byref(out)) == -2
     assert lib.tsqr_plan_query(100, 4, 5, None, ctypes.byref(out)) == -3
     assert lib.tsqr_plan_query(100, 4, 0, None, None) == -5
 
@@ -110,6 +110,51 @@ def test_levels_match_binary_pairing():
         assert q["tree_levels"] == L
 
 
+@pytest.mark.parametrize("prec,want_q", [(0, 1), (0, 0), (1, 1)])
+def test_empty_problem_plans_need_no_device(prec, want_q):
+    """n = 0 (any m >= 0): a plan with no workspace whose calls check their
+    leading dimensions, reference no matrix (NULL pointers pass), launch
+    nothing and return 0; call order is still enforced.  No device is touched,
+    so this runs without a GPU."""
+    from paper_0809_2407_amd import _lib
+    lib = _lib.load()
+    for m in (0, 10):
+        out = _lib.TsqrInfo()
+        assert lib.tsqr_plan_query(m, 0, prec, None, ctypes.byref(out)) == 0
+        assert (out.m, out.n, out.num_leaves, out.num_tiles, out.workspace_bytes) == (m, 0, 0, 0, 0)
+        h = ctypes.c_void_p()
+        opts = _lib.TsqrOpts(0, 0, 0, 0, 0, want_q, 0)
+        assert lib.tsqr_plan_create(ctypes.byref(h), m, 0, prec, ctypes.byref(opts), None) == 0
+        assert lib.tsqr_form_q(h, None, m, None, m) == 4  # nothing factored yet
+        assert lib.tsqr_factor(h, None, m - 1, None, 0) == -3  # lda < m
+        assert lib.tsqr_factor(h, None, m, None, 0) == 0
+        dummy = 8  # never dereferenced: Q^T B = B without reflectors
+        if want_q:
+            assert lib.tsqr_form_q(h, None, m, None, m) == 0
+            assert lib.tsqr_apply_qt(h, None, m, 3, dummy, m) == 0
+            assert lib.tsqr_apply_qt(h, None, m, 3, None, m) == (-5 if m > 0 else 0)  # 0 x 3: not referenced
+            assert lib.tsqr_apply_qt(h, None, m, -1, dummy, m) == -4
+            if m > 0:
+                assert lib.tsqr_apply_qt(h, None, m, 3, dummy, m - 1) == -6
+                assert lib.tsqr_form_q(h, None, m, None, m - 1) == -5
+        else:
+            assert lib.tsqr_form_q(h, None, m, None, m) == 4
+        if prec == 1:
+            assert lib.tsqr_mixed_q1(h, None, m) == 0
+        assert lib.tsqr_plan_info(h, ctypes.byref(out)) == 0
+        assert (out.m, out.n, out.workspace_bytes, out.reorth_applied) == (m, 0, 0, 0)
+        assert lib.tsqr_plan_destroy(h) == 0
+        # the allocation-free entry point and CAQR take the same convention
+        assert lib.tsqr_factor_r_noalloc(m, 0, None, m, None, 0, None, ctypes.byref(out)) == 0
+        assert (out.m, out.n) == (m, 0)
+        c = ctypes.c_void_p()
+        assert lib.tsqr_caqr_plan_create(ctypes.byref(c), m, 0, 0, None) == 0
+        assert lib.tsqr_caqr_factor(c, None, m, None, 0) == 0
+        assert lib.tsqr_caqr_factor_rhs(c, None, m, None, 0, 2) == 0
+        assert lib.tsqr_caqr_apply_qt(c, None, m, 2, dummy, m) == 0
+        assert lib.tsqr_caqr_plan_destroy(c) == 0
+
+
 def test_batched_argument_errors_without_device():
     from paper_0809_2407_amd import _lib
     lib = _lib.load()
@@ -122,6 +167,7 @@ def test_batched_argument_errors_without_device():
     assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, ms, None, 0, None, None) == -4
     assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, ms, ns, 7, None, None) == -5
     assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, I64(100, 10), ns, 0, None, None) == -3
+    assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, ms, I64(8, -1), 0, None, None) == -3
     assert lib.tsqr_batched_plan_create(ctypes.byref(P), 2, ms, I64(8, 65), 0, None, None) == 3
     assert lib.tsqr_batched_factor(None, None, None, None, None) == -1
     assert lib.tsqr_batched_plan_destroy(None) == -1
@@ -252,7 +298,7 @@ def test_caqr_plans_reject_arguments_without_device():
     h = ctypes.c_void_p()
     assert lib.tsqr_caqr_plan_create(None, 100, 4, 0, None) == -1
     assert lib.tsqr_caqr_plan_create(ctypes.byref(h), 3, 4, 0, None) == -2
-    assert lib.tsqr_caqr_plan_create(ctypes.byref(h), 100, 0, 0, None) == -3
+    assert lib.tsqr_caqr_plan_create(ctypes.byref(h), 100, -1, 0, None) == -3
     assert lib.tsqr_caqr_plan_create(ctypes.byref(h), 100, 4, 65, None) == -4
     assert lib.tsqr_caqr_factor(None, 1, 1, 1, 1) == -1
     assert lib.tsqr_caqr_factor_rhs(None, 1, 1, 1, 1, 0) == -1
