@@ -28,7 +28,6 @@ namespace tsqr {
     case 40: return CALL(40);                                                                         \
     case 44: return CALL(44);                                                                         \
     case 48: return CALL(48);                                                                         \
-    case 52: return CALL(52);                                                                         \
     case 56: return CALL(56);                                                                         \
     case 64: return CALL(64);                                                                         \
     default: return hipErrorInvalidValue;                                                             \
@@ -103,7 +102,7 @@ int leaf_lds_bytes(int np, bool mixed, bool want_q)
 #define CASE(NP) \
     case NP: return leaf_lds_bytes_np<NP>(mixed, want_q);
         CASE(4) CASE(8) CASE(12) CASE(16) CASE(20) CASE(24) CASE(28) CASE(32)
-        CASE(36) CASE(40) CASE(44) CASE(48) CASE(52) CASE(56) CASE(64)
+        CASE(36) CASE(40) CASE(44) CASE(48) CASE(56) CASE(64)
 #undef CASE
     default: return 0;
     }

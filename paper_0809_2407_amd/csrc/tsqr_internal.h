@@ -42,16 +42,18 @@ __host__ __device__ constexpr int tile_rows_for(int np)
 }
 
 // Padded column count of the kernels for n columns: n rounded up to a multiple
-// of 4, except that widths 57-60 run on the 64-column kernels.  At 60 columns
-// the factor layout gives each lane 15 columns, and the compiler leaves the
-// column loops of that instantiation rolled, which puts the whole tile in
-// scratch memory; four more zero columns (tau = 0 reflectors) cost less.
+// of 4, except that widths 49-52 run on the 56-column kernels and 57-60 on the
+// 64-column ones.  At 52 and 60 columns the factor layout gives each lane an
+// odd number of columns (13, 15), and the compiler leaves the column loops of
+// those instantiations rolled, which puts the whole tile in scratch memory
+// (432-528 bytes per lane with no spill reported); four more zero columns
+// (tau = 0 reflectors) cost far less.
 __host__ __device__ constexpr int padded_width(int64_t n)
 {
-    return (n > 56 && n <= 60) ? 64 : (int)((n + 3) / 4 * 4);
+    return (n > 56 && n <= 60) ? 64 : ((n > 48 && n <= 52) ? 56 : (int)((n + 3) / 4 * 4));
 }
 // Most zero columns padded_width adds at a padded count np.
-__host__ __device__ constexpr int max_padding(int np) { return np == 64 ? 7 : 3; }
+__host__ __device__ constexpr int max_padding(int np) { return (np == 64 || np == 56) ? 7 : 3; }
 
 // Rows per tile of the mixed-precision leaf kernel, whose tile is held in FP32:
 // twice the FP64 tile in the same registers, at most 1024.

@@ -67,14 +67,14 @@ def _query(**kw):
     return plan_query(**kw)
 
 
-@pytest.mark.parametrize("n", [1, 3, 4, 8, 16, 17, 20, 32, 33, 48, 56, 57, 60, 61, 64])
+@pytest.mark.parametrize("n", [1, 3, 4, 8, 16, 17, 20, 32, 33, 48, 49, 52, 53, 56, 57, 60, 61, 64])
 def test_tile_rows_respect_fast_memory_bound(n):
     """m/P * n + n(n+1)/2 <= W (Sec. 4.2) with W the per-wavefront register
     budget for the tile (64 doubles per lane, 4096 per wavefront)."""
     q = _query(m=1 << 20, n=n)
     np_ = q["n_padded"]
-    # n rounded up to a multiple of 4; widths 57-60 run on the 64-column kernels
-    assert np_ == (64 if 57 <= n <= 60 else (n + 3) // 4 * 4)
+    # n rounded up to a multiple of 4; widths 49-52 run on the 56-column kernels, 57-60 on the 64-column ones
+    assert np_ == (64 if 57 <= n <= 60 else (56 if 49 <= n <= 52 else (n + 3) // 4 * 4))
     assert q["tile_rows"] * np_ <= 64 * 64
     assert q["tile_rows"] >= np_
 

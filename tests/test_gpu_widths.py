@@ -1,5 +1,5 @@
 """Every padded column count of the kernels (widths rounded up to a multiple of
-4, widths 57-60 on the 64-column kernels), with widths that are not a multiple
+4, widths 49-52 on the 56-column kernels and 57-60 on the 64-column ones), with widths that are not a multiple
 of 4 so the zero columns past n are exercised in each: the FP64 path against
 the oracle run on the same tree, element by element, and the mixed path
 against the bounds of the method."""
@@ -13,7 +13,7 @@ from metrics import backward_error, fp64_bound, is_upper, orthogonality, rel_dif
 
 pytestmark = pytest.mark.gpu
 
-WIDTHS = [2, 7, 10, 13, 19, 22, 26, 31, 34, 38, 43, 46, 50, 53, 55, 57, 58, 60, 62, 63]
+WIDTHS = [2, 7, 10, 13, 19, 22, 26, 31, 34, 38, 43, 46, 49, 50, 52, 53, 55, 57, 58, 60, 62, 63]
 
 
 @pytest.mark.parametrize("n", WIDTHS)
@@ -24,7 +24,7 @@ def test_fp64_every_kernel_width(n):
     A = synth.gaussian(6000 + 3 * n, n, seed=1000 + n)
     announce(f"fp64 width {n}: {A.shape[0]}x{n} hybrid3")
     R, Q, _, info = run_tsqr(A, tree="hybrid", flat_len=3)
-    assert info["n_padded"] == (64 if 57 <= n <= 60 else (n + 3) // 4 * 4)
+    assert info["n_padded"] == (64 if 57 <= n <= 60 else (56 if 49 <= n <= 52 else (n + 3) // 4 * 4))
     assert info["num_leaves"] > 1
     assert is_upper(R) and np.all(np.diag(R) >= 0)
     t = oracle.TSQR(A, info["leaf_rows"], info["tile_rows"])
@@ -72,8 +72,8 @@ def test_mixed_every_kernel_width(n):
     assert rel_diff(R, oracle.qr_reference(A, want_q=False)) <= 1e-5
 
 
-@pytest.mark.parametrize("n", [57, 59, 60])
-def test_apply_qt_on_64_column_kernels(n):
+@pytest.mark.parametrize("n", [49, 51, 52, 57, 59, 60])
+def test_apply_qt_on_widened_kernels(n):
     """Q^T B for widths padded by 4-7 columns, every row against the oracle's
     replay of the same tree."""
     torch = need_gpu()
@@ -96,17 +96,19 @@ def test_apply_qt_on_64_column_kernels(n):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_batched_widths_57_to_60_equal_single_plans(precision):
-    """A batched plan whose 64-column class holds widths 57-60 and 64 gives
-    every problem the bits of its single-problem plan."""
+def test_batched_widened_widths_equal_single_plans(precision):
+    """A batched plan whose 56-column class holds widths 49-52 and 56 and whose
+    64-column class holds 57-60 and 64 gives every problem the bits of its
+    single-problem plan."""
     torch = need_gpu()
     from paper_0809_2407_amd import tsqr as T
 
-    shapes = [(9000, 57), (3000, 60), (12000, 64), (5000, 58), (2500, 59)]
+    shapes = [(9000, 57), (3000, 60), (12000, 64), (5000, 58), (2500, 59), (7000, 49), (4000, 52), (6000, 56),
+              (3500, 50)]
     mats = [synth.gaussian(m, n, seed=1500 + i) for i, (m, n) in enumerate(shapes)]
-    announce(f"batched {precision} widths 57-60")
+    announce(f"batched {precision} widths 49-52 and 57-60")
     with T.BatchedPlan([m for m, _ in shapes], [n for _, n in shapes], precision=precision) as bp:
-        assert all(bp.problem_info(i)["n_padded"] == 64 for i in range(len(shapes)))
+        assert all(bp.problem_info(i)["n_padded"] == (64 if n > 56 else 56) for i, (_, n) in enumerate(shapes))
         As = [T.to_colmajor(torch.from_numpy(A)) for A in mats]
         Rs = bp.factor(As)
         Qs = bp.form_q(As, [T.colmajor(m, n) for m, n in shapes])
