@@ -22,9 +22,12 @@ The default line also carries, unless --no-extras:
                          {8, 16, 32, 64}): one batched plan per call against the
                          loop of single calls on the same stream (FP64), and
                          the mixed batched plan on the same problems;
-  beyond_tsqr            CAQR, the out-of-HBM flat tree and the competitors of
-                         Sec. 5, three timed steps each (their full lines:
-                         --workload caqr_... / stream_... / competitors_...).
+  beyond_tsqr            CAQR, the out-of-HBM flat tree, the competitors of
+                         Sec. 5 and the paper-shaped sweep (10^5 x {50, 200,
+                         400}, 10^6 x 50, 6.4e6 x 50, m n = 2^24 at n = 4 ..
+                         64), three timed steps each (their full lines:
+                         --workload caqr_... / stream_... / competitors_... /
+                         paper_shapes_fp64).
 Unless --no-peaks, every single-problem line also carries the part's measured
 ceilings (measured_peaks: streaming copy and read, FP64 FMA and MFMA loops, and
 a copy in the Q kernel's access pattern at the workload's geometry) and the
@@ -94,7 +97,15 @@ NEXT_ROWS = {
     "caqr_fp64_rqtb_m131072_n256_b32_k32": dict(m=1 << 17, n=256, panel=32, rhs=32, decades=6.0),
     "stream_fp64_r_m16777216_n32_kappa1e12": dict(m=1 << 24, n=32, decades=12.0),
     "competitors_fp64_rq_m16777216_n32": dict(m=1 << 24, n=32, decades=(3.0, 12.0)),
+    "paper_shapes_fp64": dict(),
 }
+
+# The shapes of the paper's experiments (context, not a target): the matrices
+# of its local-QR tables (10^5 x {50, 200, 400}, 10^6 x 50, 6.4e6 x 50) and
+# its out-of-DRAM sweep at m n = 2^24, n = 4 .. 64.  Widths above 64 go
+# through CAQR with TSQR panels (R only).
+PAPER_SHAPES = [(100_000, 50), (100_000, 200), (100_000, 400), (1_000_000, 50), (6_400_000, 50),
+                (1 << 22, 4), (1 << 21, 8), (1 << 20, 16), (1 << 19, 32), (1 << 18, 64)]
 
 
 def log(msg: str) -> None:
@@ -889,6 +900,77 @@ def caqr_line(args, name: str) -> dict:
     return res
 
 
+def paper_shapes_line(args, name: str) -> dict:
+    """The paper-shaped sweep: iid N(0,1) entries (the paper states no
+    distribution), per shape R only and R + explicit Q (TSQR, n <= 64) or R
+    (CAQR, panels of 32, wider), each against its path roofline (bytes 8mn for
+    R, 32mn for R + Q; CAQR as in its own line), with the backward error and
+    orthogonality of R + Q and ||R^T R - A^T A|| / ||A||^2 of the CAQR R."""
+    import torch
+    from paper_0809_2407_amd import tsqr as T
+
+    recs = []
+    for m, n in PAPER_SHAPES:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(args.seed + m + n)
+        A = torch.randn((n, m), generator=g, device="cuda", dtype=torch.float64).t()
+        log(f"paper shapes: {m} x {n}")
+        if n > 64:
+            b = 32
+            plan = T.CaqrPlan(m, n, b)
+            W, R = T.colmajor(m, n), T.colmajor(n, n)
+            t = events_time(lambda: plan.factor(W, R), args.steps, args.warmup, lambda: W.copy_(A))
+            plan.close()
+            fl = flops_r(m, n)
+            by = 0.0
+            for j in range(-(-n // b)):
+                mj, bj = m - j * b, min(b, n - j * b)
+                cj = n - j * b - bj
+                by += 16.0 * mj * bj + -(-cj // 32) * 8.0 * mj * bj + 16.0 * mj * cj
+            with torch.no_grad():
+                gram = float(torch.linalg.norm(R.t().matmul(R) - A.t().matmul(A)) / torch.linalg.norm(A) ** 2)
+            roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), by / (HBM_PEAK_GBS * 1e9)) * 1e3
+            recs.append({"m": m, "n": n, "method": "caqr", "mode": "r", "ms_median": t["median"], "ms_min": t["min"],
+                         "gflops": fl / (t["median"] * 1e-3) / 1e9, "bytes": by,
+                         "path_roofline_frac": roof / t["median"], "gram_error": gram})
+            del W, R, A
+            continue
+        with T.Plan(m, n, want_q=False) as p:
+            R = T.colmajor(n, n)
+            t = events_time(lambda: p.factor(A, R), args.steps, args.warmup)
+        fl, by = flops_r(m, n), 8.0 * m * n
+        roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), by / (HBM_PEAK_GBS * 1e9)) * 1e3
+        recs.append({"m": m, "n": n, "method": "tsqr", "mode": "r", "ms_median": t["median"], "ms_min": t["min"],
+                     "gflops": fl / (t["median"] * 1e-3) / 1e9, "bytes": by, "path_roofline_frac": roof / t["median"]})
+        with T.Plan(m, n) as p:
+            V, R, Q = T.colmajor(m, n), T.colmajor(n, n), T.colmajor(m, n)
+
+            def rq():
+                p.factor_into(A, V, R)
+                p.form_q(V, Q)
+
+            t = events_time(rq, args.steps, args.warmup)
+            info = p.info()
+        with torch.no_grad():
+            bwd = float(torch.linalg.norm(A - Q.matmul(R)) / torch.linalg.norm(A))
+            orth = float(torch.linalg.norm(Q.t().matmul(Q) - torch.eye(n, dtype=torch.float64, device="cuda")))
+        fl, by = flops_rq(m, n), 32.0 * m * n
+        roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), by / (HBM_PEAK_GBS * 1e9)) * 1e3
+        recs.append({"m": m, "n": n, "method": "tsqr", "mode": "rq", "ms_median": t["median"], "ms_min": t["min"],
+                     "gflops": fl / (t["median"] * 1e-3) / 1e9, "bytes": by, "path_roofline_frac": roof / t["median"],
+                     "backward_error": bwd, "orthogonality": orth, "leaf_rows": info["leaf_rows"],
+                     "tile_rows": info["tile_rows"], "num_leaves": info["num_leaves"]})
+        del V, R, Q, A
+    torch.cuda.empty_cache()
+    for r in recs:
+        log(f"  {r['method']} {r['mode']} {r['m']} x {r['n']}: {r['ms_median']:.3f} ms, {r['gflops']:.0f} GFLOP/s, "
+            f"{100 * r['path_roofline_frac']:.1f}% of its path roofline")
+    return {"metric": "paper-shaped TSQR / CAQR GFLOP/s & % path roofline (context)", "workload": name,
+            "steps": args.steps, "warmup": args.warmup, "dtype": "f64",
+            "data": f"synthetic: iid N(0,1), torch generator on the device, seed {args.seed} + m + n",
+            "records": recs}
+
+
 def stream_line(args, name: str) -> dict:
     """The out-of-HBM flat tree (Sec. 7.1): A in pinned host memory, streamed
     to the GPU in row blocks while the previous block is factored.  Bound by
@@ -1074,7 +1156,8 @@ def main(argv=None) -> int:
     if args.workload in BATCHED:
         return run_batched(args)
     if args.workload in NEXT_ROWS:
-        fn = {"caqr": caqr_line, "stream": stream_line, "competitors": competitors_line}[args.workload.split("_")[0]]
+        fn = {"caqr": caqr_line, "stream": stream_line, "competitors": competitors_line,
+              "paper": paper_shapes_line}[args.workload.split("_")[0]]
         print(json.dumps(fn(args, args.workload)), flush=True)
         return 0
     result = run_single(args, args.workload, cpu=not args.no_cpu_baseline, check=not args.no_check)
@@ -1103,7 +1186,8 @@ def main(argv=None) -> int:
         result["beyond_tsqr"] = {name.split("_")[0]: fn(short, name) for name, fn in (
             ("caqr_fp64_rqtb_m131072_n256_b32_k32", caqr_line),
             ("stream_fp64_r_m16777216_n32_kappa1e12", stream_line),
-            ("competitors_fp64_rq_m16777216_n32", competitors_line))}
+            ("competitors_fp64_rq_m16777216_n32", competitors_line),
+            ("paper_shapes_fp64", paper_shapes_line))}
     print(json.dumps(result), flush=True)
     return 0
 

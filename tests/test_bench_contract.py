@@ -49,6 +49,12 @@ def test_workloads_are_well_formed():
     assert bench.DEFAULT in bench.WORKLOADS
     for name, w in bench.BATCHED.items():
         assert w["count"] >= 1 and w["m_lo"] <= w["m_hi"], name
+    # the paper-shaped sweep: TSQR plans exist for every width up to 64 (wider ones go through CAQR)
+    from paper_0809_2407_amd import tsqr as T
+    for m, n in bench.PAPER_SHAPES:
+        assert m >= n >= 1, (m, n)
+        if n <= 64:
+            assert T.plan_query(m, n)["num_leaves"] >= 1
 
 
 def test_profiles_match_the_kernel_sources():
