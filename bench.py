@@ -951,9 +951,8 @@ def paper_shapes_line(args, name: str) -> dict:
 
             t = events_time(rq, args.steps, args.warmup)
             info = p.info()
-        with torch.no_grad():
-            bwd = float(torch.linalg.norm(A - Q.matmul(R)) / torch.linalg.norm(A))
-            orth = float(torch.linalg.norm(Q.t().matmul(Q) - torch.eye(n, dtype=torch.float64, device="cuda")))
+        acc = accuracy_of(A, Q, R)  # Q^T Q summed over row blocks
+        bwd, orth = acc["backward_error"], acc["orthogonality"]
         fl, by = flops_rq(m, n), 32.0 * m * n
         roof = max(fl / (FP64_PEAK_TFLOPS * 1e12), by / (HBM_PEAK_GBS * 1e9)) * 1e3
         recs.append({"m": m, "n": n, "method": "tsqr", "mode": "rq", "ms_median": t["median"], "ms_min": t["min"],

@@ -127,3 +127,29 @@ def test_batched_widened_widths_equal_single_plans(precision):
         bound = fp64_bound(n) if precision == "fp64" else 1e-6
         assert backward_error(A, Q, R) <= bound
         assert orthogonality(Q) <= (fp64_bound(n) if precision == "fp64" else 1e-13)
+
+
+@pytest.mark.parametrize("m,n", [(100_000, 50), (1_000_000, 50)])
+def test_paper_local_qr_shapes_against_the_oracle(m, n):
+    """The n = 50 shapes of the paper's local-QR tables, in the geometry a plan
+    picks by itself: R and Q element by element against the oracle on the same
+    tree, orthogonality measured on the host (FP64 sums by row blocks) within
+    the FP64 bound."""
+    torch = need_gpu()
+    from paper_0809_2407_amd import tsqr as T
+
+    A = synth.gaussian(m, n, seed=1700 + n)
+    announce(f"paper shape {m}x{n}")
+    R, Q, _, info = run_tsqr(A)
+    assert info["n_padded"] == 56
+    t = oracle.TSQR(A, info["leaf_rows"], info["tile_rows"])
+    Ro, Qo = t.R(), t.form_q()
+    assert np.abs(R - Ro).max() <= 1e-13 * np.linalg.norm(Ro)
+    assert np.abs(Q - Qo).max() <= 1e-13
+    G = np.zeros((n, n))
+    for i in range(0, m, 4096):
+        G += Q[i:i + 4096].T @ Q[i:i + 4096]
+    orth = float(np.linalg.norm(G - np.eye(n)))
+    print(f"[gpu-case] {m}x{n}: orthogonality {orth:.2e} (host, by row blocks), "
+          f"max|Q - Q_oracle| {np.abs(Q - Qo).max():.2e}", flush=True)
+    assert orth <= fp64_bound(n)
