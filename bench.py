@@ -283,10 +283,21 @@ def accuracy_of(A, Q, R) -> dict:
 
     m, n = A.shape
     with torch.no_grad():
-        nA = torch.linalg.norm(A)
-        E = torch.addmm(A, Q, R, alpha=-1.0)
-        bwd = float(torch.linalg.norm(E) / nA)
-        del E
+        if m * n < 1 << 31:
+            nA = torch.linalg.norm(A)
+            E = torch.addmm(A, Q, R, alpha=-1.0)
+            bwd = float(torch.linalg.norm(E) / nA)
+            del E
+        else:
+            # a device GEMM on column-major views spanning more than 2^31
+            # elements returned wrong products: compact row chunks instead
+            e2 = a2 = 0.0
+            for r in range(0, m, 1 << 22):
+                Ac = A[r:r + (1 << 22)].contiguous()
+                e2 += float(torch.linalg.norm(torch.addmm(Ac, Q[r:r + (1 << 22)].contiguous(), R.contiguous(),
+                                                          alpha=-1.0))) ** 2
+                a2 += float(torch.linalg.norm(Ac)) ** 2
+            bwd = (e2 / a2) ** 0.5
         # Q^T Q as a sum over row blocks: one GEMM with k = m accumulates
         # an error near sqrt(m) eps, above the orthogonality being measured
         nb = 4096

@@ -174,3 +174,74 @@ def test_qtb_at_the_krylov_shape():
             top = float((B[:n] - Q.t().matmul(B0)).abs().max() / torch.linalg.norm(B0))
     assert keep <= 1e-13, keep
     assert top <= 1e-15, top
+
+
+def test_more_elements_than_a_32_bit_index_reaches():
+    """m = 2^27 + 4321, n = 20: 2.7e9 elements (21.5 GB per matrix), so element
+    offsets pass 2^31 and byte offsets 2^34, in the geometry a plan picks by
+    itself and with a ragged last tile.  R and Q element by element against the
+    oracle on the same tree; backward error and orthogonality on the device."""
+    torch = need_gpu()
+    from paper_0809_2407_amd import tsqr as T
+
+    m, n = (1 << 27) + 4321, 20
+    announce(f"beyond 32-bit element offsets: {m} x {n}")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(SEED + 7)
+    A = torch.randn((n, m), generator=g, device="cuda", dtype=torch.float64).t()
+    with T.Plan(m, n) as p:
+        V, R, Q = T.colmajor(m, n), T.colmajor(n, n), T.colmajor(m, n)
+        p.factor_into(A, V, R)
+        p.form_q(V, Q)
+        torch.cuda.synchronize()
+        info = p.info()
+    del V
+    torch.cuda.empty_cache()
+    assert (m - 1) * n >= 1 << 31 and m % info["tile_rows"] != 0
+    with torch.no_grad():
+        # by row chunks, each copied to compact storage first: a device GEMM on
+        # the column-major views themselves (leading dimension m, so the operand
+        # spans (n - 1) m + rows > 2^31 elements) returned wrong products here,
+        # for a Q and R that match the oracle's
+        e2, a2, bad = 0.0, 0.0, []
+        for r in range(0, m, 1 << 22):
+            Ac = A[r:r + (1 << 22)].contiguous()
+            Ec = torch.addmm(Ac, Q[r:r + (1 << 22)].contiguous(), R.contiguous(), alpha=-1.0)
+            ec, ac = float(torch.linalg.norm(Ec)) ** 2, float(torch.linalg.norm(Ac)) ** 2
+            e2, a2 = e2 + ec, a2 + ac
+            if ec > 1e-24 * ac:
+                bad.append(r)
+            del Ec, Ac
+        bwd = (e2 / a2) ** 0.5
+        if bad:
+            announce(f"row chunks of 2^22 with a large residual start at rows {bad[:8]} ({len(bad)} chunks)")
+        G = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        for r in range(0, m, 1 << 22):
+            blk = Q[r:r + (1 << 22)]
+            nb = blk.shape[0] // 4096 * 4096
+            if nb:
+                Qb = blk[:nb].t().reshape(n, nb // 4096, 4096).permute(1, 0, 2).contiguous()
+                G += torch.bmm(Qb, Qb.transpose(1, 2).contiguous()).sum(dim=0)
+                del Qb
+            if nb < blk.shape[0]:
+                G += blk[nb:].t().matmul(blk[nb:])
+        orth = float(torch.linalg.norm(G - torch.eye(n, dtype=torch.float64, device="cuda")))
+    announce(f"device: backward {bwd:.2e}, orthogonality {orth:.2e}; oracle on {info['num_leaves']} leaves")
+    Ah = np.asfortranarray(A.cpu().numpy())
+    del A
+    Rh = R.cpu().numpy()
+    Qh = Q.cpu().numpy()
+    del Q
+    torch.cuda.empty_cache()
+    t = oracle.TSQR(Ah, info["leaf_rows"], info["tile_rows"])
+    del Ah
+    Ro = t.R()
+    Qo = t.form_q()
+    del t
+    dr = np.abs(Rh - Ro).max() / np.linalg.norm(Ro)
+    dq = np.abs(Qh - Qo).max(axis=1)
+    rows = np.nonzero(dq > 1e-13)[0]
+    announce(f"oracle: |R - R_oracle| / |R| {dr:.2e}, max |Q - Q_oracle| {dq.max():.2e}, "
+             f"{rows.size} rows of Q off" + (f" (first {rows[:4]}, last {rows[-1]})" if rows.size else ""))
+    assert dr <= 1e-13 and rows.size == 0
+    assert bwd <= fp64_bound(n) and orth <= fp64_bound(n), (bwd, orth)
