@@ -261,7 +261,10 @@ typedef struct {
 } tsqr_tune_result;
 
 /* Tune the class of (m, n, prec, want_q).  scratch (m x n, ld >= m, device) is
- * only read; NULL makes the tuner allocate and fill its own.  Each candidate
+ * only read; NULL makes the tuner allocate and fill its own.  With Q, an FP64
+ * candidate is timed writing its reflectors to a buffer of their own and Q to
+ * another (not Q over the reflectors in place, which above 48 columns runs a
+ * slower kernel), so the tuner allocates up to three m x n matrices.  Each candidate
  * runs reps + 1 times (the first untimed) on hip_stream; the call
  * synchronises.  With cache_path, a cached class is returned at once and a
  * tuned one is stored.  Errors: -1 m, -2 n, -3 prec, -4 want_q, -6 ld < m,

@@ -244,10 +244,14 @@ tsqr_status tsqr_autotune(int64_t m, int64_t n, tsqr_precision prec, int want_q,
         if (e != hipSuccess) return e == hipErrorOutOfMemory ? 2 : 1;
         A = own;
     }
-    double *Q = nullptr, *R = nullptr;
+    // FP64 with Q: the reflectors go to V and Q is formed into its own buffer,
+    // the form most callers run (Q over the reflectors in place gives each
+    // leaf one wavefront above 48 columns, a slower kernel)
+    double *Q = nullptr, *V = nullptr, *R = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t he = hipMalloc((void**)&R, (size_t)n * n * sizeof(double));
     if (he == hipSuccess && want_q) he = hipMalloc((void**)&Q, (size_t)m * n * sizeof(double));
+    if (he == hipSuccess && want_q && prec == TSQR_FP64) he = hipMalloc((void**)&V, (size_t)m * n * sizeof(double));
     if (he == hipSuccess) he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
 
@@ -309,8 +313,8 @@ tsqr_status tsqr_autotune(int64_t m, int64_t n, tsqr_precision prec, int want_q,
         double t_best = -1.0;
         for (int r = 0; r <= reps && st == 0; ++r) {  // r = 0 warms up
             he = hipEventRecord(e0, s);
-            if (he == hipSuccess) st = tsqr_factor_into(p, A, ld, want_q ? Q : nullptr, m, R, n);
-            if (he == hipSuccess && st == 0 && want_q && prec == TSQR_FP64) st = tsqr_form_q(p, Q, m, Q, m);
+            if (he == hipSuccess) st = tsqr_factor_into(p, A, ld, V, m, R, n);
+            if (he == hipSuccess && st == 0 && want_q && prec == TSQR_FP64) st = tsqr_form_q(p, V, m, Q, m);
             if (he == hipSuccess && st == 0 && want_q && prec == TSQR_MIXED) st = tsqr_form_q(p, nullptr, m, Q, m);
             if (he == hipSuccess && st == 0) he = hipEventRecord(e1, s);
             if (he == hipSuccess && st == 0) he = hipEventSynchronize(e1);
@@ -329,6 +333,7 @@ tsqr_status tsqr_autotune(int64_t m, int64_t n, tsqr_precision prec, int want_q,
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     if (Q) hipFree(Q);
+    if (V) hipFree(V);
     if (R) hipFree(R);
     if (own) hipFree(own);
     if (he != hipSuccess) return he == hipErrorOutOfMemory ? 2 : 1;
