@@ -57,21 +57,56 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
         // Narrow widths (np <= 24) keep about 4096 leaves.  Mixed precision caps
         // the chain at kMaxChainF32 tiles (accuracy guard: FP32 rounding grows
         // along a chain).  For a problem on its own, the quarter-of-the-data
-        // guard never leaves fewer than 512 leaves: on small problems (m below
+        // guard is capped at chains of tiles/1024 tiles, rounded down to a power
+        // of two (at least 2 from 48
+        // columns once there are 1024 tiles): on small problems (m below
         // about 2^21 at n = 64) the parallelism of more, shorter chains
-        // outweighs the larger per-leaf factors (measured at m = 131072,
-        // n = 64: R 0.80 against 1.30 ms, R + Q 1.12 against 1.69 ms, R with
-        // Q^T B on 192 columns 1.49 against 1.98 ms).  In a batch the other
-        // problems supply the parallelism and the guard stays (2048 problems of
-        // m in [1000, 200000]: 107 ms with it, 147 ms without).
+        // outweighs the larger per-leaf factors.  Measured over m = 2^16 ..
+        // 2^21 and n = 16, 32, 50, 64 against chains of 1 .. 32 tiles: the
+        // best chain is within a factor 2 of that cap (at m = 524288, n = 64:
+        // R + Q 1.69 ms against 2.02 ms with the earlier cap of tiles/512,
+        // R only 0.87 against 1.18 ms; at 2^21 rows the quarter guard binds
+        // and nothing changes).  In a batch the other problems supply the
+        // parallelism and the guard stays (2048 problems of m in [1000,
+        // 200000]: 107 ms with it, 147 ms without).
         const bool two_per_simd = leaf_lds_bytes(L.np, mixed, want_q) <= 20480;
         const int64_t target = !want_q ? 16384 : (!two_per_simd ? 1024 : (L.np > 24 ? 2048 : 4096));
         f = tiles_total / target;
         int64_t f_mem = (16 * (int64_t)L.np * L.np + L.mt * n - 1) / (L.mt * n);
-        if (!in_batch) f_mem = std::min<int64_t>(f_mem, std::max<int64_t>(1, tiles_total / 512));
+        if (!in_batch) {
+            // a power of two: a chain of 15 tiles at m = 10^6, n = 50 gave 1041
+            // leaves, whose Q pass (two wavefronts per leaf) overran one
+            // resident round by 34 wavefronts (2.96 ms against 2.05 ms)
+            int64_t cap = 1;
+            while (cap * 2 <= tiles_total / 1024) cap *= 2;
+            if (L.np >= 48 && tiles_total >= 1024) cap = std::max<int64_t>(cap, 2);
+            f_mem = std::min<int64_t>(f_mem, cap);
+        }
         f = std::max<int64_t>(std::max<int64_t>(1, f_mem), std::min<int64_t>(256, f));
+        const int64_t fmax = std::min<int64_t>(mixed ? kMaxChainF32 : 256, std::max<int64_t>(1, tiles_total));
         if (mixed) f = std::min<int64_t>(f, kMaxChainF32);
         f = std::min<int64_t>(f, std::max<int64_t>(1, tiles_total));
+        if (want_q && !in_batch) {
+            // the leaf kernel holds `target` leaves at once and the last leaf
+            // takes the remainder, so a chain just under the right length
+            // costs a second round, or a last leaf of almost two chains: at
+            // m = 6.4e6, n = 50 chains of 48 / 49 / 50 tiles (2083 / 2040 /
+            // 2000 leaves, the last of 64 / 129 / 50 tiles) took 10.4 / 9.2 /
+            // 6.9 ms, at m = 3e6, n = 64 chains of 22 / 23 (2130 / 2038
+            // leaves) 6.7 / 4.5 ms.  Among chains from f up to twice f take
+            // the one with the least f * rounds + (last leaf's excess tiles).
+            auto cost = [&](int64_t g) {
+                const int64_t lr = g * L.mt, P = std::max<int64_t>(1, m / lr);
+                const int64_t last = (m - (P - 1) * lr + L.mt - 1) / L.mt;
+                return g * ((P + target - 1) / target) + std::max<int64_t>(0, last - g);
+            };
+            int64_t best = f, bc = cost(f);
+            for (int64_t g = f + 1; g <= std::min<int64_t>(2 * f, fmax); ++g) {
+                const int64_t c = cost(g);
+                if (c < bc) best = g, bc = c;
+            }
+            f = best;
+        }
     }
     if (f < 1) f = 1;
     L.f = f;
