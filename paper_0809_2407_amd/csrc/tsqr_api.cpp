@@ -86,19 +86,21 @@ bool make_layout(Layout& L, int64_t m, int64_t n, int64_t leaf_rows_req, int fla
         const int64_t fmax = std::min<int64_t>(mixed ? kMaxChainF32 : 256, std::max<int64_t>(1, tiles_total));
         if (mixed) f = std::min<int64_t>(f, kMaxChainF32);
         f = std::min<int64_t>(f, std::max<int64_t>(1, tiles_total));
-        if (want_q && !in_batch) {
-            // the leaf kernel holds `target` leaves at once and the last leaf
-            // takes the remainder, so a chain just under the right length
+        if (!in_batch) {
+            // the leaf kernel holds `per_round` leaves at once (R only: two
+            // wavefronts per SIMD, whatever the 16384-leaf target) and the last
+            // leaf takes the remainder, so a chain just under the right length
             // costs a second round, or a last leaf of almost two chains: at
             // m = 6.4e6, n = 50 chains of 48 / 49 / 50 tiles (2083 / 2040 /
             // 2000 leaves, the last of 64 / 129 / 50 tiles) took 10.4 / 9.2 /
             // 6.9 ms, at m = 3e6, n = 64 chains of 22 / 23 (2130 / 2038
             // leaves) 6.7 / 4.5 ms.  Among chains from f up to twice f take
             // the one with the least f * rounds + (last leaf's excess tiles).
+            const int64_t per_round = want_q ? target : (two_per_simd ? 2048 : 1024);
             auto cost = [&](int64_t g) {
                 const int64_t lr = g * L.mt, P = std::max<int64_t>(1, m / lr);
                 const int64_t last = (m - (P - 1) * lr + L.mt - 1) / L.mt;
-                return g * ((P + target - 1) / target) + std::max<int64_t>(0, last - g);
+                return g * ((P + per_round - 1) / per_round) + std::max<int64_t>(0, last - g);
             };
             int64_t best = f, bc = cost(f);
             for (int64_t g = f + 1; g <= std::min<int64_t>(2 * f, fmax); ++g) {
